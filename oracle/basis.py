@@ -1,0 +1,64 @@
+"""Edge basis: polynomial cutoff envelope, Bessel radial basis, real spherical
+harmonics (float64, torch so that autograd can differentiate them).
+
+The paper embeds interatomic distances in a basis of 8 Bessel functions times a
+polynomial cutoff envelope (section "Training details"), and the geometry of
+each neighbour through spherical harmonics of the unit edge vector (section
+"Allegro: Scalable Equivariant Deep Learning", the Y^{ik} of Eq. tp), with full
+O(3) symmetry.  The exact forms are deferred there to the original Allegro
+paper; the readings used are:
+
+* envelope, p = 6:  u(t) = 1 - (p+1)(p+2)/2 t^p + p(p+2) t^(p+1) - p(p+1)/2 t^(p+2),
+  t = d / r_c  (so u(0) = 1 and u, u', u'' vanish at t = 1);
+* Bessel:  B_n(d) = sqrt(2 / r_c) sin(n pi d / r_c) / d, n = 1..n_bessel, with
+  fixed frequencies;
+* real spherical harmonics with "component" normalisation
+  (sum_m Y_lm(r)^2 = 2l + 1 on the unit sphere), m ordered -l..l:
+    Y_0 = 1
+    Y_1 = sqrt(3) (y, z, x)
+    Y_2 = (sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2 - 1), sqrt15 xz, sqrt15/2 (x^2 - y^2)).
+  The parity of Y_l is (-1)^l.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+
+def envelope(t: torch.Tensor, p: int = 6) -> torch.Tensor:
+    """Polynomial cutoff u(t) for t = d / r_c in [0, 1)."""
+    return (1.0 - (p + 1) * (p + 2) / 2.0 * t ** p + p * (p + 2) * t ** (p + 1)
+            - p * (p + 1) / 2.0 * t ** (p + 2))
+
+
+def bessel(d: torch.Tensor, r_cut: float, n_bessel: int) -> torch.Tensor:
+    """[E, n_bessel] Bessel basis B_n(d)."""
+    n = torch.arange(1, n_bessel + 1, dtype=d.dtype)
+    return math.sqrt(2.0 / r_cut) * torch.sin(n[None, :] * math.pi * d[:, None] / r_cut) / d[:, None]
+
+
+def spherical_harmonics(rhat: torch.Tensor, l_max: int) -> torch.Tensor:
+    """[E, (l_max+1)^2] real spherical harmonics of unit vectors."""
+    if l_max > 2:
+        raise NotImplementedError("l_max <= 2")
+    x, y, z = rhat[:, 0], rhat[:, 1], rhat[:, 2]
+    cols = [torch.ones_like(x)]
+    if l_max >= 1:
+        s3 = math.sqrt(3.0)
+        cols += [s3 * y, s3 * z, s3 * x]
+    if l_max >= 2:
+        s15, s5 = math.sqrt(15.0), math.sqrt(5.0)
+        cols += [s15 * x * y, s15 * y * z, s5 / 2.0 * (3.0 * z * z - 1.0), s15 * x * z,
+                 s15 / 2.0 * (x * x - y * y)]
+    return torch.stack(cols, dim=1)
+
+
+def spherical_harmonics_np(rhat: np.ndarray, l_max: int) -> np.ndarray:
+    return spherical_harmonics(torch.as_tensor(rhat, dtype=torch.float64), l_max).numpy()
+
+
+def irrep_of_component(l_max: int):
+    """l of each component index c = l^2 + (m + l)."""
+    return [l for l in range(l_max + 1) for _ in range(2 * l + 1)]

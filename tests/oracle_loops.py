@@ -1,0 +1,111 @@
+"""Loop-form re-evaluation of the Allegro energy for tiny inputs (test helper).
+
+Written independently of the vectorised oracle, in the other form that the
+paper's equations allow: per ordered pair, per neighbour k, per path, with the
+unfused coupling tensors and the tensor product taken *inside* the neighbour
+sum (the left-hand side of Eq. tp), in plain Python floats.  Agreement with the
+oracle pins its indexing (strided components, segment grouping, path fusion,
+factorisation of the neighbour sum).
+"""
+import math
+
+import numpy as np
+
+from oracle import cg
+from oracle.neighbors import neighbor_list
+
+
+def _silu(v):
+    return [a / (1.0 + math.exp(-a)) for a in v]
+
+
+def _matvec(x, W):
+    W = np.asarray(W, dtype=np.float64)
+    return [sum(x[k] * W[k, c] for k in range(len(x))) for c in range(W.shape[1])]
+
+
+def _mlp(x, Ws):
+    for k, W in enumerate(Ws):
+        x = _matvec(x, W)
+        if k < len(Ws) - 1:
+            x = _silu(x)
+    return x
+
+
+def _sh(v):
+    x, y, z = v
+    s3, s15, s5 = math.sqrt(3), math.sqrt(15), math.sqrt(5)
+    return [1.0, s3 * y, s3 * z, s3 * x, s15 * x * y, s15 * y * z, s5 / 2 * (3 * z * z - 1),
+            s15 * x * z, s15 / 2 * (x * x - y * y)]
+
+
+def energy(mc, w, sysm):
+    pos, Z = np.asarray(sysm.pos), np.asarray(sysm.species)
+    L = np.where(np.asarray(sysm.pbc) != 0, np.asarray(sysm.cell, dtype=float), 0.0)
+    I, J, S = neighbor_list(pos, sysm.cell, sysm.pbc, mc.r_cut, n_local=sysm.n_local)
+    n, lm, nS = mc.n_tensor, mc.l_max, mc.n_species
+    dim = (lm + 1) ** 2
+    lof = [l for l in range(lm + 1) for _ in range(2 * l + 1)]
+    paths = cg.layer_paths(lm, mc.n_layers)
+    edges = []
+    for (i, j, s) in zip(I.tolist(), J.tolist(), S.tolist()):
+        r = [(pos[j, a] - pos[i, a]) + s[a] * L[a] for a in range(3)]
+        d = math.sqrt(sum(c * c for c in r))
+        t, p = d / mc.r_cut, mc.envelope_p
+        u = 1 - (p + 1) * (p + 2) / 2 * t ** p + p * (p + 2) * t ** (p + 1) - p * (p + 1) / 2 * t ** (p + 2)
+        Rb = [math.sqrt(2 / mc.r_cut) * math.sin(k * math.pi * d / mc.r_cut) / d * u
+              for k in range(1, mc.n_bessel + 1)]
+        Y = _sh([c / d for c in r])[:dim]
+        inp = [0.0] * (2 * nS)
+        inp[Z[i]] = 1.0
+        inp[nS + Z[j]] = 1.0
+        x = [u * v for v in _mlp(inp + Rb, [w[f"twobody.W{k}"] for k in range(len(mc.twobody_dims))])]
+        a0 = _matvec(x, w["embed0"])
+        V = [[a0[lof[c] * n + q] * Y[c] for q in range(n)] for c in range(dim)]
+        edges.append(dict(i=i, u=u, Y=Y, x=x, V=V))
+    cn = 1.0 / math.sqrt(mc.avg_num_neighbors)
+    for Lr in range(1, mc.n_layers + 1):
+        final = Lr == mc.n_layers
+        al = np.asarray(w[f"layer{Lr}.alpha"], dtype=np.float64)
+        M = np.asarray(w[f"layer{Lr}.mix"], dtype=np.float64)
+        kept = paths[Lr - 1]
+        cnt = {}
+        for (_, _, lo) in kept:
+            cnt[lo] = cnt.get(lo, 0) + 1
+        wk = [_matvec(e["x"], w[f"layer{Lr}.env"]) for e in edges]
+        n_out = 1 if final else dim
+        newV = []
+        for e in edges:
+            T = [[0.0] * n for _ in range(n_out)]
+            for (k, f) in enumerate(edges):
+                if f["i"] != e["i"]:
+                    continue
+                for (l1, l2, lo) in kept:
+                    C = cg.coupling(l1, l2, lo)
+                    a = al[l1, l2, lo] / math.sqrt(cnt[lo])
+                    for m1 in range(2 * l1 + 1):
+                        for m2 in range(2 * l2 + 1):
+                            for m3 in range(2 * lo + 1):
+                                cf = C[m1, m2, m3]
+                                if cf == 0.0:
+                                    continue
+                                c1, c2, c3 = l1 * l1 + m1, l2 * l2 + m2, lo * lo + m3
+                                for q in range(n):
+                                    T[c3][q] += a * cf * e["V"][c1][q] * cn * wk[k][l2 * n + q] * f["Y"][c2]
+            if mc.channel_mix:
+                Vn = [[sum(M[lof[c], v, q] * T[c][q] for q in range(n)) / math.sqrt(n) for v in range(n)]
+                      for c in range(n_out)]
+            else:
+                Vn = T
+            newV.append(Vn)
+        for e, Vn in zip(edges, newV):
+            h = _mlp(e["x"] + Vn[0], [w[f"layer{Lr}.mlp.W{k}"] for k in range(len(mc.latent_dims))])
+            e["x"] = [(a + e["u"] * b) / math.sqrt(2) for a, b in zip(e["x"], h)]
+            e["V"] = Vn
+    out = []
+    for e in edges:
+        y = e["x"]
+        for k in range(len(mc.edge_dims) + 1):
+            y = _matvec(y, w[f"edge.W{k}"])
+        out.append(y[0])
+    return np.asarray(out)

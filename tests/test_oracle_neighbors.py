@@ -1,0 +1,97 @@
+"""Pins of the oracle neighbour list (CPU only).
+
+The list is defined by exhaustive search (section "Allegro: Scalable
+Equivariant Deep Learning": ordered pairs within the cutoff).  It is checked
+against scipy's k-d tree (an independent library search), closed-form image
+counts, the ordered-pair symmetry and the strict cutoff tie rule.
+"""
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import workloads as W
+from oracle.neighbors import neighbor_list
+
+
+def _as_set(i, j, s):
+    return set(zip(i.tolist(), j.tolist(), map(tuple, s.tolist())))
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_matches_scipy_kdtree(cfg):
+    mc = W.model_config(cfg)
+    s = W.system(cfg)
+    i, j, sh = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="brute")
+    # scipy's own distance on the minimum image (box > 2 r_c here)
+    tree = cKDTree(s.pos, boxsize=s.cell)
+    pairs = tree.query_pairs(mc.r_cut, output_type="ndarray")
+    d = s.pos[pairs[:, 1]] - s.pos[pairs[:, 0]]
+    d -= np.round(d / s.cell) * s.cell
+    dist = np.sqrt((d * d).sum(1))
+    near_tie = np.abs(dist - mc.r_cut) < 1e-9
+    assert not near_tie.any()
+    ref = set()
+    for (a, b) in pairs.tolist():
+        ref.add((a, b)); ref.add((b, a))
+    got = set(zip(i.tolist(), j.tolist()))
+    assert got == ref
+    assert len(got) == len(i)  # one image per pair when L > 2 r_c
+
+
+def test_sorted_and_symmetric():
+    mc = W.model_config(1)
+    s = W.system(1)
+    i, j, sh = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut)
+    key = np.lexsort((sh[:, 2], sh[:, 1], sh[:, 0], j, i))
+    assert np.array_equal(key, np.arange(len(i)))
+    st = _as_set(i, j, sh)
+    assert all((b, a, (-x, -y, -z)) in st for (a, b, (x, y, z)) in st)
+
+
+def test_kdtree_candidates_equal_brute():
+    mc = W.model_config(2)
+    s = W.system(2)
+    a = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="brute")
+    b = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="kdtree")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_single_atom_small_box_images():
+    # one atom in a cube of side 3 with r_c = 4: images at |s| L < 4 -> the 6 face images
+    pos = np.array([[0.5, 1.0, 2.0]])
+    i, j, s = neighbor_list(pos, [3.0, 3.0, 3.0], [1, 1, 1], 4.0)
+    assert len(i) == 6 and np.all(np.abs(s).sum(1) == 1)
+    # r_c = 4.5: |s|^2 <= 2 -> 6 + 12 = 18 images
+    i, j, s = neighbor_list(pos, [3.0, 3.0, 3.0], [1, 1, 1], 4.5)
+    assert len(i) == 18
+
+
+def test_cutoff_tie_is_excluded():
+    pos = np.array([[1.0, 2.0, 3.0], [5.0, 2.0, 3.0], [1.0, 5.5, 3.0]])
+    i, j, s = neighbor_list(pos, [0, 0, 0], [0, 0, 0], 4.0)
+    got = _as_set(i, j, s)
+    assert (0, 1, (0, 0, 0)) not in got          # d = 4 exactly
+    assert (0, 2, (0, 0, 0)) in got              # d = 3.5
+    # periodic tie: image across a 20 A box at exactly 4 A
+    pos = np.array([[1.0, 1.0, 1.0], [17.0, 1.0, 1.0]])
+    i, j, s = neighbor_list(pos, [20.0, 20.0, 20.0], [1, 1, 1], 4.0)
+    assert len(i) == 0
+    pos = np.array([[1.0, 1.0, 1.0], [17.25, 1.0, 1.0]])
+    i, j, s = neighbor_list(pos, [20.0, 20.0, 20.0], [1, 1, 1], 4.0)
+    assert _as_set(i, j, s) == {(0, 1, (-1, 0, 0)), (1, 0, (1, 0, 0))}
+
+
+def test_ghost_shell_list_matches_periodic():
+    """Centres of a non-periodic box plus its periodic-image ghost shell see
+    exactly the neighbours of the periodic box (strict locality, section
+    "Optimized LAMMPS-Kokkos implementation")."""
+    mc = W.model_config(1)
+    s = W.system(1)
+    g = W.ghost_shell(s, mc.r_cut + 0.5)
+    i0, j0, s0 = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut)
+    i1, j1, s1 = neighbor_list(g.pos, g.cell, g.pbc, mc.r_cut, n_local=g.n_local)
+    assert np.all(s1 == 0)
+    own = np.concatenate([np.arange(s.n_local), g.ghost_owner])
+    assert np.array_equal(i0, i1) or sorted(zip(i0, own[j1])) == sorted(zip(i0, j0))
+    assert sorted(zip(i1.tolist(), own[j1].tolist())) == sorted(zip(i0.tolist(), j0.tolist()))
