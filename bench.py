@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the Allegro energy+force path on one MI355X.
+
+One step = allegro_neighbors + allegro_energy_forces (energy, per-atom
+energies, forces, virial) on the 23,558-atom protein-like periodic box
+(0.1 atoms/A^3, H:C:N:O = 50:30:8:12, r_c = 6 A; model: 8 Bessel, l_max 2,
+2 layers, 64 tensor channels, latent MLPs [256, 256, 256], edge MLP [128]),
+seeded synthetic positions and weights already resident in HBM.
+
+The headline value is BF16-mixed atom-steps/s (MLP GEMMs in BF16 on MFMA with
+FP32 accumulation); the plain FP32 path on the same GPU is reported beside it.
+`roofline` describes the dominant kernel, timed with HIP events on the stream
+it runs on; `cpu_baseline` is the FP64 oracle on the host cores on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BF16_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
+FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
+
+
+def mlp_macs_per_edge(mc):
+    """Algorithmic multiply-adds per edge of each MLP kernel kind: forward
+    GEMMs (incl. the fused head), and input-gradient GEMMs of the adjoint
+    (the adjoint's recomputation of the forward chain is not counted)."""
+    d, n, LW = mc.latent, mc.n_tensor, (mc.l_max + 1) * mc.n_tensor
+
+    def chain(dims):
+        return sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+
+    two = chain([2 * mc.n_species + mc.n_bessel] + list(mc.twobody_dims))
+    lat = chain([d + n] + list(mc.latent_dims))
+    out = {
+        "mlp_fwd_twobody": two + d * 2 * LW,
+        "mlp_fwd_latent": lat + d * LW,
+        "mlp_fwd_final": lat + d,
+        "mlp_bwd_final": lat,
+        "mlp_bwd_latent": lat + LW * d,
+        "mlp_bwd_twobody": two + 2 * LW * d,
+    }
+    if mc.n_layers == 1:
+        out.pop("mlp_fwd_latent")
+        out.pop("mlp_bwd_latent")
+    return out
+
+
+def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times):
+    import torch
+    import paper_2304_10061_amd as P
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    m = P.Model(P.config_from(mc, precision=precision), W.pack_weights(mc, w))
+    pos = torch.as_tensor(s.pos, dtype=torch.float64, device=dev)
+    sp = torch.as_tensor(s.species, dtype=torch.int32, device=dev)
+    F = torch.empty((s.n_total, 3), dtype=torch.float64, device=dev)
+    Ea = torch.empty(s.n_local, dtype=torch.float64, device=dev)
+    vir = torch.empty(9, dtype=torch.float64, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def step():
+        m.neighbors(pos, sp, s.cell, s.pbc, s.n_local)
+        m.energy_forces(pos, sp, F, atom_energy=Ea, virial=vir, energy=E)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res = {"ms_per_step": ms, "edges": m.num_edges(), "energy": float(E.item()),
+           "workspace_GB": m.workspace_bytes() / 1e9}
+    if want_kernel_times:
+        m.set_timing(True)
+        reps = 3
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        kt = m.kernel_times()
+        m.set_timing(False)
+        res["kernel_ms"] = {k: v[0] / reps for k, v in kt.items()}
+        res["kernel_launches"] = {k: v[1] // reps for k, v in kt.items()}
+        # the neighbour build alone (events on the same stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            m.neighbors(pos, sp, s.cell, s.pbc, s.n_local)
+        ev[1].record()
+        torch.cuda.synchronize()
+        res["neighbors_ms"] = ev[0].elapsed_time(ev[1]) / reps
+    m.close()
+    return res
+
+
+def cpu_baseline(mc, s, w, n_centres):
+    import torch
+    from oracle import model as OM
+    from oracle.neighbors import neighbor_list
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    nbr = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="kdtree")
+    rng = np.random.default_rng(0)
+    cents = np.sort(rng.choice(s.n_local, size=n_centres, replace=False))
+    p = OM.Params(mc, w)
+    t0 = time.perf_counter()
+    OM.evaluate_centres(mc, w, s, cents, nbr, params=p)
+    t = time.perf_counter() - t0
+    return {"value": n_centres / t, "unit": "atom-steps/s", "cores": int(torch.get_num_threads()),
+            "kind": "oracle",
+            "sample": f"{n_centres} random centres of the same box (their {int(np.sum(np.isin(nbr[0], cents)))} "
+                      f"edges, energy + edge gradients in FP64), {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the energy/force path runs on a single MI355X "
+              "(spatial decomposition across GPUs is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import workloads as W
+    mc, s, w = W.workload(3)
+    bf = run_gpu(mc, s, w, 1, args.steps, args.warmup, want_kernel_times=True)
+    fp = None if args.no_fp32 else run_gpu(mc, s, w, 0, max(3, args.steps // 4), min(2, args.warmup), True)
+
+    value = s.n_local / (bf["ms_per_step"] * 1e-3)
+    macs = mlp_macs_per_edge(mc)
+    kms = bf["kernel_ms"]
+    dom = max(kms, key=kms.get)
+    roof = None
+    if dom in macs:
+        flops = 2.0 * macs[dom] * bf["edges"] * bf["kernel_launches"].get(dom, 1)
+        achieved = flops / (kms[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                "flops_per_launch": flops / max(1, bf["kernel_launches"].get(dom, 1)),
+                "avg_launch_ms": kms[dom] / max(1, bf["kernel_launches"].get(dom, 1))}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
+                "frac": None, "traffic": None}
+    # whole-step MLP-GEMM MFMA utilisation
+    mlp_ms = sum(v for k, v in kms.items() if k in macs)
+    mlp_flops = 2.0 * sum(macs.values()) * bf["edges"]
+    out = {
+        "metric": "atom-steps/s (E+forces), 23.5k-atom protein-like box, FP32 vs BF16-MFMA",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": bf["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "protein-like periodic box: 23558 atoms, 61.76 A cube, H:C:N:O 50:30:8:12, "
+                               "jittered lattice +-0.5 A, r_c 6 A; Allegro l_max 2, 2 layers, 64 tensor "
+                               "channels, latent MLP [256,256,256], edge MLP [128]; random weights",
+                   "atoms": int(s.n_local), "edges": int(bf["edges"]), "global_batch": int(s.n_local),
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "mlp_gemm": {"tflops": mlp_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms else None,
+                     "mfma_frac": (mlp_flops / (mlp_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS) if mlp_ms else None,
+                     "ms": mlp_ms},
+        "kernel_ms": {k: round(v, 4) for k, v in sorted(kms.items(), key=lambda kv: -kv[1])},
+        "neighbors_ms": bf["neighbors_ms"],
+        "workspace_GB": bf["workspace_GB"],
+    }
+    if fp is not None:
+        out["fp32"] = {"value": s.n_local / (fp["ms_per_step"] * 1e-3), "ms_per_step": fp["ms_per_step"],
+                       "mlp_gemm_ms": sum(v for k, v in fp["kernel_ms"].items() if k in macs),
+                       "energy_bf16_minus_fp32_per_atom": (bf["energy"] - fp["energy"]) / s.n_local}
+        out["bf16_speedup_vs_fp32"] = fp["ms_per_step"] / bf["ms_per_step"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mc, s, w, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * allegro_mi355x.h - C interface of the MI355X (gfx950) Allegro energy-and-force
+ * library.
+ *
+ * The method (arXiv 2304.10061, section "Allegro: Scalable Equivariant Deep
+ * Learning"): the total energy is a sum of per-species scaled and shifted atomic
+ * energies, E = sum_i sigma_{Z_i} E_i + mu_{Z_i}; each atomic energy is a sum of
+ * ordered-pair energies E_i = sum_{j in N(i)} E_ij over the neighbours j of i
+ * within the cutoff r_c; the pair energies come from a strictly local network
+ * of scalar (latent MLP) and tensor (Clebsch-Gordan tensor product, Eq. tp)
+ * tracks.  Molecular dynamics needs forces every step (section "Problem
+ * overview"), returned here as F = -dE/dx together with per-atom energies and
+ * the virial, as an MD engine's pair style consumes them (section "Optimized
+ * LAMMPS-Kokkos implementation").  Units: eV and Angstrom (section "Training
+ * details").
+ *
+ * Conventions for every entry point
+ *  - Returns ALLEGRO_OK (0) or a negative status; never aborts and never lets a
+ *    C++ exception escape.  allegro_last_error() describes the last failure.
+ *  - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *    pointers are host memory owned by the caller.  The library owns the
+ *    neighbour list, the coupling tables, the packed weights and its workspace.
+ *  - All device work is ordered on `stream` (a hipStream_t; NULL = the default
+ *    stream).  Functions that report a count to the host synchronise that
+ *    stream.  A model handle is not thread-safe.
+ *  - Atoms [0, n_local) are centres; atoms [n_local, n_total) are ghosts that
+ *    only appear as neighbours (one GPU's spatial-decomposition share).
+ */
+#ifndef ALLEGRO_MI355X_H
+#define ALLEGRO_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ALLEGRO_OK = 0,
+  ALLEGRO_E_INVAL = -1,     /* bad argument, shape or unsupported configuration */
+  ALLEGRO_E_NOMEM = -2,     /* device or host allocation failed */
+  ALLEGRO_E_CAPACITY = -3,  /* edge capacity exceeded (capacity-limited mode);
+                               capacity has been regrown, call again */
+  ALLEGRO_E_DEVICE = -4,    /* a HIP runtime call failed */
+  ALLEGRO_E_NONFINITE = -5, /* non-finite energy or forces were produced */
+  ALLEGRO_E_STATE = -6      /* call order violated (e.g. no neighbour list yet) */
+};
+
+enum { ALLEGRO_PREC_FP32 = 0, ALLEGRO_PREC_BF16 = 1 };
+
+typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
+
+/*
+ * Model hyper-parameters (section "Training details" lists the kinds: two-body
+ * latent MLP, later latent MLPs, a linear environment embedding, an edge-energy
+ * MLP with one hidden layer and no nonlinearity, 8 Bessel functions with a
+ * polynomial envelope, l_max = 2, full O(3)).
+ *   n_species        number of atom types (one-hot width), 1..12, with 2 n_species + n_bessel <= 32
+ *   n_bessel         radial basis size, 1..16
+ *   envelope_p       polynomial envelope exponent p (u(r_c) = u' = u'' = 0)
+ *   l_max            1 or 2
+ *   n_layers         1 or 2 Allegro (tensor product) layers
+ *   n_tensor         tensor feature channels n: 8, 16, 32 or 64
+ *   twobody_dims     output widths of the two-body MLP (1..3 layers); the last
+ *                    one is the latent width d
+ *   latent_dims      output widths of each later latent MLP (1..3 layers); last = d
+ *   edge_dims        hidden width(s) of the edge-energy MLP (exactly 1 entry)
+ *   r_cut            cutoff radius (A)
+ *   avg_num_neighbors  environment-sum normalisation, the sum is scaled by
+ *                    1/sqrt(avg_num_neighbors)
+ *   channel_mix      1 = per-irrep linear channel mixing after each tensor
+ *                    product, 0 = none
+ *   precision        ALLEGRO_PREC_FP32 or ALLEGRO_PREC_BF16 (MLP GEMMs in BF16
+ *                    with FP32 accumulation)
+ *   edge_chunk       0 = evaluate all edges at once; otherwise the largest
+ *                    number of edges whose activations are held at a time
+ *                    (whole centre segments; bounds workspace memory)
+ * Widths d must be multiples of 16 and at most 512.
+ */
+typedef struct {
+  int32_t n_species, n_bessel, envelope_p, l_max, n_layers, n_tensor;
+  int32_t twobody_dims[4], n_twobody;
+  int32_t latent_dims[4], n_latent;
+  int32_t edge_dims[4], n_edge;
+  double r_cut, avg_num_neighbors;
+  int32_t channel_mix;
+  int32_t precision;
+  int64_t edge_chunk;
+} AllegroConfig;
+
+/* Host-side description of a configuration (no device work). */
+typedef struct {
+  int64_t n_weights;          /* floats expected by allegro_create */
+  int32_t n_paths[2];         /* kept tensor-product paths per layer */
+  int32_t n_nonzero[2];       /* non-zeros of each layer's fused coupling table */
+  int32_t dim;                /* (l_max+1)^2 strided components */
+  int32_t latent;             /* latent width d */
+} AllegroInfo;
+
+/*
+ * allegro_describe: validate `cfg` and describe it (host only, no GPU needed).
+ * Path selection and pruning follow section "Optimized tensor product": every
+ * (l1,p1) x (l2,p2) -> (l_out,p_out) with |l1-l2| <= l_out <= l1+l2,
+ * p_out = p1 p2, keeping only paths that can still reach the final scalars.
+ * Returns ALLEGRO_E_INVAL for unsupported configurations.
+ */
+int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info);
+
+/*
+ * allegro_create: build a model on the current HIP device.
+ *   weights        host, n_weights floats in this order (row-major float32):
+ *                  twobody.W0..Wk [fan_in][fan_out] (fan_in of W0 = 2 S + n_bessel:
+ *                  one-hot(Z_i), one-hot(Z_j), radial basis);
+ *                  embed0 [d][(l_max+1) n]  (column l*n + u);
+ *                  per layer L: env [d][(l_max+1) n], alpha [l_max+1]^3 indexed
+ *                  [l1][l2][l_out] (raw path weights; unused entries ignored),
+ *                  mix [l_max+1][n][n] indexed [l][v][u], mlp.W0..Wk with
+ *                  fan_in of W0 = d + n ([x, scalar tensor features]);
+ *                  edge.W0 [d][h], edge.W1 [h][1].
+ *   species_scale  host [n_species] sigma (NULL = 1)
+ *   species_shift  host [n_species] mu (NULL = 0)
+ *   out            receives the handle (NULL on failure)
+ * The weights are copied; the caller may free them afterwards.
+ */
+int allegro_create(const AllegroConfig* cfg, const float* weights, int64_t n_weights,
+                   const double* species_scale, const double* species_shift,
+                   AllegroModel** out);
+
+/*
+ * allegro_neighbors: build the ordered neighbour list of the n_local centres
+ * (every (i, j, s) with |x_j - x_i + s L| < r_c, i != j or s != 0; section
+ * "Allegro: Scalable Equivariant Deep Learning").  The distance test is
+ *   dx = (x_j - x_i) + s_x L_x (per axis, IEEE double, no fused operations),
+ *   d2 = (dx dx + dy dy) + dz dz, kept iff d2 < r_c * r_c,
+ * and each centre's neighbours are sorted by (j, s_x, s_y, s_z), so the list is
+ * reproducible bit for bit.
+ *   pos      dev [n_total][3] double (any coordinates; periodic axes need not
+ *            be wrapped, within 500 box lengths of the box)
+ *   species  dev [n_total] int32 in [0, n_species)
+ *   cell     host [9] double, row vectors; must be diagonal (orthorhombic);
+ *            entries of non-periodic axes are ignored
+ *   pbc      host [3] int32, 1 = periodic axis
+ *   n_edges  host, receives the edge count (may be NULL)
+ * Synchronises `stream` (the edge count sizes the list).  The list stays valid
+ * for allegro_energy_forces until the next call.
+ */
+int allegro_neighbors(AllegroModel* m, int64_t n_local, int64_t n_total, const double* pos,
+                      const int32_t* species, const double* cell, const int32_t* pbc,
+                      void* stream, int64_t* n_edges);
+
+/*
+ * allegro_energy_forces: evaluate the network on the current neighbour list.
+ *   pos, species  the arrays given to allegro_neighbors (same n_total)
+ *   atom_energy   dev [n_local] double: sigma_Z E_i + mu_Z (may be NULL)
+ *   forces        dev [n_total][3] double, overwritten; ghost rows hold the
+ *                 forces on the ghost copies (fold them onto their owners)
+ *   virial        dev [9] double, W = -sum_e r_e (x) dE/dr_e (may be NULL)
+ *   atom_virial   dev [n_total][9] double, half of each edge term to each end
+ *                 (may be NULL)
+ *   energy        dev [1] double, total energy (may be NULL)
+ * Energy reduction and virial are accumulated in FP64; everything else runs in
+ * the model's precision.  Does not synchronise.
+ */
+int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* species,
+                          double* atom_energy, double* forces, double* virial,
+                          double* atom_virial, double* energy, void* stream);
+
+/*
+ * allegro_copy_edges: copy the current neighbour list to caller buffers.
+ *   centre    dev [E] int32 (i), neighbor dev [E] int32 (j),
+ *   shift     dev [E][3] int32 (s); any of them may be NULL.
+ */
+int allegro_copy_edges(AllegroModel* m, int32_t* centre, int32_t* neighbor, int32_t* shift,
+                       void* stream);
+
+/* allegro_num_edges: edge count of the current neighbour list (host value). */
+int64_t allegro_num_edges(const AllegroModel* m);
+
+/*
+ * allegro_set_timing: enable (1) or disable (0) per-kernel timing of
+ * allegro_energy_forces and reset the accumulated times.  When enabled, every
+ * kernel launch is bracketed by a pair of HIP events recorded on the caller's
+ * stream (a small overhead; for measurement runs only).
+ */
+int allegro_set_timing(AllegroModel* m, int32_t enable);
+
+/*
+ * allegro_kernel_times: accumulated event times per kernel kind since the last
+ * allegro_set_timing.  Synchronises the recorded events.
+ *   max_entries  capacity of the output arrays
+ *   names        host [max_entries][48] NUL-terminated kernel kind names (may be NULL)
+ *   total_ms     host [max_entries] summed duration in milliseconds (may be NULL)
+ *   launches     host [max_entries] number of timed launches (may be NULL)
+ *   n_entries    host, number of kernel kinds recorded (may exceed max_entries)
+ */
+int allegro_kernel_times(AllegroModel* m, int32_t max_entries, char* names, double* total_ms,
+                         int64_t* launches, int32_t* n_entries);
+
+/* allegro_workspace_bytes: device bytes currently held by the model. */
+int64_t allegro_workspace_bytes(const AllegroModel* m);
+
+/* allegro_destroy: free the model (NULL is ignored). */
+void allegro_destroy(AllegroModel* m);
+
+/* allegro_last_error: message of the last failure of `m` (or of a failed
+ * create when m is NULL); never NULL. */
+const char* allegro_last_error(const AllegroModel* m);
+
+/* allegro_status_string: name of a status code. */
+const char* allegro_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALLEGRO_MI355X_H */

@@ -1,0 +1,931 @@
+// abi.cpp - the C interface: model construction (weight packing, coupling
+// tables), the neighbour-list driver and the energy/force driver.
+//
+// Host-side work happens once per model (allegro_create) or once per neighbour
+// build (allocation of the edge workspace, which depends on the edge count);
+// allegro_energy_forces only enqueues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/allegro_mi355x.h"
+#include "coupling.h"
+#include "internal.h"
+
+using namespace allegro;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIP_OK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      throw Fail{ALLEGRO_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)};       \
+  } while (0)
+
+#define REQUIRE(cond, msg)                                  \
+  do {                                                      \
+    if (!(cond)) throw Fail{ALLEGRO_E_INVAL, (msg)};        \
+  } while (0)
+
+// Device allocation that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t want) {
+    if (want <= bytes && p) return;
+    release();
+    if (want == 0) want = 256;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Fail{ALLEGRO_E_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed"};
+    }
+    bytes = want;
+  }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+void upload(DevBuf& b, const void* src, size_t bytes) {
+  b.ensure(bytes);
+  HIP_OK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+}
+
+int rup(int v, int m) { return ((v + m - 1) / m) * m; }
+
+// Packs a K x N row-major matrix (y = x @ W) into MFMA B fragments.
+void pack_b(const std::vector<double>& W, int K, int N, int prec, std::vector<char>& out, GemmB& g) {
+  const int Kp = rup(K, 32), Np = rup(N, 32), nkb = Kp / 32;
+  const size_t count = (size_t)Kp * Np;
+  const int esz = prec ? 2 : 4;
+  out.assign(count * esz, 0);
+  for (int k = 0; k < K; ++k)
+    for (int n = 0; n < N; ++n) {
+      const int nt = n / 16, kb = k / 32, lane = (n % 16) + 16 * ((k % 32) / 8), el = k % 8;
+      const size_t idx = ((size_t)(nt * nkb + kb) * 64 + lane) * 8 + el;
+      const float v = (float)W[(size_t)k * N + n];
+      if (prec) {
+        __bf16 b = (__bf16)v;
+        std::memcpy(out.data() + idx * 2, &b, 2);
+      } else {
+        std::memcpy(out.data() + idx * 4, &v, 4);
+      }
+    }
+  g.K = K; g.N = N; g.Kp = Kp; g.Np = Np;
+}
+
+std::vector<double> transpose(const std::vector<double>& W, int K, int N) {
+  std::vector<double> T((size_t)K * N);
+  for (int k = 0; k < K; ++k)
+    for (int n = 0; n < N; ++n) T[(size_t)n * K + k] = W[(size_t)k * N + n];
+  return T;
+}
+
+struct PackedMat {
+  DevBuf buf;
+  GemmB g;
+};
+
+void make_packed(PackedMat& pm, const std::vector<double>& W, int K, int N, int prec) {
+  std::vector<char> host;
+  pack_b(W, K, N, prec, host, pm.g);
+  upload(pm.buf, host.data(), host.size());
+  pm.g.p = pm.buf.p;
+}
+
+struct Validated {
+  int S, nb, p, lmax, nl, n, d, dim, LW, h;
+  std::vector<int> dims2b, dimsL;
+  int64_t n_weights;
+};
+
+bool pow2_in(int n) { return n == 8 || n == 16 || n == 32 || n == 64; }
+
+Validated validate(const AllegroConfig* c) {
+  REQUIRE(c != nullptr, "config is NULL");
+  Validated v{};
+  v.S = c->n_species; v.nb = c->n_bessel; v.p = c->envelope_p; v.lmax = c->l_max;
+  v.nl = c->n_layers; v.n = c->n_tensor;
+  REQUIRE(v.S >= 1 && v.S <= 12, "n_species must be in 1..12");
+  REQUIRE(v.nb >= 1 && v.nb <= 16, "n_bessel must be in 1..16");
+  REQUIRE(2 * v.S + v.nb <= 32, "2 n_species + n_bessel must be at most 32");
+  REQUIRE(v.p >= 2 && v.p <= 12, "envelope_p must be in 2..12");
+  REQUIRE(v.lmax == 1 || v.lmax == 2, "l_max must be 1 or 2");
+  REQUIRE(v.nl == 1 || v.nl == 2, "n_layers must be 1 or 2 (deeper models need odd-parity paths)");
+  REQUIRE(pow2_in(v.n), "n_tensor must be 8, 16, 32 or 64");
+  REQUIRE(c->n_twobody >= 1 && c->n_twobody <= 3, "n_twobody must be 1..3");
+  REQUIRE(c->n_latent >= 1 && c->n_latent <= 3, "n_latent must be 1..3");
+  REQUIRE(c->n_edge == 1, "edge MLP must have exactly one hidden layer");
+  for (int k = 0; k < c->n_twobody; ++k) v.dims2b.push_back(c->twobody_dims[k]);
+  for (int k = 0; k < c->n_latent; ++k) v.dimsL.push_back(c->latent_dims[k]);
+  v.d = v.dims2b.back();
+  REQUIRE(v.dimsL.back() == v.d, "last latent width must equal last two-body width");
+  for (int w : v.dims2b) REQUIRE(w >= 16 && w <= 512 && w % 16 == 0, "MLP widths must be multiples of 16 in 16..512");
+  for (int w : v.dimsL) REQUIRE(w >= 16 && w <= 512 && w % 16 == 0, "MLP widths must be multiples of 16 in 16..512");
+  v.h = c->edge_dims[0];
+  REQUIRE(v.h >= 1 && v.h <= 4096, "edge hidden width must be in 1..4096");
+  REQUIRE(c->r_cut > 0 && std::isfinite(c->r_cut), "r_cut must be positive");
+  REQUIRE(c->avg_num_neighbors > 0 && std::isfinite(c->avg_num_neighbors), "avg_num_neighbors must be positive");
+  REQUIRE(c->precision == ALLEGRO_PREC_FP32 || c->precision == ALLEGRO_PREC_BF16, "precision must be 0 or 1");
+  REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
+  v.dim = (v.lmax + 1) * (v.lmax + 1);
+  v.LW = (v.lmax + 1) * v.n;
+  // weight count, in the documented order
+  int64_t cnt = 0;
+  int prev = 2 * v.S + v.nb;
+  for (int w : v.dims2b) { cnt += (int64_t)prev * w; prev = w; }
+  cnt += (int64_t)v.d * v.LW;                              // embed0
+  const int L1 = v.lmax + 1;
+  for (int L = 0; L < v.nl; ++L) {
+    cnt += (int64_t)v.d * v.LW;                            // env
+    cnt += (int64_t)L1 * L1 * L1;                          // alpha
+    cnt += (int64_t)L1 * v.n * v.n;                        // mix
+    prev = v.d + v.n;
+    for (int w : v.dimsL) { cnt += (int64_t)prev * w; prev = w; }
+  }
+  cnt += (int64_t)v.d * v.h + v.h;                         // edge MLP
+  v.n_weights = cnt;
+  return v;
+}
+
+// Fused coupling-table values of one layer, in the compile-time pattern order.
+template <int LMAX, bool FINAL>
+std::vector<float> fused_values(const double* alpha_raw, int* nnz) {
+  using Pat = TpPattern<LMAX, FINAL>;
+  const int L1 = LMAX + 1;
+  // paths into each output l, and Frobenius norm of each path block
+  int per_out[3] = {0, 0, 0};
+  double norm2[3][3][3] = {};
+  for (int l1 = 0; l1 <= LMAX; ++l1)
+    for (int l2 = 0; l2 <= LMAX; ++l2)
+      for (int lo = 0; lo <= LMAX; ++lo) {
+        if (!path_kept(l1, l2, lo, LMAX, FINAL)) continue;
+        per_out[lo]++;
+        for (int a = l1 * l1; a < (l1 + 1) * (l1 + 1); ++a)
+          for (int b = l2 * l2; b < (l2 + 1) * (l2 + 1); ++b)
+            for (int c = lo * lo; c < (lo + 1) * (lo + 1); ++c) {
+              const double g = gaunt_raw(a, b, c);
+              norm2[l1][l2][lo] += g * g;
+            }
+      }
+  std::vector<float> out(Pat::NNZ);
+  for (int k = 0; k < Pat::NNZ; ++k) {
+    const TpEntry t = Pat::list.e[k];
+    const int l1 = l_of(t.a), l2 = l_of(t.b), lo = l_of(t.c);
+    const double al = alpha_raw[(l1 * L1 + l2) * L1 + lo] / std::sqrt((double)per_out[lo]);
+    out[k] = (float)(al * gaunt_raw(t.a, t.b, t.c) / std::sqrt(norm2[l1][l2][lo]));
+  }
+  *nnz = Pat::NNZ;
+  return out;
+}
+
+std::vector<float> fused_values_rt(int lmax, bool final_layer, const double* alpha, int* nnz) {
+  if (lmax == 1) return final_layer ? fused_values<1, true>(alpha, nnz) : fused_values<1, false>(alpha, nnz);
+  return final_layer ? fused_values<2, true>(alpha, nnz) : fused_values<2, false>(alpha, nnz);
+}
+
+int count_paths(int lmax, bool final_layer) {
+  int c = 0;
+  for (int l1 = 0; l1 <= lmax; ++l1)
+    for (int l2 = 0; l2 <= lmax; ++l2)
+      for (int lo = 0; lo <= lmax; ++lo) c += path_kept(l1, l2, lo, lmax, final_layer) ? 1 : 0;
+  return c;
+}
+
+struct Mlp {
+  PackedMat fwd[kMaxMlpLayers], bwd[kMaxMlpLayers];
+  int nl = 0;
+  MlpW view() const {
+    MlpW w;
+    w.nl = nl;
+    for (int k = 0; k < nl; ++k) { w.fwd[k] = fwd[k].g; w.bwd[k] = bwd[k].g; }
+    return w;
+  }
+};
+
+}  // namespace
+
+struct AllegroModel {
+  AllegroConfig cfg{};
+  Validated v{};
+  int prec = 1;
+  std::string err;
+  int device = 0;
+
+  Mlp twobody, latent[2];
+  PackedMat head0, head0T, env2, env2T;   // [embed0 | env1] and env2
+  DevBuf mixF[2], mixB[2];                // packed FP32 mixing matrices per layer
+  int mix_stride = 0;
+  DevBuf tpw[2];                          // fused coupling non-zeros per layer
+  float tp_final[9] = {0};                // final-layer diagonal weights
+  DevBuf we, gconst, scale, shift;
+  double c_norm = 1.0;
+
+  // neighbour list
+  int64_t n_local = -1, n_total = 0, E = 0;
+  double L[3] = {0, 0, 0};
+  DevBuf ei, ej, es, row_ptr, rrow_ptr, redge, keys;
+  DevBuf cell_of, img, cell_count, cell_start, cell_cursor, cell_atoms, count, rcount, rcursor;
+  DevBuf bbox, scan_tmp, err_flag;
+  std::vector<int32_t> h_row_ptr;
+  std::vector<int64_t> chunk_c;           // centre boundaries of chunks
+  std::vector<int64_t> chunk_rp_off;      // offset of each chunk's rebased row pointers
+  DevBuf chunk_rp;
+  int64_t Ec = 0, Nc = 0;
+
+  // optional per-kernel timing with HIP events on the caller's stream
+  bool timing = false;
+  struct KTime { std::string name; double ms = 0.0; int64_t launches = 0; };
+  std::vector<KTime> ktimes;
+  std::vector<std::pair<size_t, std::pair<hipEvent_t, hipEvent_t>>> pending;
+
+  // workspace
+  DevBuf eb, x[2], head0o, wenv2, V1, gam[2], eij, gxa, gxb, gTf, gs, ghead0, gw2, gT, gY, gu, gR;
+  DevBuf g_e, atom_e, partial;
+};
+
+namespace {
+
+int fail(AllegroModel* m, const Fail& f) {
+  if (m) m->err = f.msg;
+  else g_create_error = f.msg;
+  return f.code;
+}
+
+std::vector<double> slice(const float* w, int64_t& off, int64_t count) {
+  std::vector<double> out(w + off, w + off + count);
+  off += count;
+  return out;
+}
+
+void build_mlp(Mlp& mlp, const std::vector<std::vector<double>>& Ws, const std::vector<int>& dims, int prec) {
+  mlp.nl = (int)Ws.size();
+  for (int k = 0; k < mlp.nl; ++k) {
+    make_packed(mlp.fwd[k], Ws[k], dims[k], dims[k + 1], prec);
+    make_packed(mlp.bwd[k], transpose(Ws[k], dims[k], dims[k + 1]), dims[k + 1], dims[k], prec);
+  }
+}
+
+void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const double* scale, const double* shift) {
+  const Validated& v = m->v;
+  REQUIRE(w != nullptr, "weights is NULL");
+  REQUIRE(n_weights == v.n_weights, "n_weights is " + std::to_string(n_weights) + ", expected " +
+                                        std::to_string(v.n_weights));
+  for (int64_t k = 0; k < n_weights; ++k) REQUIRE(std::isfinite(w[k]), "weights contain non-finite values");
+  HIP_OK(hipGetDevice(&m->device));
+  const int prec = m->prec;
+  const int n = v.n, d = v.d, LW = v.LW, L1 = v.lmax + 1;
+  int64_t off = 0;
+  // two-body MLP
+  std::vector<int> dims{2 * v.S + v.nb};
+  std::vector<std::vector<double>> Ws;
+  for (int wd : v.dims2b) {
+    Ws.push_back(slice(w, off, (int64_t)dims.back() * wd));
+    dims.push_back(wd);
+  }
+  build_mlp(m->twobody, Ws, dims, prec);
+  const std::vector<double> embed0 = slice(w, off, (int64_t)d * LW);
+  std::vector<double> env[2], alpha[2], mix[2];
+  std::vector<std::vector<double>> mlpW[2];
+  for (int L = 0; L < v.nl; ++L) {
+    env[L] = slice(w, off, (int64_t)d * LW);
+    alpha[L] = slice(w, off, (int64_t)L1 * L1 * L1);
+    mix[L] = slice(w, off, (int64_t)L1 * n * n);
+    int prev = d + n;
+    for (int wd : v.dimsL) {
+      mlpW[L].push_back(slice(w, off, (int64_t)prev * wd));
+      prev = wd;
+    }
+  }
+  const std::vector<double> We0 = slice(w, off, (int64_t)d * v.h);
+  const std::vector<double> We1 = slice(w, off, (int64_t)v.h);
+  const double rn = 1.0 / std::sqrt((double)n);
+
+  // the final layer's scalar channel mixing folds into the rows of its first
+  // latent-MLP matrix that read the scalar tensor features
+  {
+    const int L = v.nl - 1;
+    const int N0 = v.dimsL[0];
+    std::vector<double>& W0 = mlpW[L][0];
+    if (m->cfg.channel_mix) {
+      std::vector<double> folded((size_t)n * N0, 0.0);
+      for (int u = 0; u < n; ++u)
+        for (int vv = 0; vv < n; ++vv) {
+          const double mvu = mix[L][(size_t)vv * n + u] * rn;   // mix[0][v][u]
+          for (int c = 0; c < N0; ++c) folded[(size_t)u * N0 + c] += mvu * W0[(size_t)(d + vv) * N0 + c];
+        }
+      for (int u = 0; u < n; ++u)
+        for (int c = 0; c < N0; ++c) W0[(size_t)(d + u) * N0 + c] = folded[(size_t)u * N0 + c];
+    }
+  }
+  std::vector<int> ldims{d + n};
+  for (int wd : v.dimsL) ldims.push_back(wd);
+  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, prec);
+
+  // heads: [embed0 | env1] after the two-body MLP, env2 after the first latent MLP
+  {
+    std::vector<double> H((size_t)d * 2 * LW);
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < LW; ++c) {
+        H[(size_t)r * 2 * LW + c] = embed0[(size_t)r * LW + c];
+        H[(size_t)r * 2 * LW + LW + c] = env[0][(size_t)r * LW + c];
+      }
+    make_packed(m->head0, H, d, 2 * LW, prec);
+    make_packed(m->head0T, transpose(H, d, 2 * LW), 2 * LW, d, prec);
+    if (v.nl == 2) {
+      make_packed(m->env2, env[1], d, LW, prec);
+      make_packed(m->env2T, transpose(env[1], d, LW), LW, d, prec);
+    }
+  }
+  // channel mixing matrices of non-final layers (FP32): forward W[u][v] = M[v][u],
+  // adjoint W[v][u] = M[v][u]
+  for (int L = 0; L + 1 < v.nl; ++L) {
+    std::vector<char> allF, allB;
+    for (int l = 0; l < L1; ++l) {
+      std::vector<double> M(mix[L].begin() + (size_t)l * n * n, mix[L].begin() + (size_t)(l + 1) * n * n);
+      std::vector<char> hf, hb;
+      GemmB g;
+      pack_b(transpose(M, n, n), n, n, 0, hf, g);
+      pack_b(M, n, n, 0, hb, g);
+      m->mix_stride = (int)(hf.size() / sizeof(float));
+      allF.insert(allF.end(), hf.begin(), hf.end());
+      allB.insert(allB.end(), hb.begin(), hb.end());
+    }
+    upload(m->mixF[L], allF.data(), allF.size());
+    upload(m->mixB[L], allB.data(), allB.size());
+  }
+  // fused coupling tables
+  for (int L = 0; L < v.nl; ++L) {
+    const bool fin = L == v.nl - 1;
+    int nnz = 0;
+    std::vector<float> vals = fused_values_rt(v.lmax, fin, alpha[L].data(), &nnz);
+    upload(m->tpw[L], vals.data(), vals.size() * sizeof(float));
+    if (fin) {
+      // final pattern entries are (a, a, 0) in ascending a
+      for (int k = 0; k < 9; ++k) m->tp_final[k] = k < nnz ? vals[k] : 0.0f;
+    }
+  }
+  // folded edge-energy vector and sigma_Z-scaled copies (the constant dE/dx^{N_l})
+  std::vector<double> wev(d, 0.0);
+  for (int r = 0; r < d; ++r)
+    for (int k = 0; k < v.h; ++k) wev[r] += We0[(size_t)r * v.h + k] * We1[k];
+  std::vector<float> wef(wev.begin(), wev.end());
+  upload(m->we, wef.data(), wef.size() * sizeof(float));
+  std::vector<double> sc(v.S, 1.0), sh(v.S, 0.0);
+  for (int s = 0; s < v.S; ++s) {
+    if (scale) sc[s] = scale[s];
+    if (shift) sh[s] = shift[s];
+    REQUIRE(std::isfinite(sc[s]) && std::isfinite(sh[s]), "species scale/shift must be finite");
+  }
+  std::vector<float> gc((size_t)v.S * d);
+  for (int s = 0; s < v.S; ++s)
+    for (int r = 0; r < d; ++r) gc[(size_t)s * d + r] = (float)(sc[s] * wev[r]);
+  upload(m->gconst, gc.data(), gc.size() * sizeof(float));
+  upload(m->scale, sc.data(), sc.size() * sizeof(double));
+  upload(m->shift, sh.data(), sh.size() * sizeof(double));
+  m->c_norm = 1.0 / std::sqrt(m->cfg.avg_num_neighbors);
+  m->err_flag.ensure(sizeof(int));
+  // check the MLP kernels fit in LDS for this configuration
+  MlpArgs probe;
+  probe.d = d; probe.n = n; probe.w = m->twobody.view(); probe.head = m->head0.g; probe.head_bwd = m->head0T.g;
+  REQUIRE(mlp_lds_bytes(probe, prec, false) != (size_t)-1 && mlp_lds_bytes(probe, prec, true) != (size_t)-1,
+          "two-body MLP too wide for the fused kernel");
+  for (int L = 0; L < v.nl; ++L) {
+    MlpArgs q;
+    q.d = d; q.n = n; q.w = m->latent[L].view();
+    if (L + 1 < v.nl) { q.head = m->env2.g; q.head_bwd = m->env2T.g; }
+    REQUIRE(mlp_lds_bytes(q, prec, false) != (size_t)-1 && mlp_lds_bytes(q, prec, true) != (size_t)-1,
+            "latent MLP too wide for the fused kernel");
+  }
+}
+
+template <class T> T* ptr(const DevBuf& b, int64_t off = 0) { return b.as<T>() + off; }
+
+// Runs `launch` and, when timing is on, brackets it with events on `s`.
+template <class Fn>
+void timed(AllegroModel* m, const char* name, hipStream_t s, Fn launch) {
+  if (!m->timing) {
+    HIP_OK(launch());
+    return;
+  }
+  size_t k = 0;
+  while (k < m->ktimes.size() && m->ktimes[k].name != name) ++k;
+  if (k == m->ktimes.size()) {
+    m->ktimes.push_back({});
+    m->ktimes.back().name = name;
+  }
+  hipEvent_t a, b;
+  HIP_OK(hipEventCreate(&a));
+  HIP_OK(hipEventCreate(&b));
+  HIP_OK(hipEventRecord(a, s));
+  HIP_OK(launch());
+  HIP_OK(hipEventRecord(b, s));
+  m->pending.push_back({k, {a, b}});
+}
+
+void collect_times(AllegroModel* m) {
+  for (auto& p : m->pending) {
+    HIP_OK(hipEventSynchronize(p.second.second));
+    float ms = 0.0f;
+    HIP_OK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    m->ktimes[p.first].ms += ms;
+    m->ktimes[p.first].launches += 1;
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  m->pending.clear();
+}
+
+void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const double* pos, const int32_t* species,
+                    const double* cell, const int32_t* pbc, hipStream_t s, int64_t* n_edges) {
+  REQUIRE(n_local >= 0 && n_total >= n_local, "need 0 <= n_local <= n_total");
+  REQUIRE(pbc != nullptr, "pbc must not be NULL");
+  REQUIRE((pos && species) || n_total == 0, "pos and species must not be NULL");
+  REQUIRE(n_total < (int64_t)1 << 30, "at most 2^30 atoms");
+  const double rc = m->cfg.r_cut;
+  double L[3];
+  int pb[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    pb[ax] = pbc[ax] ? 1 : 0;
+    L[ax] = 0.0;
+    if (pb[ax]) {
+      REQUIRE(cell != nullptr, "cell must be given for periodic axes");
+      L[ax] = cell[4 * ax];
+      REQUIRE(std::isfinite(L[ax]) && L[ax] > 0, "periodic box lengths must be positive");
+    }
+  }
+  if (cell && (pb[0] || pb[1] || pb[2]))
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        if (r != c) REQUIRE(cell[3 * r + c] == 0.0, "only orthorhombic cells are supported");
+  m->n_local = n_local;
+  m->n_total = n_total;
+  for (int ax = 0; ax < 3; ++ax) m->L[ax] = L[ax];
+
+  NbrArgs a;
+  a.n_local = n_local; a.n_total = n_total; a.pos = pos; a.r_cut2 = rc * rc;
+  a.species = species; a.n_species = m->v.S;
+  for (int ax = 0; ax < 3; ++ax) { a.L[ax] = L[ax]; a.pbc[ax] = pb[ax]; }
+  const int64_t nt = std::max<int64_t>(n_total, 1);
+  // bounding box of the open axes
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  if (n_total > 0 && (!pb[0] || !pb[1] || !pb[2])) {
+    m->bbox.ensure(1024 * 6 * sizeof(double));
+    a.bbox = ptr<double>(m->bbox);
+    int nb = 0;
+    HIP_OK(launch_bbox(a, &nb, s));
+    std::vector<double> part((size_t)nb * 6);
+    HIP_OK(hipMemcpyAsync(part.data(), a.bbox, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int ax = 0; ax < 3; ++ax) { lo[ax] = 1e300; hi[ax] = -1e300; }
+    for (int b = 0; b < nb; ++b)
+      for (int ax = 0; ax < 3; ++ax) {
+        lo[ax] = std::min(lo[ax], part[b * 6 + ax]);
+        hi[ax] = std::max(hi[ax], part[b * 6 + 3 + ax]);
+      }
+    for (int ax = 0; ax < 3; ++ax)
+      if (!pb[ax]) {
+        if (!(std::isfinite(lo[ax]) && std::isfinite(hi[ax])))
+          throw Fail{ALLEGRO_E_NONFINITE, "non-finite positions"};
+      }
+  }
+  const double grow = rc * (1.0 + 1e-10) + 1e-12;
+  int64_t ncell = 1;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double span = pb[ax] ? L[ax] : (hi[ax] - lo[ax]);
+    int nc = (int)std::floor(span / grow);
+    nc = std::max(1, std::min(nc, 1024));
+    a.nc[ax] = nc;
+    a.h[ax] = pb[ax] ? L[ax] / nc : (span > 0 ? span / nc : 1.0);
+    a.lo[ax] = pb[ax] ? 0.0 : lo[ax];
+    // stencil half-width: every image within r_c lies within R cells
+    int R = (int)std::ceil(grow / a.h[ax]);
+    if (!pb[ax]) R = std::min(std::max(R, 1), nc);
+    a.R[ax] = std::max(1, R);
+    REQUIRE(!pb[ax] || a.R[ax] <= 64, "box too small for the cutoff (more than 64 images per axis)");
+    ncell *= nc;
+  }
+  m->cell_of.ensure(nt * 4); m->img.ensure(nt * 12); m->cell_count.ensure((ncell + 1) * 4);
+  m->cell_start.ensure((ncell + 1) * 4); m->cell_cursor.ensure((ncell + 1) * 4); m->cell_atoms.ensure(nt * 4);
+  m->count.ensure(std::max<int64_t>(n_local, 1) * 4); m->row_ptr.ensure((n_local + 1) * 4);
+  m->rcount.ensure(nt * 4); m->rcursor.ensure(nt * 4); m->rrow_ptr.ensure((nt + 1) * 4);
+  m->scan_tmp.ensure(exclusive_scan_tmp_bytes(std::max<int64_t>(std::max(nt, ncell), n_local) + 1));
+  a.cell_of = ptr<int32_t>(m->cell_of); a.img = ptr<int32_t>(m->img);
+  a.cell_count = ptr<int32_t>(m->cell_count); a.cell_start = ptr<int32_t>(m->cell_start);
+  a.cell_cursor = ptr<int32_t>(m->cell_cursor); a.cell_atoms = ptr<int32_t>(m->cell_atoms);
+  a.count = ptr<int32_t>(m->count); a.row_ptr = ptr<int32_t>(m->row_ptr);
+  a.rcount = ptr<int32_t>(m->rcount); a.rcursor = ptr<int32_t>(m->rcursor); a.rrow_ptr = ptr<int32_t>(m->rrow_ptr);
+  a.scan_tmp = m->scan_tmp.p;
+  int* err = ptr<int>(m->err_flag);
+  HIP_OK(hipMemsetAsync(err, 0, sizeof(int), s));
+  HIP_OK(launch_fill_i32(a.cell_count, 0, ncell, s));
+  HIP_OK(launch_fill_i32(a.cell_cursor, 0, ncell, s));
+  if (n_total > 0) HIP_OK(launch_bin_atoms_err(a, err, s));
+  HIP_OK(launch_exclusive_scan(a.cell_count, a.cell_start, ncell, a.scan_tmp, s));
+  if (n_total > 0) HIP_OK(launch_fill_cells(a, s));
+  HIP_OK(launch_count_neighbors(a, s));
+  HIP_OK(launch_exclusive_scan(a.count, a.row_ptr, n_local, a.scan_tmp, s));
+  m->h_row_ptr.resize(n_local + 1);
+  int herr = 0;
+  HIP_OK(hipMemcpyAsync(m->h_row_ptr.data(), a.row_ptr, (n_local + 1) * 4, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (herr & 2) throw Fail{ALLEGRO_E_NONFINITE, "non-finite positions"};
+  if (herr & 1) throw Fail{ALLEGRO_E_INVAL, "positions lie more than 500 box lengths outside the box"};
+  if (herr & 4) throw Fail{ALLEGRO_E_INVAL, "species out of range [0, n_species)"};
+  const int64_t E = m->h_row_ptr[n_local];
+  m->E = E;
+  const int64_t Ee = std::max<int64_t>(E, 1);
+  m->ei.ensure(Ee * 4); m->ej.ensure(Ee * 4); m->es.ensure(Ee * 12); m->keys.ensure(Ee * 8);
+  m->redge.ensure(Ee * 4);
+  a.keys = ptr<unsigned long long>(m->keys); a.ei = ptr<int32_t>(m->ei); a.ej = ptr<int32_t>(m->ej);
+  a.es = ptr<int32_t>(m->es); a.redge = ptr<int32_t>(m->redge);
+  HIP_OK(launch_fill_neighbors(a, s));
+  HIP_OK(launch_sort_neighbors(a, s));
+  HIP_OK(launch_fill_i32(a.rcount, 0, n_total, s));
+  HIP_OK(launch_fill_i32(a.rcursor, 0, n_total, s));
+  HIP_OK(launch_reverse_csr(a, E, s));
+
+  // chunks of whole centres and the workspace they need
+  const int64_t cap = m->cfg.edge_chunk > 0 ? m->cfg.edge_chunk : INT64_MAX;
+  m->chunk_c.assign(1, 0);
+  int64_t c = 0;
+  m->Ec = 0; m->Nc = 0;
+  while (c < n_local) {
+    int64_t b = c + 1;
+    while (b < n_local && m->h_row_ptr[b + 1] - m->h_row_ptr[c] <= cap) ++b;
+    m->Ec = std::max<int64_t>(m->Ec, m->h_row_ptr[b] - m->h_row_ptr[c]);
+    m->Nc = std::max<int64_t>(m->Nc, b - c);
+    m->chunk_c.push_back(b);
+    c = b;
+  }
+  {
+    std::vector<int32_t> crp;
+    m->chunk_rp_off.clear();
+    for (size_t k = 0; k + 1 < m->chunk_c.size(); ++k) {
+      m->chunk_rp_off.push_back((int64_t)crp.size());
+      const int64_t cA = m->chunk_c[k], cB = m->chunk_c[k + 1];
+      for (int64_t q = cA; q <= cB; ++q) crp.push_back((int32_t)(m->h_row_ptr[q] - m->h_row_ptr[cA]));
+    }
+    if (crp.empty()) crp.push_back(0);
+    upload(m->chunk_rp, crp.data(), crp.size() * sizeof(int32_t));
+  }
+  const Validated& v = m->v;
+  const int64_t Ec = std::max<int64_t>(m->Ec, 1), Nc = std::max<int64_t>(m->Nc, 1);
+  const size_t f = sizeof(float);
+  m->eb.ensure(Ec * kEB * f);
+  for (int L = 0; L < v.nl; ++L) m->x[L].ensure(Ec * v.d * f);
+  m->head0o.ensure(Ec * 2 * v.LW * f);
+  if (v.nl == 2) {
+    m->wenv2.ensure(Ec * v.LW * f);
+    m->V1.ensure(Ec * v.dim * v.n * f);
+    m->gw2.ensure(Ec * v.LW * f);
+    m->gT.ensure(Ec * v.dim * v.n * f);
+    m->gxb.ensure(Ec * v.d * f);
+    m->gs.ensure(Ec * v.n * f);
+  }
+  for (int L = 0; L < v.nl; ++L) m->gam[L].ensure(Nc * v.dim * v.n * f);
+  m->eij.ensure(Ec * f);
+  m->gxa.ensure(Ec * v.d * f);
+  m->gTf.ensure(Ec * v.n * f);
+  m->ghead0.ensure(Ec * 2 * v.LW * f);
+  m->gY.ensure(Ec * 9 * f);
+  m->gu.ensure(Ec * f);
+  m->gR.ensure(Ec * v.nb * f);
+  m->g_e.ensure(Ee * 3 * f);
+  m->atom_e.ensure(std::max<int64_t>(n_local, 1) * sizeof(double));
+  m->partial.ensure(((nt + 255) / 256) * 10 * sizeof(double));
+  if (n_edges) *n_edges = E;
+}
+
+void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* species, double* atom_energy,
+                        double* forces, double* virial, double* atom_virial, double* energy, hipStream_t s) {
+  if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
+  REQUIRE((pos && species && forces) || m->n_total == 0, "pos, species and forces must not be NULL");
+  const Validated& v = m->v;
+  const int prec = m->prec;
+  const int d = v.d, n = v.n, LW = v.LW, dim = v.dim;
+  double* aE = atom_energy ? atom_energy : ptr<double>(m->atom_e);
+  const int32_t* ei = ptr<int32_t>(m->ei);
+  const int32_t* ej = ptr<int32_t>(m->ej);
+  const int32_t* es = ptr<int32_t>(m->es);
+  for (size_t k = 0; k + 1 < m->chunk_c.size(); ++k) {
+    const int64_t cA = m->chunk_c[k], cB = m->chunk_c[k + 1];
+    const int64_t eA = m->h_row_ptr[cA], eB = m->h_row_ptr[cB];
+    const int E = (int)(eB - eA), nc = (int)(cB - cA);
+    // row pointers of the chunk's centres, relative to its first edge
+    const int32_t* drp = ptr<int32_t>(m->chunk_rp) + m->chunk_rp_off[k];
+
+    EdgeArgs ea;
+    ea.E = E; ea.pos = pos; ea.ei = ei + eA; ea.ej = ej + eA; ea.es = es + 3 * eA;
+    for (int ax = 0; ax < 3; ++ax) ea.L[ax] = m->L[ax];
+    ea.r_cut = m->cfg.r_cut; ea.p = v.p; ea.n_bessel = v.nb; ea.l_max = v.lmax;
+    ea.eb = ptr<float>(m->eb);
+    timed(m, "edge_basis", s, [&] { return launch_edge_basis(ea, s); });
+
+    MlpArgs base;
+    base.E = E; base.d = d; base.n = n; base.l_max = v.lmax; base.n_species = v.S; base.n_bessel = v.nb;
+    base.eb = ptr<float>(m->eb); base.ei = ei + eA; base.ej = ej + eA; base.species = species;
+    base.centre_base = (int)cA;
+
+    MlpArgs m0 = base;
+    m0.kind = kTwoBody; m0.w = m->twobody.view(); m0.head = m->head0.g; m0.head_bwd = m->head0T.g;
+    m0.x_out = ptr<float>(m->x[0]); m0.head_out = ptr<float>(m->head0o);
+    timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, prec, s); });
+
+    TensorArgs tb;
+    tb.E = E; tb.n_centres = nc; tb.n = n; tb.l_max = v.lmax; tb.row_ptr = drp; tb.ei = ei + eA;
+    tb.centre_base = (int)cA; tb.eb = ptr<float>(m->eb); tb.c_norm = (float)m->c_norm;
+    tb.channel_mix = m->cfg.channel_mix ? 1 : 0; tb.mix_scale = (float)(1.0 / std::sqrt((double)n));
+    tb.mix_stride = m->mix_stride;
+
+    TensorArgs t1 = tb;
+    t1.w_env = ptr<float>(m->head0o) + LW; t1.ld_w = 2 * LW; t1.gam = ptr<float>(m->gam[0]);
+    timed(m, "env", s, [&] { return launch_env(t1, s); });
+
+    const VSrc v_a0{ptr<float>(m->head0o), 2 * LW, 1};
+    const VSrc v_1{ptr<float>(m->V1), dim * n, 0};
+    MlpArgs mf = base;
+    mf.kind = kLatentFinal; mf.we = ptr<float>(m->we); mf.g_const = ptr<float>(m->gconst);
+    for (int k = 0; k < 9; ++k) mf.tp_w[k] = m->tp_final[k];
+    mf.eij = ptr<float>(m->eij);
+    MlpArgs m1 = base;
+    if (v.nl == 2) {
+      TensorArgs t1m = t1;
+      t1m.v = v_a0; t1m.tpw = ptr<float>(m->tpw[0]); t1m.mixB = m->mixF[0].p; t1m.v_out = ptr<float>(m->V1);
+      timed(m, "tp_mix", s, [&] { return launch_tp_mix(t1m, false, s); });
+      m1.kind = kLatent; m1.w = m->latent[0].view(); m1.head = m->env2.g; m1.head_bwd = m->env2T.g;
+      m1.x_prev = ptr<float>(m->x[0]); m1.s_in = ptr<float>(m->V1); m1.s_ld = dim * n;
+      m1.x_out = ptr<float>(m->x[1]); m1.head_out = ptr<float>(m->wenv2);
+      timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(m1, prec, s); });
+      TensorArgs t2 = tb;
+      t2.w_env = ptr<float>(m->wenv2); t2.ld_w = LW; t2.gam = ptr<float>(m->gam[1]);
+      timed(m, "env", s, [&] { return launch_env(t2, s); });
+      mf.w = m->latent[1].view(); mf.x_prev = ptr<float>(m->x[1]); mf.tp_v = v_1; mf.tp_gam = ptr<float>(m->gam[1]);
+    } else {
+      mf.w = m->latent[0].view(); mf.x_prev = ptr<float>(m->x[0]); mf.tp_v = v_a0; mf.tp_gam = ptr<float>(m->gam[0]);
+    }
+    timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, prec, s); });
+
+    ReduceArgs ra;
+    ra.n_centres = nc; ra.centre_base = (int)cA; ra.row_ptr = drp; ra.eij = ptr<float>(m->eij);
+    ra.species = species; ra.scale = ptr<double>(m->scale); ra.shift = ptr<double>(m->shift); ra.atom_energy = aE;
+    timed(m, "atom_energy", s, [&] { return launch_atom_energy(ra, s); });
+
+    // ---- adjoint ----
+    mf.g_xprev = ptr<float>(m->gxa); mf.g_s = ptr<float>(m->gTf); mf.g_u = ptr<float>(m->gu); mf.gu_accum = 0;
+    timed(m, "mlp_bwd_final", s, [&] { return launch_mlp_bwd(mf, prec, s); });
+
+    TensorArgs tf = tb;
+    tf.g_t = ptr<float>(m->gTf); tf.g_Y = ptr<float>(m->gY); tf.gy_accum = 0;
+    tf.tpw = ptr<float>(m->tpw[v.nl - 1]);
+    if (v.nl == 2) {
+      tf.v = v_1; tf.gam = ptr<float>(m->gam[1]); tf.w_env = ptr<float>(m->wenv2); tf.ld_w = LW;
+      tf.g_w = ptr<float>(m->gw2); tf.ld_gw = LW;
+    } else {
+      tf.v = v_a0; tf.gam = ptr<float>(m->gam[0]); tf.w_env = ptr<float>(m->head0o) + LW; tf.ld_w = 2 * LW;
+      tf.g_w = ptr<float>(m->ghead0) + LW; tf.ld_gw = 2 * LW; tf.g_a0 = ptr<float>(m->ghead0);
+    }
+    timed(m, "tp_env_adjoint_final", s, [&] { return launch_tp_env_adjoint(tf, true, s); });
+
+    float* gx_two = ptr<float>(m->gxa);
+    if (v.nl == 2) {
+      m1.g_head = ptr<float>(m->gw2); m1.g_x = ptr<float>(m->gxa); m1.g_xprev = ptr<float>(m->gxb);
+      m1.g_s = ptr<float>(m->gs); m1.g_u = ptr<float>(m->gu); m1.gu_accum = 1;
+      timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(m1, prec, s); });
+      TensorArgs tm = tb;
+      tm.g_tnext = ptr<float>(m->gTf); tm.gam_next = ptr<float>(m->gam[1]);
+      for (int k = 0; k < 9; ++k) tm.tp_wnext[k] = m->tp_final[k];
+      tm.g_s = ptr<float>(m->gs); tm.mixB = m->mixB[0].p; tm.g_tout = ptr<float>(m->gT);
+      timed(m, "mix_adjoint", s, [&] { return launch_mix_adjoint(tm, s); });
+      TensorArgs t1b = tb;
+      t1b.g_t = ptr<float>(m->gT); t1b.v = v_a0; t1b.gam = ptr<float>(m->gam[0]);
+      t1b.w_env = ptr<float>(m->head0o) + LW; t1b.ld_w = 2 * LW; t1b.tpw = ptr<float>(m->tpw[0]);
+      t1b.g_w = ptr<float>(m->ghead0) + LW; t1b.ld_gw = 2 * LW; t1b.g_a0 = ptr<float>(m->ghead0);
+      t1b.g_Y = ptr<float>(m->gY); t1b.gy_accum = 1;
+      timed(m, "tp_env_adjoint", s, [&] { return launch_tp_env_adjoint(t1b, false, s); });
+      gx_two = ptr<float>(m->gxb);
+    }
+    m0.g_head = ptr<float>(m->ghead0); m0.g_x = gx_two; m0.g_u = ptr<float>(m->gu); m0.gu_accum = 1;
+    m0.g_R = ptr<float>(m->gR);
+    timed(m, "mlp_bwd_twobody", s, [&] { return launch_mlp_bwd(m0, prec, s); });
+
+    ea.g_Y = ptr<float>(m->gY); ea.g_R = ptr<float>(m->gR); ea.g_u = ptr<float>(m->gu);
+    ea.g_e = ptr<float>(m->g_e) + 3 * eA;
+    timed(m, "edge_adjoint", s, [&] { return launch_edge_adjoint(ea, s); });
+  }
+  ForceArgs fa;
+  fa.n_total = m->n_total; fa.n_local = m->n_local; fa.pos = pos; fa.row_ptr = ptr<int32_t>(m->row_ptr);
+  fa.rrow_ptr = ptr<int32_t>(m->rrow_ptr); fa.redge = ptr<int32_t>(m->redge); fa.ei = ei; fa.ej = ej; fa.es = es;
+  for (int ax = 0; ax < 3; ++ax) fa.L[ax] = m->L[ax];
+  fa.g_e = ptr<float>(m->g_e); fa.forces = forces; fa.atom_virial = atom_virial;
+  fa.partial = ptr<double>(m->partial); fa.atom_energy = aE;
+  int nb = 0;
+  timed(m, "forces", s, [&] { return launch_forces(fa, &nb, s); });
+  if (virial || energy) timed(m, "final_sums", s, [&] { return launch_final_sums(fa.partial, nb, virial, energy, s); });
+}
+
+}  // namespace
+
+extern "C" {
+
+int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info) {
+  try {
+    const Validated v = validate(cfg);
+    if (info) {
+      info->n_weights = v.n_weights;
+      info->dim = v.dim;
+      info->latent = v.d;
+      for (int L = 0; L < 2; ++L) {
+        info->n_paths[L] = 0;
+        info->n_nonzero[L] = 0;
+      }
+      for (int L = 0; L < v.nl; ++L) {
+        const bool fin = L == v.nl - 1;
+        info->n_paths[L] = count_paths(v.lmax, fin);
+        info->n_nonzero[L] = tp_list(v.lmax, fin).n;
+      }
+    }
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(nullptr, f);
+  } catch (...) {
+    return fail(nullptr, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_create(const AllegroConfig* cfg, const float* weights, int64_t n_weights, const double* species_scale,
+                   const double* species_shift, AllegroModel** out) {
+  if (out) *out = nullptr;
+  AllegroModel* m = nullptr;
+  try {
+    REQUIRE(out != nullptr, "out is NULL");
+    const Validated v = validate(cfg);
+    m = new (std::nothrow) AllegroModel();
+    if (!m) throw Fail{ALLEGRO_E_NOMEM, "host allocation failed"};
+    m->cfg = *cfg;
+    m->v = v;
+    m->prec = cfg->precision;
+    create_impl(m, weights, n_weights, species_scale, species_shift);
+    *out = m;
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    delete m;
+    return fail(nullptr, f);
+  } catch (const std::bad_alloc&) {
+    delete m;
+    return fail(nullptr, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
+  } catch (...) {
+    delete m;
+    return fail(nullptr, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_neighbors(AllegroModel* m, int64_t n_local, int64_t n_total, const double* pos, const int32_t* species,
+                      const double* cell, const int32_t* pbc, void* stream, int64_t* n_edges) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    neighbors_impl(m, n_local, n_total, pos, species, cell, pbc, (hipStream_t)stream, n_edges);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    m->n_local = -1;
+    return fail(m, f);
+  } catch (const std::bad_alloc&) {
+    m->n_local = -1;
+    return fail(m, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
+  } catch (...) {
+    m->n_local = -1;
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* species, double* atom_energy,
+                          double* forces, double* virial, double* atom_virial, double* energy, void* stream) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    energy_forces_impl(m, pos, species, atom_energy, forces, virial, atom_virial, energy, (hipStream_t)stream);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  } catch (const std::bad_alloc&) {
+    return fail(m, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
+  } catch (...) {
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_copy_edges(AllegroModel* m, int32_t* centre, int32_t* neighbor, int32_t* shift, void* stream) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
+    hipStream_t s = (hipStream_t)stream;
+    if (m->E > 0) {
+      if (centre) HIP_OK(hipMemcpyAsync(centre, m->ei.p, m->E * 4, hipMemcpyDeviceToDevice, s));
+      if (neighbor) HIP_OK(hipMemcpyAsync(neighbor, m->ej.p, m->E * 4, hipMemcpyDeviceToDevice, s));
+      if (shift) HIP_OK(hipMemcpyAsync(shift, m->es.p, m->E * 12, hipMemcpyDeviceToDevice, s));
+    }
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  }
+}
+
+int64_t allegro_num_edges(const AllegroModel* m) { return m ? m->E : -1; }
+
+int allegro_set_timing(AllegroModel* m, int32_t enable) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    collect_times(m);
+    m->ktimes.clear();
+    m->timing = enable != 0;
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  }
+}
+
+int allegro_kernel_times(AllegroModel* m, int32_t max_entries, char* names, double* total_ms, int64_t* launches,
+                         int32_t* n_entries) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    collect_times(m);
+    const int n = (int)m->ktimes.size();
+    if (n_entries) *n_entries = n;
+    for (int k = 0; k < n && k < max_entries; ++k) {
+      if (names) {
+        std::memset(names + 48 * k, 0, 48);
+        std::strncpy(names + 48 * k, m->ktimes[k].name.c_str(), 47);
+      }
+      if (total_ms) total_ms[k] = m->ktimes[k].ms;
+      if (launches) launches[k] = m->ktimes[k].launches;
+    }
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  }
+}
+
+int64_t allegro_workspace_bytes(const AllegroModel* m) {
+  if (!m) return -1;
+  const DevBuf* bufs[] = {&m->ei, &m->ej, &m->es, &m->row_ptr, &m->rrow_ptr, &m->redge, &m->keys, &m->cell_of,
+                          &m->img, &m->cell_count, &m->cell_start, &m->cell_cursor, &m->cell_atoms, &m->count,
+                          &m->rcount, &m->rcursor, &m->bbox, &m->scan_tmp, &m->eb, &m->x[0], &m->x[1],
+                          &m->head0o, &m->wenv2, &m->V1, &m->gam[0], &m->gam[1], &m->eij, &m->gxa, &m->gxb,
+                          &m->gTf, &m->gs, &m->ghead0, &m->gw2, &m->gT, &m->gY, &m->gu, &m->gR, &m->g_e,
+                          &m->atom_e, &m->partial, &m->chunk_rp};
+  int64_t s = 0;
+  for (const DevBuf* b : bufs) s += (int64_t)b->bytes;
+  return s;
+}
+
+void allegro_destroy(AllegroModel* m) {
+  if (!m) return;
+  for (auto& p : m->pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  delete m;
+}
+
+const char* allegro_last_error(const AllegroModel* m) {
+  if (m) return m->err.c_str();
+  return g_create_error.c_str();
+}
+
+const char* allegro_status_string(int status) {
+  switch (status) {
+    case ALLEGRO_OK: return "ALLEGRO_OK";
+    case ALLEGRO_E_INVAL: return "ALLEGRO_E_INVAL";
+    case ALLEGRO_E_NOMEM: return "ALLEGRO_E_NOMEM";
+    case ALLEGRO_E_CAPACITY: return "ALLEGRO_E_CAPACITY";
+    case ALLEGRO_E_DEVICE: return "ALLEGRO_E_DEVICE";
+    case ALLEGRO_E_NONFINITE: return "ALLEGRO_E_NONFINITE";
+    case ALLEGRO_E_STATE: return "ALLEGRO_E_STATE";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

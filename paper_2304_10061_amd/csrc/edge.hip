@@ -1,0 +1,233 @@
+// edge.hip - per-edge basis and its adjoint, per-atom energies, forces and the
+// virial.
+//
+// Edge basis (section "Training details": 8 Bessel functions times a
+// polynomial cutoff envelope; section "Allegro: Scalable Equivariant Deep
+// Learning": spherical harmonics of the edge direction, full O(3)).  Forms:
+//   u(t) = 1 - (p+1)(p+2)/2 t^p + p(p+2) t^(p+1) - p(p+1)/2 t^(p+2),  t = d / r_c
+//   R_n  = sqrt(2/r_c) sin(n pi d / r_c) / d * u,   n = 1..n_bessel
+//   Y    = real harmonics with sum_m Y_lm^2 = 2l+1:
+//          1;  sqrt3 (y, z, x);  sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2-1), sqrt15 xz, sqrt15/2 (x^2-y^2)
+// The edge vector r = (x_j - x_i) + s L is formed in FP64 and then rounded to
+// FP32; the basis is FP32.
+//
+// Energies (section "Allegro: Scalable Equivariant Deep Learning", first
+// equation; section "Mixed-precision calculations": shifting, scaling and
+// summation of atomic energies in double precision): E_i is the FP32 sum of
+// its pair energies, A_i = sigma_Z E_i + mu_Z and E = sum A_i in FP64.
+//
+// Forces from edge gradients g_e = dE/dr_e:  F_k = sum_{e from k} g_e -
+// sum_{e to k} g_e, gathered per atom through the CSR and the reverse CSR (no
+// atomics, so results are bit-reproducible); virial W = -sum_e r_e (x) g_e in
+// FP64 with half of each edge term assigned to each end.
+#include "devutil.h"
+#include "internal.h"
+
+namespace allegro {
+
+namespace {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kS3 = 1.7320508075688772f;
+constexpr float kS5 = 2.23606797749979f;
+constexpr float kS15 = 3.872983346207417f;
+
+__device__ __forceinline__ void sh9(float x, float y, float z, float* Y) {
+  Y[0] = 1.0f;
+  Y[1] = kS3 * y; Y[2] = kS3 * z; Y[3] = kS3 * x;
+  Y[4] = kS15 * x * y; Y[5] = kS15 * y * z; Y[6] = 0.5f * kS5 * (3.0f * z * z - 1.0f);
+  Y[7] = kS15 * x * z; Y[8] = 0.5f * kS15 * (x * x - y * y);
+}
+
+__device__ __forceinline__ float ipow(float t, int p) {
+  float r = 1.0f;
+  for (int k = 0; k < p; ++k) r *= t;
+  return r;
+}
+
+__device__ __forceinline__ void edge_vector(const EdgeArgs& a, int64_t e, double* r) {
+  const int i = a.ei[e], j = a.ej[e];
+  for (int ax = 0; ax < 3; ++ax)
+    r[ax] = (a.pos[3 * j + ax] - a.pos[3 * i + ax]) + (double)a.es[3 * e + ax] * a.L[ax];
+}
+
+__global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= a.E) return;
+  double r[3];
+  edge_vector(a, e, r);
+  const double dd = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  const float d = (float)dd;
+  const float x = (float)(r[0] / dd), y = (float)(r[1] / dd), z = (float)(r[2] / dd);
+  const float rc = (float)a.r_cut;
+  const float t = d / rc;
+  const int p = a.p;
+  const float tp = ipow(t, p);
+  const float u = 1.0f - 0.5f * (p + 1) * (p + 2) * tp + (float)(p * (p + 2)) * tp * t -
+                  0.5f * p * (p + 1) * tp * t * t;
+  float* o = a.eb + e * kEB;
+  float Y[9];
+  sh9(x, y, z, Y);
+  const int dim = (a.l_max + 1) * (a.l_max + 1);
+  for (int c = 0; c < 9; ++c) o[c] = c < dim ? Y[c] : 0.0f;
+  o[kEB_U] = u;
+  o[kEB_D] = d;
+  o[kEB_RHAT] = x; o[kEB_RHAT + 1] = y; o[kEB_RHAT + 2] = z;
+  o[14] = 0.0f; o[15] = 0.0f;
+  const float pref = sqrtf(2.0f / rc);
+  for (int k = 0; k < 16; ++k) {
+    float v = 0.0f;
+    if (k < a.n_bessel) v = pref * sinf((float)(k + 1) * kPi * d / rc) / d * u;
+    o[kEB_R + k] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= a.E) return;
+  const float* o = a.eb + e * kEB;
+  const float d = o[kEB_D], u = o[kEB_U];
+  const float x = o[kEB_RHAT], y = o[kEB_RHAT + 1], z = o[kEB_RHAT + 2];
+  const float rc = (float)a.r_cut;
+  const float t = d / rc;
+  const int p = a.p;
+  // du/dd = -(p(p+1)(p+2)/2) t^(p-1) (1-t)^2 / r_c
+  const float omt = 1.0f - t;
+  const float du = -0.5f * (float)(p * (p + 1) * (p + 2)) * ipow(t, p - 1) * omt * omt / rc;
+  const float pref = sqrtf(2.0f / rc);
+  float gu = a.g_u[e];
+  float gd = 0.0f;
+  for (int k = 0; k < a.n_bessel; ++k) {
+    const float w = (float)(k + 1) * kPi / rc;
+    float sn, cs;
+    sincosf(w * d, &sn, &cs);
+    const float B = pref * sn / d;
+    const float dB = pref * (w * cs / d - sn / (d * d));
+    const float gR = a.g_R[e * a.n_bessel + k];
+    gu += gR * B;
+    gd += gR * dB * u;
+  }
+  gd += gu * du;
+  const float* gY = a.g_Y + e * 9;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  if (a.l_max >= 1) {
+    gx += kS3 * gY[3]; gy += kS3 * gY[1]; gz += kS3 * gY[2];
+  }
+  if (a.l_max >= 2) {
+    gx += kS15 * (y * gY[4] + z * gY[7] + x * gY[8]);
+    gy += kS15 * (x * gY[4] + z * gY[5] - y * gY[8]);
+    gz += kS15 * (y * gY[5] + x * gY[7]) + 3.0f * kS5 * z * gY[6];
+  }
+  const float dot = gx * x + gy * y + gz * z;
+  const float inv = 1.0f / d;
+  float* g = a.g_e + 3 * e;
+  g[0] = gd * x + (gx - dot * x) * inv;
+  g[1] = gd * y + (gy - dot * y) * inv;
+  g[2] = gd * z + (gz - dot * z) * inv;
+}
+
+__global__ __launch_bounds__(256) void k_atom_energy(ReduceArgs a) {
+  const int lane = lane_id();
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= a.n_centres) return;
+  float s = 0.0f;
+  for (int e = a.row_ptr[c] + lane; e < a.row_ptr[c + 1]; e += kWave) s += a.eij[e];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int g = a.centre_base + c;
+    const int z = a.species[g];   // validated by the neighbour build
+    a.atom_energy[g] = a.scale[z] * (double)s + a.shift[z];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
+  __shared__ double red[10][256];
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double av[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double en = 0.0;
+  if (k < a.n_total) {
+    float f[3] = {0.0f, 0.0f, 0.0f};
+    auto add_edge = [&](int e, float sign) {
+      const float* g = a.g_e + 3 * (int64_t)e;
+      const int i = a.ei[e], j = a.ej[e];
+      double r[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        f[ax] += sign * g[ax];
+        r[ax] = (a.pos[3 * j + ax] - a.pos[3 * i + ax]) + (double)a.es[3 * (int64_t)e + ax] * a.L[ax];
+      }
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) av[3 * p + q] -= 0.5 * r[p] * (double)g[q];
+    };
+    if (k < a.n_local)
+      for (int e = a.row_ptr[k]; e < a.row_ptr[k + 1]; ++e) add_edge(e, 1.0f);
+    for (int q = a.rrow_ptr[k]; q < a.rrow_ptr[k + 1]; ++q) add_edge(a.redge[q], -1.0f);
+    for (int ax = 0; ax < 3; ++ax) a.forces[3 * k + ax] = (double)f[ax];
+    if (a.atom_virial)
+      for (int q = 0; q < 9; ++q) a.atom_virial[9 * k + q] = av[q];
+    if (k < a.n_local) en = a.atom_energy[k];
+  }
+  for (int q = 0; q < 9; ++q) red[q][threadIdx.x] = av[q];
+  red[9][threadIdx.x] = en;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 10; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 10) a.partial[blockIdx.x * 10 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_final_sums(const double* __restrict__ part, int nb,
+                                                    double* __restrict__ virial,
+                                                    double* __restrict__ energy) {
+  __shared__ double red[10][256];
+  double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += 256)
+    for (int q = 0; q < 10; ++q) acc[q] += part[b * 10 + q];
+  for (int q = 0; q < 10; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < 10; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 9 && virial) virial[threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x == 9 && energy) *energy = red[9][0];
+}
+
+inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_edge_basis(const EdgeArgs& a, hipStream_t s) {
+  if (a.E <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_basis, dim3(blocks(a.E, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_edge_adjoint(const EdgeArgs& a, hipStream_t s) {
+  if (a.E <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_adjoint, dim3(blocks(a.E, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_atom_energy(const ReduceArgs& a, hipStream_t s) {
+  if (a.n_centres <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_atom_energy, dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_forces(const ForceArgs& a, int* n_blocks, hipStream_t s) {
+  const int nb = (int)blocks(a.n_total > 0 ? a.n_total : 1, 256);
+  *n_blocks = nb;
+  hipLaunchKernelGGL(k_forces, dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_sums(const double* partial, int n_blocks, double* virial, double* energy,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_final_sums, dim3(1), dim3(256), 0, s, partial, n_blocks, virial, energy);
+  return hipGetLastError();
+}
+
+}  // namespace allegro

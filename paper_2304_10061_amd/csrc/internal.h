@@ -1,0 +1,225 @@
+// internal.h - data layouts and kernel entry points shared by the host runtime
+// (abi.cpp) and the gfx950 kernels (*.hip).  Not part of the public interface.
+//
+// Edge-major layouts in HBM (E = edges of the current chunk, rows ordered by
+// centre, each centre's neighbours sorted by (j, shift)):
+//   eb      [E][kEB]     float  edge record: Y[0..8], u, d, rhat[3], R[16..31]
+//   x^L     [E][d]       float  latent (scalar-track) features, the residual stream
+//   head    [E][H]       float  outputs of the linear map that follows an MLP
+//                               (after the two-body MLP: [a0 | w^1], each
+//                               (l_max+1) n wide, column l n + u)
+//   V^L     [E][dim][n]  float  tensor features, component-major: the n channels
+//                               of one strided component are contiguous
+//   Gamma^L [N][dim][n]  float  per-centre environment sums
+// dim = (l_max+1)^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace allegro {
+
+constexpr int kEB = 32;     // floats per edge record
+constexpr int kEB_U = 9;
+constexpr int kEB_D = 10;
+constexpr int kEB_RHAT = 11;
+constexpr int kEB_R = 16;   // radial basis R_n = B_n u, n < 16
+
+constexpr int kMaxMlpLayers = 3;
+
+// Packed MFMA B operand of a K x N matrix (y = x @ W): fragments
+// [Np/16][Kp/32][64 lanes][8 elements]; lane l of fragment (nt, kb) holds
+// rows k = 32 kb + 8 (l / 16) + 0..7 of column n = 16 nt + l % 16 (zero padded).
+struct GemmB {
+  const void* p = nullptr;
+  int K = 0, N = 0, Kp = 0, Np = 0;
+};
+
+struct MlpW {
+  int nl = 0;
+  GemmB fwd[kMaxMlpLayers];
+  GemmB bwd[kMaxMlpLayers];   // packed W^T (for input gradients)
+};
+
+enum MlpKind { kTwoBody = 0, kLatent = 1, kLatentFinal = 2 };
+
+// Where a tensor-product input V[e][a][u] comes from.
+struct VSrc {
+  const float* p = nullptr;   // stored V [E][dim][n]  or  a0 (head columns 0..(l_max+1)n)
+  int ld = 0;                 // row stride (floats)
+  int from_a0 = 0;            // V[a][u] = a0[l(a) n + u] * Y[a]
+};
+
+struct MlpArgs {
+  int E = 0;                  // rows of this launch
+  int kind = 0;
+  int d = 0, n = 0, l_max = 0, n_species = 0, n_bessel = 0;
+  MlpW w;
+  GemmB head;                 // forward head (none when head.p == nullptr)
+  GemmB head_bwd;             // its transpose (backward)
+  const float* eb = nullptr;
+  const int32_t* ei = nullptr;  // centre of each edge (global atom index)
+  int centre_base = 0;          // first centre of the chunk (Gamma rows are chunk-local)
+  const int32_t* ej = nullptr;  // neighbour of each edge (global atom index)
+  const int32_t* species = nullptr;  // [n_total]
+  // latent inputs
+  const float* x_prev = nullptr;  // [E][d]
+  const float* s_in = nullptr;    // non-final: V^L (component 0 = first n floats), row stride s_ld
+  int s_ld = 0;
+  // final layer: scalar tensor-product outputs computed in the prologue
+  VSrc tp_v;
+  const float* tp_gam = nullptr;  // Gamma [centres][dim][n]
+  float tp_w[9] = {0};            // diagonal coupling weight of each component
+  float res_scale = 0.70710678118654752f;
+  // forward outputs
+  float* x_out = nullptr;         // [E][d]
+  float* head_out = nullptr;      // [E][head.N]
+  float* eij = nullptr;           // final: [E]
+  const float* we = nullptr;      // final: folded edge-energy vector [d]
+  // backward inputs / outputs
+  const float* g_head = nullptr;  // [E][head.N]
+  const float* g_x = nullptr;     // [E][d] gradient w.r.t. x_out (partial)
+  const float* g_const = nullptr; // final: [n_species][d] = sigma_Z * we
+  float* g_xprev = nullptr;       // [E][d]
+  float* g_s = nullptr;           // [E][n]
+  float* g_u = nullptr;           // [E]
+  int gu_accum = 0;
+  float* g_R = nullptr;           // two-body: [E][n_bessel]
+};
+
+struct EdgeArgs {
+  int64_t E = 0;
+  const double* pos = nullptr;
+  const int32_t* ei = nullptr;    // global centre index
+  const int32_t* ej = nullptr;
+  const int32_t* es = nullptr;    // [E][3]
+  double L[3] = {0, 0, 0};        // periodic lengths (0 = open axis)
+  double r_cut = 0;
+  int p = 6, n_bessel = 8, l_max = 2;
+  float* eb = nullptr;
+  // backward
+  const float* g_Y = nullptr;     // [E][9]
+  const float* g_R = nullptr;     // [E][n_bessel]
+  const float* g_u = nullptr;     // [E]
+  float* g_e = nullptr;           // [E][3]
+};
+
+struct TensorArgs {
+  int E = 0;                      // edges of the chunk
+  int n_centres = 0;
+  int n = 0, l_max = 0;
+  const int32_t* row_ptr = nullptr;  // [n_centres+1], chunk-relative
+  const int32_t* ei = nullptr;       // centre per edge (global atom index)
+  int centre_base = 0;               // first centre of the chunk
+  const float* eb = nullptr;
+  const float* w_env = nullptr;   // [E][(l_max+1) n] at row stride ld_w
+  int ld_w = 0;
+  float c_norm = 1.0f;
+  float* gam = nullptr;           // [n_centres][dim][n]
+  VSrc v;                         // tensor-product input
+  const float* tpw = nullptr;     // device: non-zero weights of the fused table
+  const void* mixB = nullptr;     // packed FP32 mixing matrices, one GemmB block per l
+  int mix_stride = 0;             // floats between consecutive l blocks
+  int channel_mix = 1;
+  float mix_scale = 1.0f;         // 1/sqrt(n)
+  float* v_out = nullptr;         // [E][dim][n]
+  // backward
+  const float* g_t = nullptr;     // [E][dout][n]
+  const float* g_s = nullptr;     // [E][n] gradient w.r.t. scalar outputs (component 0)
+  const float* gam_next = nullptr;  // final layer Gamma (to rebuild dE/dV)
+  const float* g_tnext = nullptr;   // final-layer dE/dT [E][n]
+  float tp_wnext[9] = {0};
+  float* g_tout = nullptr;        // [E][dim][n]
+  float* g_w = nullptr;           // [E][(l_max+1) n] at row stride ld_gw
+  int ld_gw = 0;
+  float* g_a0 = nullptr;          // [E][(l_max+1) n] at row stride ld_gw (layer 1 only)
+  float* g_Y = nullptr;           // [E][9]
+  int gy_accum = 0;
+};
+
+// Kernel launchers (each returns hipSuccess or the launch error).
+hipError_t launch_edge_basis(const EdgeArgs& a, hipStream_t s);
+hipError_t launch_edge_adjoint(const EdgeArgs& a, hipStream_t s);
+hipError_t launch_mlp_fwd(const MlpArgs& a, int prec, hipStream_t s);
+hipError_t launch_mlp_bwd(const MlpArgs& a, int prec, hipStream_t s);
+size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd);
+hipError_t launch_env(const TensorArgs& a, hipStream_t s);
+hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s);
+hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s);
+hipError_t launch_tp_env_adjoint(const TensorArgs& a, bool final_layer, hipStream_t s);
+
+struct ReduceArgs {
+  int n_centres = 0;              // centres of the chunk
+  int centre_base = 0;            // global index of the chunk's first centre
+  const int32_t* row_ptr = nullptr;  // chunk-relative [n_centres+1]
+  const float* eij = nullptr;
+  const int32_t* species = nullptr;
+  const double* scale = nullptr;
+  const double* shift = nullptr;
+  double* atom_energy = nullptr;  // global [n_local]
+};
+hipError_t launch_atom_energy(const ReduceArgs& a, hipStream_t s);
+
+struct ForceArgs {
+  int64_t n_total = 0, n_local = 0;
+  const double* pos = nullptr;
+  const int32_t* row_ptr = nullptr;   // [n_local+1]
+  const int32_t* rrow_ptr = nullptr;  // [n_total+1] reverse CSR (edges by neighbour)
+  const int32_t* redge = nullptr;     // [E] edge ids grouped by neighbour, ascending
+  const int32_t* ei = nullptr;
+  const int32_t* ej = nullptr;
+  const int32_t* es = nullptr;
+  double L[3] = {0, 0, 0};
+  const float* g_e = nullptr;
+  double* forces = nullptr;
+  double* atom_virial = nullptr;      // may be null
+  double* partial = nullptr;          // [n_blocks][10]  (virial 9 + energy 1)
+  const double* atom_energy = nullptr;
+};
+hipError_t launch_forces(const ForceArgs& a, int* n_blocks, hipStream_t s);
+hipError_t launch_final_sums(const double* partial, int n_blocks, double* virial, double* energy,
+                             hipStream_t s);
+
+struct NbrArgs {
+  int64_t n_local = 0, n_total = 0;
+  const double* pos = nullptr;
+  const int32_t* species = nullptr;
+  int n_species = 0;
+  double L[3] = {0, 0, 0};
+  int pbc[3] = {0, 0, 0};
+  double lo[3] = {0, 0, 0};       // grid origin (open axes)
+  double h[3] = {1, 1, 1};        // cell size
+  int nc[3] = {1, 1, 1};          // cells per axis
+  int R[3] = {1, 1, 1};           // stencil half-width per axis
+  double r_cut2 = 0;
+  int32_t* cell_of = nullptr;     // [n_total]
+  int32_t* img = nullptr;         // [n_total][3] image index q (x = x_wrapped + q L)
+  int32_t* cell_count = nullptr;  // [n_cells]
+  int32_t* cell_start = nullptr;  // [n_cells+1]
+  int32_t* cell_cursor = nullptr; // [n_cells]
+  int32_t* cell_atoms = nullptr;  // [n_total]
+  int32_t* count = nullptr;       // [n_local]
+  int32_t* row_ptr = nullptr;     // [n_local+1]
+  unsigned long long* keys = nullptr;  // [E] unsorted candidate keys
+  int32_t* ei = nullptr;
+  int32_t* ej = nullptr;
+  int32_t* es = nullptr;
+  int32_t* rcount = nullptr;      // [n_total]
+  int32_t* rrow_ptr = nullptr;    // [n_total+1]
+  int32_t* rcursor = nullptr;     // [n_total]
+  int32_t* redge = nullptr;       // [E]
+  double* bbox = nullptr;         // [n_blocks][6] partial min/max
+  void* scan_tmp = nullptr;       // exclusive_scan_tmp_bytes(max(n_total, n_cells))
+};
+hipError_t launch_bbox(const NbrArgs& a, int* n_blocks, hipStream_t s);
+hipError_t launch_bin_atoms_err(const NbrArgs& a, int* err, hipStream_t s);
+hipError_t launch_fill_cells(const NbrArgs& a, hipStream_t s);
+hipError_t launch_count_neighbors(const NbrArgs& a, hipStream_t s);
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t s);
+size_t exclusive_scan_tmp_bytes(int64_t n);
+hipError_t launch_fill_neighbors(const NbrArgs& a, hipStream_t s);
+hipError_t launch_sort_neighbors(const NbrArgs& a, hipStream_t s);
+hipError_t launch_reverse_csr(const NbrArgs& a, int64_t E, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace allegro

@@ -1,0 +1,289 @@
+"""Parity of the HIP path (through the C interface) with the FP64 oracle.
+
+Tolerances (FP64 oracle as reference):
+  neighbour lists     bit-exact (i, j, shift) arrays
+  FP32 path           |E - E_ref| / N <= 1e-6 eV/atom, max |F - F_ref| <= 1e-4 eV/A
+  BF16-mixed path     |E - E_ref| / N <= 1e-3 eV/atom, RMS(F - F_ref) <= 1% of RMS(F_ref)
+Inputs are the seeded synthetic workloads; the oracle never sees GPU output.
+"""
+import copy
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2304_10061_amd as P
+import workloads as W
+from oracle import model as OM
+from oracle.neighbors import neighbor_list
+
+from gpu_helpers import gpu_edges, gpu_eval, gpu_model, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP32, BF16 = P.PREC_FP32, P.PREC_BF16
+
+
+def _report(tag, **kw):
+    print(tag, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _check_fp32(tag, got, ref, n):
+    dE = abs(float(got["energy"][0]) - ref.energy) / n
+    dF = float(np.abs(got["forces"] - ref.forces).max())
+    dEi = float(np.abs(got["atom_energy"] - ref.atom_energy).max())
+    dW = float(np.abs(got["virial"].reshape(3, 3) - ref.virial).max())
+    _report(tag, dE_per_atom=dE, max_dF=dF, max_dEi=dEi, max_dW=dW, Frms=float(np.sqrt((ref.forces ** 2).mean())))
+    assert dE <= 1e-6
+    assert dF <= 1e-4
+    assert dW <= 1e-4 * max(1.0, float(np.abs(ref.virial).max()))
+
+
+def _check_bf16(tag, got, ref, n):
+    dE = abs(float(got["energy"][0]) - ref.energy) / n
+    rel = float(np.sqrt(((got["forces"] - ref.forces) ** 2).mean()) / np.sqrt((ref.forces ** 2).mean()))
+    _report(tag, dE_per_atom=dE, force_rel_rms=rel)
+    assert dE <= 1e-3
+    assert rel <= 0.01
+
+
+# ----------------------------------------------------------------------------- neighbours
+
+def _nbr_cases():
+    mc1, s1 = W.model_config(1), W.system(1)
+    cases = [("cfg1", s1, 4.0), ("cfg2", W.system(2), 4.0)]
+    g = W.ghost_shell(s1, 6.0)
+    cases.append(("cfg1_ghosts", g, 4.0))
+    un = copy.copy(s1)
+    pos = s1.pos.copy()
+    pos[::3] += np.array([8.6, -17.2, 25.8])        # unwrapped images of the same atoms
+    un.pos = pos
+    cases.append(("unwrapped", un, 4.0))
+    tiny = W.System(pos=np.array([[0.5, 1.0, 2.0], [2.9, 0.1, 0.4], [1.5, 1.5, 1.5]]),
+                    species=np.array([0, 1, 0], dtype=np.int32), cell=np.array([3.0, 3.0, 3.0]),
+                    pbc=np.ones(3, np.int32), n_local=3)
+    cases.append(("box_smaller_than_cutoff", tiny, 4.5))
+    tie = W.System(pos=np.array([[1.0, 1.0, 1.0], [5.0, 1.0, 1.0], [1.0, 4.5, 1.0], [17.25, 1.0, 1.0]]),
+                   species=np.zeros(4, np.int32), cell=np.array([20.0, 20.0, 20.0]),
+                   pbc=np.ones(3, np.int32), n_local=4)
+    cases.append(("exact_ties", tie, 4.0))
+    mixed = copy.copy(W.system(2))
+    mixed.pbc = np.array([1, 1, 0], np.int32)
+    cases.append(("mixed_pbc", mixed, 4.0))
+    cl = W.clusters(6, 11)
+    cases.append(("clusters", cl, 4.0))
+    ghosts_only_local = copy.copy(g)
+    ghosts_only_local.n_local = 10
+    cases.append(("few_centres", ghosts_only_local, 4.0))
+    return cases
+
+
+@pytest.mark.parametrize("case", _nbr_cases(), ids=lambda c: c[0])
+def test_neighbors_bit_exact(case):
+    name, s, rc = case
+    mc = W.ModelConfig(n_species=2, r_cut=rc, l_max=1, n_layers=1, n_tensor=8,
+                       twobody_dims=(32, 32), latent_dims=(32, 32))
+    w = W.make_weights(mc, np.random.default_rng(0))
+    m = gpu_model(mc, w, FP32)
+    i, j, sh = gpu_edges(m, s)
+    ri, rj, rs = neighbor_list(s.pos, s.cell, s.pbc, rc, n_local=s.n_local)
+    _report(name, edges=len(ri))
+    assert np.array_equal(i, ri) and np.array_equal(j, rj) and np.array_equal(sh, rs)
+
+
+def test_neighbors_bit_exact_protein_box():
+    mc = W.model_config(3)
+    s = W.system(3)
+    m = gpu_model(mc, W.make_weights(mc, np.random.default_rng(0)), BF16)
+    i, j, sh = gpu_edges(m, s)
+    ri, rj, rs = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="kdtree")
+    _report("cfg3", edges=len(ri), per_atom=len(ri) / s.n_local)
+    assert np.array_equal(i, ri) and np.array_equal(j, rj) and np.array_equal(sh, rs)
+
+
+# ----------------------------------------------------------------------------- energies/forces
+
+@pytest.fixture(scope="module")
+def cfg2():
+    mc, s, w = W.workload(2)
+    sc, sh = W.species_scale_shift(mc, np.random.default_rng(21))
+    ref = OM.evaluate(mc, w, s, sc, sh)
+    return mc, s, w, sc, sh, ref
+
+
+def test_fp32_water_box(cfg2):
+    mc, s, w, sc, sh, ref = cfg2
+    m = gpu_model(mc, w, FP32, sc, sh)
+    got = gpu_eval(m, s)
+    _check_fp32("cfg2_fp32", got, ref, s.n_local)
+    assert np.allclose(got["atom_virial"].reshape(-1, 3, 3).sum(0), got["virial"].reshape(3, 3), atol=1e-8)
+    assert np.abs(got["atom_energy"] - ref.atom_energy).max() < 1e-5
+
+
+def test_bf16_water_box(cfg2):
+    mc, s, w, sc, sh, ref = cfg2
+    m = gpu_model(mc, w, BF16, sc, sh)
+    got = gpu_eval(m, s)
+    _check_bf16("cfg2_bf16", got, ref, s.n_local)
+
+
+def test_chunked_equals_whole(cfg2):
+    mc, s, w, sc, sh, ref = cfg2
+    a = gpu_eval(gpu_model(mc, w, FP32, sc, sh), s)
+    b = gpu_eval(gpu_model(mc, w, FP32, sc, sh, edge_chunk=9000), s)
+    assert np.array_equal(a["forces"], b["forces"])
+    assert np.array_equal(a["atom_energy"], b["atom_energy"])
+
+
+def test_repeatable_bitwise(cfg2):
+    mc, s, w, sc, sh, ref = cfg2
+    m = gpu_model(mc, w, BF16, sc, sh)
+    a, b = gpu_eval(m, s), gpu_eval(m, s)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+SMALL = [
+    ("one_layer_lmax1", dict(l_max=1, n_layers=1, n_tensor=8, twobody_dims=(32, 32), latent_dims=(32, 32))),
+    ("two_layer_lmax1_n16", dict(l_max=1, n_layers=2, n_tensor=16, twobody_dims=(64,), latent_dims=(64,))),
+    ("no_channel_mix", dict(l_max=2, n_layers=2, n_tensor=32, twobody_dims=(64, 64), latent_dims=(64, 64),
+                            channel_mix=False)),
+    ("one_layer_lmax2_n64", dict(l_max=2, n_layers=1, n_tensor=64, twobody_dims=(128, 128, 128),
+                                 latent_dims=(128, 128, 128))),
+    ("uneven_widths", dict(l_max=2, n_layers=2, n_tensor=16, twobody_dims=(48, 96, 80), latent_dims=(112, 80))),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: c[0])
+@pytest.mark.parametrize("prec", [FP32, BF16], ids=["fp32", "bf16"])
+def test_small_models(case, prec):
+    name, kw = case
+    mc = W.ModelConfig(n_species=2, r_cut=4.0, **kw)
+    w = W.make_weights(mc, np.random.default_rng(5))
+    s = W.system(1)
+    sc, sh = W.species_scale_shift(mc, np.random.default_rng(6))
+    ref = OM.evaluate(mc, w, s, sc, sh)
+    got = gpu_eval(gpu_model(mc, w, prec, sc, sh), s)
+    if prec == FP32:
+        _check_fp32(name, got, ref, s.n_local)
+    else:
+        _check_bf16(name, got, ref, s.n_local)
+
+
+def test_clusters_and_ghost_shell_fp32():
+    mc = W.model_config(4)
+    w = W.make_weights(mc, np.random.default_rng(8))
+    cl = W.clusters(5, 3, lo=20, hi=300)
+    ref = OM.evaluate(mc, w, cl)
+    got = gpu_eval(gpu_model(mc, w, FP32), cl)
+    _check_fp32("clusters", got, ref, cl.n_local)
+    # ghost-shell share of a periodic box = the periodic box
+    s = W.jittered_lattice_box(1000, (1000 / 0.1) ** (1 / 3), 0.5, W.PROTEIN_MIX, 12)
+    g = W.ghost_shell(s, 6.0)
+    m = gpu_model(mc, w, FP32)
+    a, b = gpu_eval(m, s), gpu_eval(m, g)
+    F = b["forces"][:s.n_local].copy()
+    np.add.at(F, g.ghost_owner, b["forces"][s.n_local:])
+    assert np.abs(a["atom_energy"] - b["atom_energy"]).max() < 1e-9
+    assert np.abs(F - a["forces"]).max() < 1e-5
+
+
+def test_empty_and_isolated():
+    mc = W.model_config(2)
+    w = W.make_weights(mc, np.random.default_rng(1))
+    sc, sh = W.species_scale_shift(mc, np.random.default_rng(2))
+    s = W.System(pos=np.array([[0.0, 0.0, 0.0], [10.0, 0.0, 0.0]]), species=np.array([0, 1], np.int32),
+                 cell=np.zeros(3), pbc=np.zeros(3, np.int32), n_local=2)
+    got = gpu_eval(gpu_model(mc, w, BF16, sc, sh), s)
+    assert np.all(got["forces"] == 0.0)
+    assert np.allclose(got["atom_energy"], sh[[0, 1]])
+    s0 = W.System(pos=np.zeros((0, 3)), species=np.zeros(0, np.int32), cell=np.zeros(3),
+                  pbc=np.zeros(3, np.int32), n_local=0)
+    got = gpu_eval(gpu_model(mc, w, BF16, sc, sh), s0)
+    assert got["energy"][0] == 0.0
+
+
+# ----------------------------------------------------------------------------- full-size protein box
+
+@pytest.fixture(scope="module")
+def cfg3():
+    mc, s, w = W.workload(3)
+    nbr = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="kdtree")
+    return mc, s, w, nbr
+
+
+def _sampled_reference(mc, s, w, nbr, rng):
+    i, j, _ = nbr
+    cents = np.sort(rng.choice(s.n_local, size=24, replace=False))
+    p = OM.Params(mc, w)
+    e_raw, _ = OM.evaluate_centres(mc, w, s, cents, nbr, params=p)
+    atoms = cents[:3]
+    need = np.unique(np.concatenate([atoms, i[np.isin(j, atoms)]]))
+    _, g = OM.evaluate_centres(mc, w, s, need, nbr, params=p)
+    F = np.zeros((len(atoms), 3))
+    for k, a in enumerate(atoms):
+        for e in np.nonzero(i == a)[0]:
+            F[k] += g[int(e)]
+        for e in np.nonzero(j == a)[0]:
+            F[k] -= g[int(e)]
+    return cents, e_raw, atoms, F
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16], ids=["fp32", "bf16"])
+def test_protein_box_sampled(cfg3, prec):
+    mc, s, w, nbr = cfg3
+    got = gpu_eval(gpu_model(mc, w, prec), s, want_atom_virial=False)
+    cents, e_ref, atoms, F_ref = _sampled_reference(mc, s, w, nbr, np.random.default_rng(3))
+    dEi = got["atom_energy"][cents] - e_ref
+    dF = got["forces"][atoms] - F_ref
+    frms = float(np.sqrt((F_ref ** 2).mean()))
+    _report(f"cfg3_{'fp32' if prec == FP32 else 'bf16'}", mean_dEi=float(abs(dEi.mean())),
+            max_dEi=float(np.abs(dEi).max()), max_dF=float(np.abs(dF).max()), Frms=frms,
+            net_force=float(np.abs(got["forces"].sum(0)).max()))
+    if prec == FP32:
+        assert abs(dEi.mean()) <= 1e-6 and np.abs(dEi).max() <= 1e-5
+        assert np.abs(dF).max() <= 1e-4
+    else:
+        assert abs(dEi.mean()) <= 1e-3
+        assert np.sqrt((dF ** 2).mean()) <= 0.01 * frms
+    # periodic box: zero net force up to FP32 accumulation
+    assert np.abs(got["forces"].sum(0)).max() < 1e-6 * s.n_local
+
+
+# ----------------------------------------------------------------------------- interface behaviour
+
+def test_error_paths():
+    mc = W.model_config(2)
+    w = W.make_weights(mc, np.random.default_rng(1))
+    m = gpu_model(mc, w, BF16)
+    s = W.system(1)
+    pos, sp = to_dev(s)
+    F = torch.empty((s.n_total, 3), dtype=torch.float64, device=pos.device)
+    with pytest.raises(P.AllegroError) as ex:
+        m.energy_forces(pos, sp, F)
+    assert ex.value.status == -6
+    bad = pos.clone()
+    bad[3, 1] = float("nan")
+    with pytest.raises(P.AllegroError) as ex:
+        m.neighbors(bad, sp, s.cell, s.pbc)
+    assert ex.value.status == -5
+    with pytest.raises(P.AllegroError) as ex:
+        m.neighbors(pos, sp, [8.6, 0.1, 0, 0, 8.6, 0, 0, 0, 8.6], s.pbc)
+    assert ex.value.status == -1
+    # the model stays usable after errors
+    got = gpu_eval(m, s)
+    assert np.isfinite(got["energy"][0])
+
+
+def test_autograd_function():
+    from paper_2304_10061_amd.autograd import energy
+    mc, s, w = W.workload(1)
+    m = gpu_model(mc, w, FP32)
+    pos, sp = to_dev(s)
+    pos.requires_grad_(True)
+    E = energy(pos, m, sp, s.cell, s.pbc)
+    E.backward()
+    ref = OM.evaluate(mc, w, s)
+    assert abs(E.item() - ref.energy) / s.n_local < 1e-6
+    assert np.abs(-pos.grad.cpu().numpy() - ref.forces).max() < 1e-4

@@ -1,0 +1,70 @@
+"""CPU checks of the C interface: the library loads, exports every declared
+symbol, and its host-side logic (configuration validation, weight count, path
+enumeration) agrees with the oracle's independent enumeration.  No GPU work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2304_10061_amd as P
+from paper_2304_10061_amd import binding
+import workloads as W
+from oracle import cg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "allegro_mi355x.h")).read()
+    return sorted(set(re.findall(r"\b(allegro_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = P.load_library()
+    decl = _declared()
+    assert len(decl) >= 10
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(binding.EXPORTS) == decl
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_describe_matches_oracle(cfg):
+    mc = W.model_config(cfg)
+    info = P.describe(P.config_from(mc))
+    paths = cg.layer_paths(mc.l_max, mc.n_layers)
+    assert [info.n_paths[k] for k in range(mc.n_layers)] == [len(p) for p in paths]
+    rng = np.random.default_rng(0)
+    nnz = [np.count_nonzero(cg.fused_table(mc.l_max, p, rng.standard_normal((3, 3, 3)), k == len(paths) - 1))
+           for k, p in enumerate(paths)]
+    assert [info.n_nonzero[k] for k in range(mc.n_layers)] == nnz
+    assert info.n_weights == W.pack_weights(mc, W.make_weights(mc, rng)).size
+    assert info.dim == (mc.l_max + 1) ** 2 and info.latent == mc.latent
+
+
+@pytest.mark.parametrize("bad", [dict(l_max=3), dict(n_layers=3), dict(n_tensor=24), dict(n_species=20),
+                                 dict(twobody_dims=(100, 100), latent_dims=(100, 100)),
+                                 dict(latent_dims=(64, 32)), dict(edge_dims=(64, 64)), dict(r_cut=-1.0)])
+def test_describe_rejects_unsupported(bad):
+    kw = dict(n_species=2, r_cut=4.0, l_max=2, n_layers=2, n_tensor=32, twobody_dims=(64, 64),
+              latent_dims=(64, 64), edge_dims=(32,))
+    kw.update(bad)
+    with pytest.raises(P.AllegroError) as ex:
+        P.describe(P.make_config(**kw))
+    assert ex.value.status == -1
+
+
+def test_create_rejects_wrong_weight_count_without_device_work():
+    mc = W.model_config(2)
+    cfg = P.config_from(mc)
+    lib = P.load_library()
+    w = np.zeros(10, np.float32)
+    h = ctypes.c_void_p()
+    st = lib.allegro_create(ctypes.byref(cfg), w.ctypes.data, w.size, None, None, ctypes.byref(h))
+    assert st == -1 and not h.value
+    assert b"n_weights" in lib.allegro_last_error(None)
+    assert lib.allegro_status_string(-3) == b"ALLEGRO_E_CAPACITY"
+    assert lib.allegro_num_edges(None) == -1
+    lib.allegro_destroy(None)
