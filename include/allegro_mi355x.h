@@ -75,7 +75,11 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *   edge_chunk       0 = evaluate all edges at once; otherwise the largest
  *                    number of edges whose activations are held at a time
  *                    (whole centre segments; bounds workspace memory)
- * Widths d must be multiples of 16 and at most 512.
+ *   neighbor_skin    extra radius of the neighbour list (A), so that a list can
+ *                    be reused over several MD steps; pairs beyond r_cut carry
+ *                    a zero envelope and contribute exactly zero.  0 = the list
+ *                    holds exactly the pairs inside r_cut.
+ * MLP widths must be multiples of 16 and at most 512; the latent width d at most 256.
  */
 typedef struct {
   int32_t n_species, n_bessel, envelope_p, l_max, n_layers, n_tensor;
@@ -86,6 +90,7 @@ typedef struct {
   int32_t channel_mix;
   int32_t precision;
   int64_t edge_chunk;
+  double neighbor_skin;
 } AllegroConfig;
 
 /* Host-side description of a configuration (no device work). */
@@ -149,6 +154,27 @@ int allegro_neighbors(AllegroModel* m, int64_t n_local, int64_t n_total, const d
                       void* stream, int64_t* n_edges);
 
 /*
+ * allegro_neighbors_batched: neighbour list of many independent, non-periodic
+ * systems evaluated together (every atom is a centre; pairs never cross
+ * systems).  System k holds atoms [atom_offsets[k], atom_offsets[k+1]).
+ *   atom_offsets  host [n_systems+1], ascending, atom_offsets[0] = 0
+ *   pos, species  dev arrays over all atom_offsets[n_systems] atoms
+ * Same distance test, ordering and synchronisation as allegro_neighbors.
+ */
+int allegro_neighbors_batched(AllegroModel* m, int32_t n_systems, const int64_t* atom_offsets,
+                              const double* pos, const int32_t* species, void* stream,
+                              int64_t* n_edges);
+
+/*
+ * allegro_system_energies: per-system totals (FP64) of per-atom energies after a
+ * batched evaluation.
+ *   atom_energy    dev [n_atoms] from allegro_energy_forces
+ *   system_energy  dev [n_systems]
+ */
+int allegro_system_energies(AllegroModel* m, const double* atom_energy, double* system_energy,
+                            void* stream);
+
+/*
  * allegro_energy_forces: evaluate the network on the current neighbour list.
  *   pos, species  the arrays given to allegro_neighbors (same n_total)
  *   atom_energy   dev [n_local] double: sigma_Z E_i + mu_Z (may be NULL)
@@ -164,6 +190,39 @@ int allegro_neighbors(AllegroModel* m, int64_t n_local, int64_t n_total, const d
 int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* species,
                           double* atom_energy, double* forces, double* virial,
                           double* atom_virial, double* energy, void* stream);
+
+/*
+ * allegro_set_ghosts: declare ghosts as periodic images of local atoms, for
+ * allegro_md_run: ghost g (atom n_local + g) sits at pos[owner[g]] + offset[g],
+ * and its force is added to its owner's.  Pass n_ghost = 0 to clear.
+ *   owner   host [n_ghost] int32 in [0, n_local)
+ *   offset  host [n_ghost][3] double (A)
+ */
+int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const int32_t* owner,
+                       const double* offset);
+
+/*
+ * allegro_md_run: n_steps of FP64 velocity Verlet (section "Problem overview":
+ * MD needs forces every step) on the current neighbour list, which should have
+ * been built with a neighbor_skin large enough for the displacement over these
+ * steps.  Per step: v += dt/2 F/m; x += dt v; ghosts follow their owners;
+ * F = -dE/dx; ghost forces fold onto owners; v += dt/2 F/m.
+ *   n_steps      steps to run (>= 0); dt_fs the time step in fs
+ *   masses       dev [n_local] double, amu
+ *   pos, vel     dev [n_total][3] / [n_local][3] double, A and A/fs, updated
+ *   forces       dev [n_total][3] double: on entry the (folded) forces at pos
+ *                unless init_forces = 1; on return the forces at the final pos
+ *   species      dev [n_total] int32
+ *   thermo       dev [n_steps][2] double, potential and kinetic energy after
+ *                each step (may be NULL)
+ *   use_graph    1 = capture one step in a HIP graph (captured once per
+ *                neighbour list and argument set) and replay it n_steps times
+ *   max_disp     host, receives the largest centre displacement since the
+ *                neighbour build (synchronises the stream; may be NULL)
+ */
+int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos,
+                   double* vel, double* forces, const int32_t* species, double* thermo,
+                   int32_t init_forces, int32_t use_graph, void* stream, double* max_disp);
 
 /*
  * allegro_copy_edges: copy the current neighbour list to caller buffers.

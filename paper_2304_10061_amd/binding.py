@@ -23,8 +23,9 @@ STATUS = {0: "ALLEGRO_OK", -1: "ALLEGRO_E_INVAL", -2: "ALLEGRO_E_NOMEM", -3: "AL
 PREC_FP32, PREC_BF16 = 0, 1
 
 # Every symbol the header declares (checked by the CPU tests).
-EXPORTS = ("allegro_describe", "allegro_create", "allegro_neighbors", "allegro_energy_forces",
-           "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
+EXPORTS = ("allegro_describe", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
+           "allegro_system_energies", "allegro_energy_forces",
+           "allegro_set_ghosts", "allegro_md_run", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
            "allegro_workspace_bytes", "allegro_destroy", "allegro_last_error", "allegro_status_string")
 
 
@@ -37,7 +38,7 @@ class AllegroConfig(ctypes.Structure):
                 ("edge_dims", ctypes.c_int32 * 4), ("n_edge", ctypes.c_int32),
                 ("r_cut", ctypes.c_double), ("avg_num_neighbors", ctypes.c_double),
                 ("channel_mix", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("edge_chunk", ctypes.c_int64)]
+                ("edge_chunk", ctypes.c_int64), ("neighbor_skin", ctypes.c_double)]
 
 
 class AllegroInfo(ctypes.Structure):
@@ -70,8 +71,17 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_create.restype = ctypes.c_int
     lib.allegro_neighbors.argtypes = [vp, i64, i64, dp, dp, vp, vp, vp, ctypes.POINTER(i64)]
     lib.allegro_neighbors.restype = ctypes.c_int
+    lib.allegro_neighbors_batched.argtypes = [vp, i32, vp, dp, dp, vp, ctypes.POINTER(i64)]
+    lib.allegro_neighbors_batched.restype = ctypes.c_int
+    lib.allegro_system_energies.argtypes = [vp, dp, dp, vp]
+    lib.allegro_system_energies.restype = ctypes.c_int
     lib.allegro_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     lib.allegro_energy_forces.restype = ctypes.c_int
+    lib.allegro_set_ghosts.argtypes = [vp, i64, i64, vp, vp]
+    lib.allegro_set_ghosts.restype = ctypes.c_int
+    lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, i32, i32, vp,
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.allegro_md_run.restype = ctypes.c_int
     lib.allegro_copy_edges.argtypes = [vp, dp, dp, dp, vp]
     lib.allegro_copy_edges.restype = ctypes.c_int
     lib.allegro_num_edges.argtypes = [vp]
@@ -97,7 +107,7 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
                 n_layers: int = 2, n_tensor: int = 32, twobody_dims: Sequence[int] = (128, 128),
                 latent_dims: Sequence[int] = (128, 128), edge_dims: Sequence[int] = (128,),
                 avg_num_neighbors: Optional[float] = None, channel_mix: bool = True,
-                precision: int = PREC_BF16, edge_chunk: int = 0) -> AllegroConfig:
+                precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0) -> AllegroConfig:
     c = AllegroConfig()
     c.n_species, c.n_bessel, c.envelope_p, c.l_max = n_species, n_bessel, envelope_p, l_max
     c.n_layers, c.n_tensor = n_layers, n_tensor
@@ -114,16 +124,17 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
     c.channel_mix = 1 if channel_mix else 0
     c.precision = int(precision)
     c.edge_chunk = int(edge_chunk)
+    c.neighbor_skin = float(neighbor_skin)
     return c
 
 
-def config_from(mc, precision: int = PREC_BF16, edge_chunk: int = 0) -> AllegroConfig:
+def config_from(mc, precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0) -> AllegroConfig:
     """Config from any object with the ModelConfig attribute names."""
     return make_config(mc.n_species, mc.r_cut, n_bessel=mc.n_bessel, envelope_p=mc.envelope_p,
                        l_max=mc.l_max, n_layers=mc.n_layers, n_tensor=mc.n_tensor,
                        twobody_dims=mc.twobody_dims, latent_dims=mc.latent_dims, edge_dims=mc.edge_dims,
                        avg_num_neighbors=mc.avg_num_neighbors, channel_mix=mc.channel_mix,
-                       precision=precision, edge_chunk=edge_chunk)
+                       precision=precision, edge_chunk=edge_chunk, neighbor_skin=neighbor_skin)
 
 
 def describe(cfg: AllegroConfig) -> AllegroInfo:
@@ -200,12 +211,44 @@ class Model:
         self.n_local, self.n_total = n_local, n_total
         return int(ne.value)
 
+    def neighbors_batched(self, atom_offsets, pos, species, stream=None) -> int:
+        """Neighbour list of independent non-periodic systems (host offsets)."""
+        off = np.ascontiguousarray(atom_offsets, dtype=np.int64)
+        ne = ctypes.c_int64(0)
+        self._check(self.lib.allegro_neighbors_batched(self.handle, int(off.size - 1), off.ctypes.data, _ptr(pos),
+                                                       _ptr(species), _stream(stream), ctypes.byref(ne)))
+        self.n_local = self.n_total = int(off[-1])
+        return int(ne.value)
+
+    def system_energies(self, atom_energy, system_energy, stream=None):
+        self._check(self.lib.allegro_system_energies(self.handle, _ptr(atom_energy), _ptr(system_energy),
+                                                     _stream(stream)))
+
     def energy_forces(self, pos, species, forces, atom_energy=None, virial=None, atom_virial=None,
                       energy=None, stream=None):
         """Enqueue one evaluation; outputs are caller-owned cuda float64 tensors."""
         self._check(self.lib.allegro_energy_forces(self.handle, _ptr(pos), _ptr(species), _ptr(atom_energy),
                                                    _ptr(forces), _ptr(virial), _ptr(atom_virial),
                                                    _ptr(energy), _stream(stream)))
+
+    def set_ghosts(self, n_local: int, owner, offset):
+        """Ghost g = atom n_local + g is owner[g]'s image at offset[g] (host arrays)."""
+        ow = np.ascontiguousarray(owner, dtype=np.int32)
+        of = np.ascontiguousarray(offset, dtype=np.float64).reshape(-1, 3)
+        self._check(self.lib.allegro_set_ghosts(self.handle, int(n_local), int(ow.size),
+                                                ow.ctypes.data if ow.size else None,
+                                                of.ctypes.data if ow.size else None))
+
+    def md_run(self, n_steps, dt_fs, masses, pos, vel, forces, species, thermo=None, init_forces=False,
+               use_graph=True, stream=None, want_max_disp=True):
+        """Velocity Verlet on the device; returns the max displacement since the
+        last neighbour build (or None)."""
+        md = ctypes.c_double(0.0)
+        self._check(self.lib.allegro_md_run(self.handle, int(n_steps), float(dt_fs), _ptr(masses), _ptr(pos),
+                                            _ptr(vel), _ptr(forces), _ptr(species), _ptr(thermo),
+                                            1 if init_forces else 0, 1 if use_graph else 0, _stream(stream),
+                                            ctypes.byref(md) if want_max_disp else None))
+        return md.value if want_max_disp else None
 
     def num_edges(self) -> int:
         return int(self.lib.allegro_num_edges(self.handle))

@@ -22,7 +22,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
 
-SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "tensor.hip"]
+SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "tensor.hip", "md.hip"]
 
 
 def _hipcc() -> str:

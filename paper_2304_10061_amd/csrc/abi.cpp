@@ -143,6 +143,7 @@ Validated validate(const AllegroConfig* c) {
   for (int k = 0; k < c->n_latent; ++k) v.dimsL.push_back(c->latent_dims[k]);
   v.d = v.dims2b.back();
   REQUIRE(v.dimsL.back() == v.d, "last latent width must equal last two-body width");
+  REQUIRE(v.d <= 256, "latent width d must be at most 256");
   for (int w : v.dims2b) REQUIRE(w >= 16 && w <= 512 && w % 16 == 0, "MLP widths must be multiples of 16 in 16..512");
   for (int w : v.dimsL) REQUIRE(w >= 16 && w <= 512 && w % 16 == 0, "MLP widths must be multiples of 16 in 16..512");
   v.h = c->edge_dims[0];
@@ -151,6 +152,7 @@ Validated validate(const AllegroConfig* c) {
   REQUIRE(c->avg_num_neighbors > 0 && std::isfinite(c->avg_num_neighbors), "avg_num_neighbors must be positive");
   REQUIRE(c->precision == ALLEGRO_PREC_FP32 || c->precision == ALLEGRO_PREC_BF16, "precision must be 0 or 1");
   REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
+  REQUIRE(c->neighbor_skin >= 0 && std::isfinite(c->neighbor_skin), "neighbor_skin must be >= 0");
   v.dim = (v.lmax + 1) * (v.lmax + 1);
   v.LW = (v.lmax + 1) * v.n;
   // weight count, in the documented order
@@ -250,11 +252,25 @@ struct AllegroModel {
   DevBuf ei, ej, es, row_ptr, rrow_ptr, redge, keys;
   DevBuf cell_of, img, cell_count, cell_start, cell_cursor, cell_atoms, count, rcount, rcursor;
   DevBuf bbox, scan_tmp, err_flag;
+  int n_sys = 0;                          // batched mode: number of independent systems
+  DevBuf sys_off, sys_id, sys_shift;
   std::vector<int32_t> h_row_ptr;
   std::vector<int64_t> chunk_c;           // centre boundaries of chunks
   std::vector<int64_t> chunk_rp_off;      // offset of each chunk's rebased row pointers
   DevBuf chunk_rp;
   int64_t Ec = 0, Nc = 0;
+
+  // molecular dynamics
+  uint64_t nbr_version = 0;               // bumped by every neighbour build
+  int64_t n_ghost = 0, ghost_n_local = 0;
+  DevBuf g_owner, g_offset, g_ptr, g_idx; // ghost images and the owner -> ghosts CSR
+  DevBuf pos_ref;                         // positions of the centres at the last neighbour build
+  DevBuf md_epot, md_part, md_counter, md_atom_e;
+  hipStream_t md_stream = nullptr;
+  hipEvent_t md_ev[2] = {nullptr, nullptr};
+  hipGraph_t md_graph = nullptr;
+  hipGraphExec_t md_exec = nullptr;
+  std::vector<uintptr_t> md_key;
 
   // optional per-kernel timing with HIP events on the caller's stream
   bool timing = false;
@@ -460,12 +476,15 @@ void collect_times(AllegroModel* m) {
 }
 
 void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const double* pos, const int32_t* species,
-                    const double* cell, const int32_t* pbc, hipStream_t s, int64_t* n_edges) {
+                    const double* cell, const int32_t* pbc, hipStream_t s, int64_t* n_edges,
+                    const int64_t* sys_off = nullptr, int n_sys = 0) {
   REQUIRE(n_local >= 0 && n_total >= n_local, "need 0 <= n_local <= n_total");
   REQUIRE(pbc != nullptr, "pbc must not be NULL");
   REQUIRE((pos && species) || n_total == 0, "pos and species must not be NULL");
   REQUIRE(n_total < (int64_t)1 << 30, "at most 2^30 atoms");
-  const double rc = m->cfg.r_cut;
+  // earlier work on this stream may still use buffers that are regrown below
+  HIP_OK(hipStreamSynchronize(s));
+  const double rc = m->cfg.r_cut + m->cfg.neighbor_skin;   // list radius
   double L[3];
   int pb[3];
   for (int ax = 0; ax < 3; ++ax) {
@@ -492,7 +511,46 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   const int64_t nt = std::max<int64_t>(n_total, 1);
   // bounding box of the open axes
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  if (n_total > 0 && (!pb[0] || !pb[1] || !pb[2])) {
+  m->n_sys = n_sys;
+  if (n_sys > 0) {
+    // independent systems: each is moved (for binning only) into its own slot
+    // of a cubic grid of slots wide enough that no cell holds two systems'
+    // atoms within the cutoff of each other; the distance test uses the
+    // original coordinates and rejects pairs from different systems
+    std::vector<int64_t> off(sys_off, sys_off + n_sys + 1);
+    upload(m->sys_off, off.data(), off.size() * sizeof(int64_t));
+    std::vector<int32_t> sid((size_t)nt, 0);
+    for (int k = 0; k < n_sys; ++k)
+      for (int64_t q = off[k]; q < off[k + 1]; ++q) sid[q] = k;
+    upload(m->sys_id, sid.data(), sid.size() * sizeof(int32_t));
+    m->bbox.ensure((size_t)n_sys * 6 * sizeof(double));
+    HIP_OK(launch_system_bbox(pos, ptr<int64_t>(m->sys_off), n_sys, ptr<double>(m->bbox), s));
+    std::vector<double> bb((size_t)n_sys * 6);
+    HIP_OK(hipMemcpyAsync(bb.data(), m->bbox.p, bb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double ext = 0.0;
+    for (int k = 0; k < n_sys; ++k) {
+      if (off[k + 1] == off[k]) continue;
+      for (int ax = 0; ax < 3; ++ax) {
+        if (!(std::isfinite(bb[6 * k + ax]) && std::isfinite(bb[6 * k + 3 + ax])))
+          throw Fail{ALLEGRO_E_NONFINITE, "non-finite positions"};
+        ext = std::max(ext, bb[6 * k + 3 + ax] - bb[6 * k + ax]);
+      }
+    }
+    const double slot = ext + 2.0 * rc + 1.0;
+    int G = 1;
+    while ((int64_t)G * G * G < n_sys) ++G;
+    std::vector<double> shift((size_t)n_sys * 3, 0.0);
+    for (int k = 0; k < n_sys; ++k) {
+      const int sl[3] = {k % G, (k / G) % G, k / (G * G)};
+      for (int ax = 0; ax < 3; ++ax)
+        shift[3 * k + ax] = (off[k + 1] > off[k]) ? sl[ax] * slot - bb[6 * k + ax] + rc : 0.0;
+    }
+    upload(m->sys_shift, shift.data(), shift.size() * sizeof(double));
+    a.sys = ptr<int32_t>(m->sys_id);
+    a.sys_shift = ptr<double>(m->sys_shift);
+    for (int ax = 0; ax < 3; ++ax) { lo[ax] = 0.0; hi[ax] = G * slot; }
+  } else if (n_total > 0 && (!pb[0] || !pb[1] || !pb[2])) {
     m->bbox.ensure(1024 * 6 * sizeof(double));
     a.bbox = ptr<double>(m->bbox);
     int nb = 0;
@@ -618,6 +676,10 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   m->g_e.ensure(Ee * 3 * f);
   m->atom_e.ensure(std::max<int64_t>(n_local, 1) * sizeof(double));
   m->partial.ensure(((nt + 255) / 256) * 10 * sizeof(double));
+  m->pos_ref.ensure(std::max<int64_t>(n_local, 1) * 3 * sizeof(double));
+  if (n_local > 0)
+    HIP_OK(hipMemcpyAsync(m->pos_ref.p, pos, n_local * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  m->nbr_version++;
   if (n_edges) *n_edges = E;
 }
 
@@ -748,9 +810,147 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
   if (virial || energy) timed(m, "final_sums", s, [&] { return launch_final_sums(fa.partial, nb, virial, energy, s); });
 }
 
+void release_graph(AllegroModel* m) {
+  if (m->md_exec) (void)hipGraphExecDestroy(m->md_exec);
+  if (m->md_graph) (void)hipGraphDestroy(m->md_graph);
+  m->md_exec = nullptr;
+  m->md_graph = nullptr;
+  m->md_key.clear();
+}
+
+void md_step(AllegroModel* m, double dt, const double* masses, double* pos, double* vel, double* forces,
+             const int32_t* species, double* thermo, int cap, hipStream_t s) {
+  const int64_t nl = m->n_local;
+  HIP_OK(launch_kick_drift(nl, dt, masses, pos, vel, forces, s));
+  if (m->n_ghost > 0)
+    HIP_OK(launch_ghost_refresh(m->n_ghost, nl, ptr<int32_t>(m->g_owner), ptr<double>(m->g_offset), pos, s));
+  energy_forces_impl(m, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
+  if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
+  HIP_OK(launch_kick(nl, dt, masses, vel, forces, s));
+  if (thermo)
+    HIP_OK(launch_thermo(nl, masses, vel, ptr<double>(m->md_part), ptr<double>(m->md_epot), thermo,
+                         ptr<int>(m->md_counter), cap, s));
+}
+
+void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, double* pos, double* vel,
+                 double* forces, const int32_t* species, double* thermo, int init_forces, int use_graph,
+                 hipStream_t s, double* max_disp) {
+  if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
+  REQUIRE(n_steps >= 0 && std::isfinite(dt) && dt > 0, "need n_steps >= 0 and dt > 0");
+  REQUIRE(m->n_sys == 0 || m->n_ghost == 0, "ghost images are not used with batched systems");
+  REQUIRE(m->n_ghost == 0 || (m->ghost_n_local == m->n_local && m->n_local + m->n_ghost == m->n_total),
+          "ghost description does not match the neighbour list");
+  REQUIRE((masses && pos && vel && forces && species) || m->n_total == 0, "NULL array");
+  const int64_t nl = m->n_local;
+  m->md_epot.ensure(sizeof(double));
+  m->md_counter.ensure(sizeof(int));
+  m->md_part.ensure(((std::max<int64_t>(nl, 1) + 255) / 256) * sizeof(double));
+  m->md_atom_e.ensure(std::max<int64_t>(nl, 1) * sizeof(double));
+  const bool was_timing = m->timing;
+  m->timing = false;
+  if (init_forces) {
+    energy_forces_impl(m, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
+    if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
+  }
+  HIP_OK(launch_fill_i32(ptr<int32_t>(m->md_counter), 0, 1, s));
+  if (use_graph && n_steps > 0) {
+    const std::vector<uintptr_t> key{(uintptr_t)pos, (uintptr_t)vel, (uintptr_t)forces, (uintptr_t)masses,
+                                     (uintptr_t)species, (uintptr_t)thermo, (uintptr_t)m->nbr_version,
+                                     (uintptr_t)n_steps, (uintptr_t)(dt * 1e9)};
+    if (!m->md_stream) HIP_OK(hipStreamCreateWithFlags(&m->md_stream, hipStreamNonBlocking));
+    if (!m->md_ev[0]) {
+      HIP_OK(hipEventCreateWithFlags(&m->md_ev[0], hipEventDisableTiming));
+      HIP_OK(hipEventCreateWithFlags(&m->md_ev[1], hipEventDisableTiming));
+    }
+    HIP_OK(hipEventRecord(m->md_ev[0], s));
+    HIP_OK(hipStreamWaitEvent(m->md_stream, m->md_ev[0], 0));
+    if (!m->md_exec || m->md_key != key) {
+      release_graph(m);
+      HIP_OK(hipStreamBeginCapture(m->md_stream, hipStreamCaptureModeRelaxed));
+      try {
+        md_step(m, dt, masses, pos, vel, forces, species, thermo, n_steps, m->md_stream);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(m->md_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        m->timing = was_timing;
+        throw;
+      }
+      HIP_OK(hipStreamEndCapture(m->md_stream, &m->md_graph));
+      HIP_OK(hipGraphInstantiate(&m->md_exec, m->md_graph, nullptr, nullptr, 0));
+      m->md_key = key;
+    }
+    for (int k = 0; k < n_steps; ++k) HIP_OK(hipGraphLaunch(m->md_exec, m->md_stream));
+    HIP_OK(hipEventRecord(m->md_ev[1], m->md_stream));
+    HIP_OK(hipStreamWaitEvent(s, m->md_ev[1], 0));
+  } else {
+    for (int k = 0; k < n_steps; ++k) md_step(m, dt, masses, pos, vel, forces, species, thermo, n_steps, s);
+  }
+  m->timing = was_timing;
+  if (max_disp) {
+    int nb = 0;
+    HIP_OK(launch_max_disp(nl, pos, ptr<double>(m->pos_ref), ptr<double>(m->md_part), &nb, s));
+    std::vector<double> part(nb);
+    HIP_OK(hipMemcpyAsync(part.data(), m->md_part.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double mx = 0.0;
+    for (double v : part) mx = std::max(mx, v);
+    *max_disp = std::sqrt(mx);
+  }
+}
+
 }  // namespace
 
 extern "C" {
+
+int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const int32_t* owner,
+                       const double* offset) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    REQUIRE(n_local >= 0 && n_ghost >= 0, "negative count");
+    REQUIRE(n_ghost == 0 || (owner && offset), "owner and offset must not be NULL");
+    std::vector<int32_t> gptr(n_local + 1, 0), gidx(std::max<int64_t>(n_ghost, 1), 0);
+    for (int64_t g = 0; g < n_ghost; ++g) {
+      REQUIRE(owner[g] >= 0 && owner[g] < n_local, "ghost owner out of range");
+      REQUIRE(std::isfinite(offset[3 * g]) && std::isfinite(offset[3 * g + 1]) && std::isfinite(offset[3 * g + 2]),
+              "non-finite ghost offset");
+      gptr[owner[g] + 1]++;
+    }
+    for (int64_t o = 0; o < n_local; ++o) gptr[o + 1] += gptr[o];
+    std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
+    for (int64_t g = 0; g < n_ghost; ++g) gidx[fill[owner[g]]++] = (int32_t)g;
+    upload(m->g_ptr, gptr.data(), gptr.size() * sizeof(int32_t));
+    upload(m->g_idx, gidx.data(), gidx.size() * sizeof(int32_t));
+    if (n_ghost > 0) {
+      upload(m->g_owner, owner, n_ghost * sizeof(int32_t));
+      upload(m->g_offset, offset, n_ghost * 3 * sizeof(double));
+    }
+    m->n_ghost = n_ghost;
+    m->ghost_n_local = n_local;
+    release_graph(m);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  } catch (...) {
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos, double* vel,
+                   double* forces, const int32_t* species, double* thermo, int32_t init_forces, int32_t use_graph,
+                   void* stream, double* max_disp) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    md_run_impl(m, n_steps, dt_fs, masses, pos, vel, forces, species, thermo, init_forces, use_graph,
+                (hipStream_t)stream, max_disp);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  } catch (...) {
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
 
 int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info) {
   try {
@@ -819,6 +1019,41 @@ int allegro_neighbors(AllegroModel* m, int64_t n_local, int64_t n_total, const d
   } catch (...) {
     m->n_local = -1;
     return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_neighbors_batched(AllegroModel* m, int32_t n_systems, const int64_t* atom_offsets, const double* pos,
+                              const int32_t* species, void* stream, int64_t* n_edges) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    REQUIRE(n_systems >= 1 && atom_offsets != nullptr, "need n_systems >= 1 and atom_offsets");
+    REQUIRE(atom_offsets[0] == 0, "atom_offsets[0] must be 0");
+    for (int k = 0; k < n_systems; ++k) REQUIRE(atom_offsets[k + 1] >= atom_offsets[k], "atom_offsets must ascend");
+    const int64_t n = atom_offsets[n_systems];
+    const int32_t pbc[3] = {0, 0, 0};
+    neighbors_impl(m, n, n, pos, species, nullptr, pbc, (hipStream_t)stream, n_edges, atom_offsets, n_systems);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    m->n_local = -1;
+    return fail(m, f);
+  } catch (const std::bad_alloc&) {
+    m->n_local = -1;
+    return fail(m, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
+  } catch (...) {
+    m->n_local = -1;
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_system_energies(AllegroModel* m, const double* atom_energy, double* system_energy, void* stream) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    if (m->n_local < 0 || m->n_sys <= 0) throw Fail{ALLEGRO_E_STATE, "no batched neighbour list"};
+    REQUIRE(atom_energy && system_energy, "atom_energy and system_energy must not be NULL");
+    HIP_OK(launch_system_sums(atom_energy, ptr<int64_t>(m->sys_off), m->n_sys, system_energy, (hipStream_t)stream));
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
   }
 }
 
@@ -903,6 +1138,11 @@ int64_t allegro_workspace_bytes(const AllegroModel* m) {
 
 void allegro_destroy(AllegroModel* m) {
   if (!m) return;
+  release_graph(m);
+  if (m->md_stream) (void)hipStreamSynchronize(m->md_stream);
+  if (m->md_stream) (void)hipStreamDestroy(m->md_stream);
+  for (hipEvent_t e : m->md_ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto& p : m->pending) {
     (void)hipEventDestroy(p.second.first);
     (void)hipEventDestroy(p.second.second);

@@ -63,8 +63,10 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
   const float t = d / rc;
   const int p = a.p;
   const float tp = ipow(t, p);
-  const float u = 1.0f - 0.5f * (p + 1) * (p + 2) * tp + (float)(p * (p + 2)) * tp * t -
-                  0.5f * p * (p + 1) * tp * t * t;
+  // zero beyond the cutoff, so that list entries in a neighbour skin contribute nothing
+  const float u = t < 1.0f ? 1.0f - 0.5f * (p + 1) * (p + 2) * tp + (float)(p * (p + 2)) * tp * t -
+                                 0.5f * p * (p + 1) * tp * t * t
+                           : 0.0f;
   float* o = a.eb + e * kEB;
   float Y[9];
   sh9(x, y, z, Y);
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
   const int p = a.p;
   // du/dd = -(p(p+1)(p+2)/2) t^(p-1) (1-t)^2 / r_c
   const float omt = 1.0f - t;
-  const float du = -0.5f * (float)(p * (p + 1) * (p + 2)) * ipow(t, p - 1) * omt * omt / rc;
+  const float du = t < 1.0f ? -0.5f * (float)(p * (p + 1) * (p + 2)) * ipow(t, p - 1) * omt * omt / rc : 0.0f;
   const float pref = sqrtf(2.0f / rc);
   float gu = a.g_u[e];
   float gd = 0.0f;

@@ -210,8 +210,15 @@ struct NbrArgs {
   int32_t* redge = nullptr;       // [E]
   double* bbox = nullptr;         // [n_blocks][6] partial min/max
   void* scan_tmp = nullptr;       // exclusive_scan_tmp_bytes(max(n_total, n_cells))
+  // batched independent systems (null otherwise): system of each atom and the
+  // offset added to its coordinates for binning only
+  const int32_t* sys = nullptr;
+  const double* sys_shift = nullptr;  // [n_systems][3]
 };
 hipError_t launch_bbox(const NbrArgs& a, int* n_blocks, hipStream_t s);
+hipError_t launch_system_bbox(const double* pos, const int64_t* offsets, int n_sys, double* out, hipStream_t s);
+hipError_t launch_system_sums(const double* atom_value, const int64_t* offsets, int n_sys, double* out,
+                              hipStream_t s);
 hipError_t launch_bin_atoms_err(const NbrArgs& a, int* err, hipStream_t s);
 hipError_t launch_fill_cells(const NbrArgs& a, hipStream_t s);
 hipError_t launch_count_neighbors(const NbrArgs& a, hipStream_t s);
@@ -221,5 +228,17 @@ hipError_t launch_fill_neighbors(const NbrArgs& a, hipStream_t s);
 hipError_t launch_sort_neighbors(const NbrArgs& a, hipStream_t s);
 hipError_t launch_reverse_csr(const NbrArgs& a, int64_t E, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+// velocity Verlet (md.hip)
+hipError_t launch_kick_drift(int64_t n, double dt, const double* m, double* x, double* v, const double* f,
+                             hipStream_t s);
+hipError_t launch_kick(int64_t n, double dt, const double* m, double* v, const double* f, hipStream_t s);
+hipError_t launch_ghost_refresh(int64_t n_ghost, int64_t n_local, const int32_t* owner, const double* offset,
+                                double* x, hipStream_t s);
+hipError_t launch_fold(int64_t n_local, const int32_t* gptr, const int32_t* gidx, double* f, hipStream_t s);
+hipError_t launch_thermo(int64_t n, const double* m, const double* v, double* part, const double* epot,
+                         double* thermo, int* counter, int cap, hipStream_t s);
+hipError_t launch_max_disp(int64_t n, const double* x, const double* x0, double* part, int* n_blocks,
+                           hipStream_t s);
 
 }  // namespace allegro

@@ -68,33 +68,63 @@ template <> struct PT<0> {
   }
 };
 
-// acc[rt][q] = A[TM x Kp] (LDS) @ B; wave w owns column tiles nt = w + 4 q.
+// Column tiles of a GEMM output are dealt to the four waves round-robin; pass
+// p covers nt = wave + 4 (p MAXCT + q), q < MAXCT, so wide outputs run in
+// several passes with a bounded accumulator set.
+template <int MAXCT>
+__device__ __forceinline__ int tile_of(int pass, int q, int wave) { return wave + 4 * (pass * MAXCT + q); }
+
+template <int MAXCT>
+__device__ __forceinline__ int npasses(int Np) { return (Np / 16 + 4 * MAXCT - 1) / (4 * MAXCT); }
+
+// acc[rt][q] = A[TM x K-range] (LDS) @ B[K-range x tiles of this pass].
+// A holds the columns of K blocks [kb0, kb1) starting at its column 0.  The B
+// fragments of the next K block are requested before the MFMAs of the
+// current one, so L2 latency overlaps matrix-core work.
 template <int PREC, int RT, int MAXCT>
 __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
-                                          int lda, const GemmB& B, int wave, int lane) {
+                                          int lda, const GemmB& B, int wave, int lane, int pass,
+                                          int kb0 = 0, int kb1 = -1, bool zero = true) {
   using P = PT<PREC>;
   using T = typename P::T;
   using F = typename P::F;
+  if (zero) {
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int q = 0; q < MAXCT; ++q) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int q = 0; q < MAXCT; ++q) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
   const int nkb = B.Kp >> 5, nct = B.Np >> 4;
-  const T* Bp = (const T*)B.p;
-  const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4);
-  for (int kb = 0; kb < nkb; ++kb) {
+  if (kb1 < 0) kb1 = nkb;
+  const T* Bl = (const T*)B.p + (size_t)lane * 8;
+  const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4) - kb0 * 32;
+  F bc[MAXCT], bn[MAXCT];
+#pragma unroll
+  for (int q = 0; q < MAXCT; ++q) {
+    const int nt = tile_of<MAXCT>(pass, q, wave);
+    if (nt < nct) bc[q] = P::load(Bl + (size_t)(nt * nkb + kb0) * 512);
+  }
+  for (int kb = kb0; kb < kb1; ++kb) {
+    if (kb + 1 < kb1) {
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) {
+        const int nt = tile_of<MAXCT>(pass, q, wave);
+        if (nt < nct) bn[q] = P::load(Bl + (size_t)(nt * nkb + kb + 1) * 512);
+      }
+    }
     F a[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) a[rt] = P::load(Arow + rt * 16 * lda + kb * 32);
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
-      const int nt = wave + 4 * q;
+      const int nt = tile_of<MAXCT>(pass, q, wave);
       if (nt < nct) {
-        const F b = P::load(Bp + ((size_t)(nt * nkb + kb) * 64 + lane) * 8);
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(a[rt], b, acc[rt][q]);
+        for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(a[rt], bc[q], acc[rt][q]);
       }
     }
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) bc[q] = bn[q];
   }
 }
 
@@ -138,14 +168,14 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int lda, 
   }
 }
 
-// Writes f(acc) into an LDS tile (row-major, T) over columns [0, Np).
+// Writes f(acc) of pass `pass` into an LDS tile (row-major, T) for columns < Np.
 template <int PREC, int RT, int MAXCT, class Fn>
 __device__ __forceinline__ void store_tile(const f32x4 (&acc)[RT][MAXCT], typename PT<PREC>::T* out,
-                                           int ldo, int Np, int wave, int lane, Fn fn) {
+                                           int ldo, int Np, int wave, int lane, int pass, Fn fn) {
   using T = typename PT<PREC>::T;
 #pragma unroll
   for (int q = 0; q < MAXCT; ++q) {
-    const int nt = wave + 4 * q;
+    const int nt = tile_of<MAXCT>(pass, q, wave);
     if (nt * 16 >= Np) continue;
     const int col = nt * 16 + (lane & 15);
 #pragma unroll
@@ -158,50 +188,64 @@ __device__ __forceinline__ void store_tile(const f32x4 (&acc)[RT][MAXCT], typena
   }
 }
 
+// Hidden layers of the chain: `in` -> SiLU -> alternate buffer, optionally
+// keeping the pre-activations.  Returns the buffer holding the last hidden
+// activation (the input of the last layer).
 template <int PREC, int TM, int MAXCT>
-__global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int lda, int ldh) {
+__device__ __forceinline__ const typename PT<PREC>::T* hidden_layers(
+    const MlpArgs& a, typename PT<PREC>::T* X, int ldx, typename PT<PREC>::T* H, int ldh,
+    typename PT<PREC>::T* Pb, int ldp, int* ldin, int wave, int lane) {
+  using T = typename PT<PREC>::T;
+  constexpr int RT = TM / 16;
+  const T* in = X;
+  *ldin = ldx;
+  f32x4 acc[RT][MAXCT];
+  for (int l = 0; l + 1 < a.w.nl; ++l) {
+    T* out = (in == X) ? H : X;
+    const int ldo = (in == X) ? ldh : ldx;
+    const GemmB& B = a.w.fwd[l];
+    for (int p = 0; p < npasses<MAXCT>(B.Np); ++p) {
+      gemm_tile<PREC, RT, MAXCT>(acc, in, *ldin, B, wave, lane, p);
+      if (Pb) store_tile<PREC, RT, MAXCT>(acc, Pb + l * TM * ldp, ldp, B.Np, wave, lane, p,
+                                          [](float v, int, int) { return v; });
+      store_tile<PREC, RT, MAXCT>(acc, out, ldo, B.Np, wave, lane, p, [](float v, int, int) { return silu(v); });
+    }
+    __syncthreads();
+    in = out;
+    *ldin = ldo;
+  }
+  return in;
+}
+
+template <int PREC, int TM, int MAXCT>
+__global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
   extern __shared__ __align__(16) char smem[];
   T* X = (T*)smem;
-  T* H = X + TM * lda;
+  T* H = X + TM * ldx;
   __shared__ float red[4][TM];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
 
-  build_input<PREC, TM>(a, X, lda, e0, a.w.fwd[0].Kp);
+  build_input<PREC, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
   __syncthreads();
-
-  T* bufs[2] = {H, X};
-  const int ldb[2] = {ldh, lda};
-  const T* in = X;
-  int ldin = lda;
-  f32x4 acc[RT][MAXCT];
+  int ldin;
+  const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, nullptr, 0, &ldin, wave, lane);
   const int nl = a.w.nl;
-  for (int l = 0; l < nl; ++l) {
-    gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[l], wave, lane);
-    if (l < nl - 1) {
-      T* out = bufs[l & 1];
-      store_tile<PREC, RT, MAXCT>(acc, out, ldb[l & 1], a.w.fwd[l].Np, wave, lane,
-                                  [](float v, int, int) { return silu(v); });
-      __syncthreads();
-      in = out;
-      ldin = ldb[l & 1];
-    }
-  }
-  // epilogue: x = u h (two-body) or rs (x_prev + u h) (latent)
+  f32x4 acc[RT][MAXCT];
+  gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // N = d: one pass
+  // epilogue: x = u h (two-body) or rs (x_prev + u h) (latent), kept in acc
   const int d = a.d;
-  float xr[RT][MAXCT][4];
 #pragma unroll
   for (int q = 0; q < MAXCT; ++q) {
-    const int col = (wave + 4 * q) * 16 + (lane & 15);
+    const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = rt * 16 + 4 * (lane >> 4) + i;
-        const int e = e0 + row;
+        const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
         float v = 0.0f;
         if (e < a.E && col < d) {
           const float u = a.eb[(size_t)e * kEB + kEB_U];
@@ -209,30 +253,24 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int lda, int ldh) {
           else v = a.res_scale * (a.x_prev[(size_t)e * d + col] + u * acc[rt][q][i]);
           if (a.x_out) a.x_out[(size_t)e * d + col] = v;
         }
-        xr[rt][q][i] = v;
+        acc[rt][q][i] = v;
       }
   }
   if (a.kind == kLatentFinal) {
     // E_ij = x . we : per-lane partial over its columns, then across lanes and waves
-    float part[RT][4];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float s = 0.0f;
+        float sum = 0.0f;
 #pragma unroll
         for (int q = 0; q < MAXCT; ++q) {
-          const int col = (wave + 4 * q) * 16 + (lane & 15);
-          if (col < d) s = fmaf(xr[rt][q][i], a.we[col], s);
+          const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+          if (col < d) sum = fmaf(acc[rt][q][i], a.we[col], sum);
         }
-        s = group_inner_sum(s, 16);
-        part[rt][i] = s;
+        sum = group_inner_sum(sum, 16);
+        if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
       }
-    if ((lane & 15) == 0)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) red[wave][rt * 16 + 4 * (lane >> 4) + i] = part[rt][i];
     __syncthreads();
     if ((int)threadIdx.x < TM) {
       const int e = e0 + threadIdx.x;
@@ -242,57 +280,49 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int lda, int ldh) {
     return;
   }
   if (a.head.p == nullptr) return;
-  // head GEMM on x (written to the buffer the last layer did not read)
+  // head GEMM on x, staged in the buffer the last layer did not read
   T* xb = (in == X) ? H : X;
-  const int ldx = (in == X) ? ldh : lda;
+  const int ldxb = (in == X) ? ldh : ldx;
+  store_tile<PREC, RT, MAXCT>(acc, xb, ldxb, a.w.fwd[nl - 1].Np, wave, lane, 0, [](float v, int, int) { return v; });
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < MAXCT; ++q) {
-    const int nt = wave + 4 * q;
-    if (nt * 16 >= a.w.fwd[nl - 1].Np) continue;
-    const int col = nt * 16 + (lane & 15);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) xb[(rt * 16 + 4 * (lane >> 4) + i) * ldx + col] = to_t<T>(xr[rt][q][i]);
-  }
-  __syncthreads();
-  gemm_tile<PREC, RT, MAXCT>(acc, xb, ldx, a.head, wave, lane);
   const int Nh = a.head.N;
+  for (int p = 0; p < npasses<MAXCT>(a.head.Np); ++p) {
+    gemm_tile<PREC, RT, MAXCT>(acc, xb, ldxb, a.head, wave, lane, p);
 #pragma unroll
-  for (int q = 0; q < MAXCT; ++q) {
-    const int col = (wave + 4 * q) * 16 + (lane & 15);
-    if (col >= Nh) continue;
+    for (int q = 0; q < MAXCT; ++q) {
+      const int col = tile_of<MAXCT>(p, q, wave) * 16 + (lane & 15);
+      if (col >= Nh) continue;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-        if (e < a.E) a.head_out[(size_t)e * Nh + col] = acc[rt][q][i];
-      }
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          if (e < a.E) a.head_out[(size_t)e * Nh + col] = acc[rt][q][i];
+        }
+    }
   }
 }
 
 template <int PREC, int TM, int MAXCT>
-__global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int lda, int ldh) {
+__global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
   extern __shared__ __align__(16) char smem[];
   T* X = (T*)smem;
-  T* H = X + TM * lda;
-  T* Pb = H + TM * ldh;                 // nl-1 buffers of [TM][ldh]
+  T* H = X + TM * ldx;
+  T* Pb = H + TM * ldh;                 // nl-1 pre-activation buffers [TM][ldh]
   __shared__ float red[4][TM];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
   const int d = a.d;
   const int nl = a.w.nl;
 
-  // 1. G = dE/dx_out
+  // 1. G = dE/dx_out (columns < d all lie in pass 0)
   f32x4 G[RT][MAXCT];
 #pragma unroll
   for (int q = 0; q < MAXCT; ++q) {
-    const int col = (wave + 4 * q) * 16 + (lane & 15);
+    const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -308,60 +338,46 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int lda, int ldh) {
   }
   f32x4 acc[RT][MAXCT];
   if (a.kind != kLatentFinal && a.head_bwd.p != nullptr) {
-    const int Kh = a.head_bwd.K, Khp = a.head_bwd.Kp;
-    for (int idx = threadIdx.x; idx < TM * Khp; idx += 256) {
-      const int r = idx / Khp, c = idx - r * Khp;
-      const int e = e0 + r;
-      float v = 0.0f;
-      if (e < a.E && c < Kh) v = a.g_head[(size_t)e * Kh + c];
-      X[r * lda + c] = to_t<T>(v);
-    }
-    __syncthreads();
-    gemm_tile<PREC, RT, MAXCT>(acc, X, lda, a.head_bwd, wave, lane);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int q = 0; q < MAXCT; ++q) G[rt][q] += acc[rt][q];
-    __syncthreads();
-  }
-
-  // 2. recompute the chain, keeping pre-activations of hidden layers
-  build_input<PREC, TM>(a, X, lda, e0, a.w.fwd[0].Kp);
-  __syncthreads();
-  const T* in = X;
-  int ldin = lda;
-  for (int l = 0; l < nl; ++l) {
-    gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[l], wave, lane);
-    if (l < nl - 1) {
-      const int Np = a.w.fwd[l].Np;
-      store_tile<PREC, RT, MAXCT>(acc, Pb + l * TM * ldh, ldh, Np, wave, lane,
-                                  [](float v, int, int) { return v; });
-      if (in == H) __syncthreads();
-      store_tile<PREC, RT, MAXCT>(acc, H, ldh, Np, wave, lane, [](float v, int, int) { return silu(v); });
-      __syncthreads();
-      in = H;
-      ldin = ldh;
-    }
-  }
-  // acc = h.  dE/du and dE/dh.
-  const float rs = (a.kind == kTwoBody) ? 1.0f : a.res_scale;
-  {
-    float part[RT][4];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float s = 0.0f;
-#pragma unroll
-        for (int q = 0; q < MAXCT; ++q) s = fmaf(G[rt][q][i], acc[rt][q][i], s);
-        part[rt][i] = group_inner_sum(s, 16);
+    // G += g_head @ W_head^T, K staged through X in chunks of its width
+    const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5, chunk = ldx >> 5;
+    for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
+      const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
+      const int w = (kb1 - kb0) * 32;
+      for (int idx = threadIdx.x; idx < TM * w; idx += 256) {
+        const int r = idx / w, c = idx - r * w;
+        const int e = e0 + r, cc = kb0 * 32 + c;
+        float v = 0.0f;
+        if (e < a.E && cc < Kh) v = a.g_head[(size_t)e * Kh + cc];
+        X[r * ldx + c] = to_t<T>(v);
       }
-    if ((lane & 15) == 0)
+      __syncthreads();
+      gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, true);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) red[wave][rt * 16 + 4 * (lane >> 4) + i] = part[rt][i];
+        for (int q = 0; q < MAXCT; ++q) G[rt][q] += acc[rt][q];
+      __syncthreads();
+    }
   }
+
+  // 2. recompute the chain, keeping hidden pre-activations
+  build_input<PREC, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  __syncthreads();
+  int ldin;
+  const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, Pb, ldh, &ldin, wave, lane);
+  gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // acc = h
+  const float rs = (a.kind == kTwoBody) ? 1.0f : a.res_scale;
+  // dE/du = rs sum_c G h
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float sum = 0.0f;
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) sum = fmaf(G[rt][q][i], acc[rt][q][i], sum);
+      sum = group_inner_sum(sum, 16);
+      if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
+    }
   __syncthreads();   // also: every wave is done reading `in`
   if ((int)threadIdx.x < TM) {
     const int e = e0 + threadIdx.x;
@@ -371,118 +387,105 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int lda, int ldh) {
       a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
     }
   }
-  {
-    const int Np = a.w.fwd[nl - 1].Np;
+  // dE/dh = rs u G into the buffer the last layer did not read
+  T* cur = (in == X) ? H : X;
+  int ldc = (in == X) ? ldh : ldx;
+  store_tile<PREC, RT, MAXCT>(G, cur, ldc, a.w.fwd[nl - 1].Np, wave, lane, 0, [&](float v, int row, int) {
+    const int e = e0 + row;
+    return e < a.E ? rs * a.eb[(size_t)e * kEB + kEB_U] * v : 0.0f;
+  });
+  __syncthreads();
+  // 3. back through the hidden layers (ping-pong between X and H)
+  for (int l = nl - 1; l > 0; --l) {
+    T* nxt = (cur == X) ? H : X;
+    const int ldn = (cur == X) ? ldh : ldx;
+    const T* Pl = Pb + (l - 1) * TM * ldh;
+    const GemmB& B = a.w.bwd[l];
+    for (int p = 0; p < npasses<MAXCT>(B.Np); ++p) {
+      gemm_tile<PREC, RT, MAXCT>(acc, cur, ldc, B, wave, lane, p);
+      store_tile<PREC, RT, MAXCT>(acc, nxt, ldn, B.Np, wave, lane, p, [&](float v, int row, int col) {
+        return v * silu_grad((float)Pl[row * ldh + col]);
+      });
+    }
+    __syncthreads();
+    cur = nxt;
+    ldc = ldn;
+  }
+  // 4. dE/dz, written straight to the outputs
+  const int S = a.n_species;
+  const GemmB& B0 = a.w.bwd[0];
+  for (int p = 0; p < npasses<MAXCT>(B0.Np); ++p) {
+    gemm_tile<PREC, RT, MAXCT>(acc, cur, ldc, B0, wave, lane, p);
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
-      const int nt = wave + 4 * q;
-      if (nt * 16 >= Np) continue;
-      const int col = nt * 16 + (lane & 15);
+      const int col = tile_of<MAXCT>(p, q, wave) * 16 + (lane & 15);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int row = rt * 16 + 4 * (lane >> 4) + i;
-          const int e = e0 + row;
-          const float u = e < a.E ? a.eb[(size_t)e * kEB + kEB_U] : 0.0f;
-          X[row * lda + col] = to_t<T>(rs * u * G[rt][q][i]);
+          const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          if (e >= a.E) continue;
+          const float g = acc[rt][q][i];
+          if (a.kind == kTwoBody) {
+            if (col >= 2 * S && col < 2 * S + a.n_bessel) a.g_R[(size_t)e * a.n_bessel + col - 2 * S] = g;
+          } else if (col < d) {
+            a.g_xprev[(size_t)e * d + col] = rs * G[rt][q][i] + g;   // p == 0 here
+          } else if (col < d + a.n) {
+            a.g_s[(size_t)e * a.n + col - d] = g;
+          }
         }
     }
-  }
-  __syncthreads();
-  // 3. back through the layers
-  for (int l = nl - 1; l >= 0; --l) {
-    gemm_tile<PREC, RT, MAXCT>(acc, X, lda, a.w.bwd[l], wave, lane);
-    if (l > 0) {
-      const T* Pl = Pb + (l - 1) * TM * ldh;
-      __syncthreads();
-      store_tile<PREC, RT, MAXCT>(acc, X, lda, a.w.bwd[l].Np, wave, lane, [&](float v, int row, int col) {
-        return v * silu_grad((float)Pl[row * ldh + col]);
-      });
-      __syncthreads();
-    }
-  }
-  // acc = dE/dz (input of the chain)
-  const int S = a.n_species;
-#pragma unroll
-  for (int q = 0; q < MAXCT; ++q) {
-    const int col = (wave + 4 * q) * 16 + (lane & 15);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-        if (e >= a.E) continue;
-        const float g = acc[rt][q][i];
-        if (a.kind == kTwoBody) {
-          if (col >= 2 * S && col < 2 * S + a.n_bessel) a.g_R[(size_t)e * a.n_bessel + col - 2 * S] = g;
-        } else if (col < d) {
-          a.g_xprev[(size_t)e * d + col] = rs * G[rt][q][i] + g;
-        } else if (col < d + a.n) {
-          a.g_s[(size_t)e * a.n + col - d] = g;
-        }
-      }
   }
 }
 
+// LDS layout: X [TM][ldx] and H [TM][ldh] (+ nl-1 pre-activation buffers of
+// [TM][ldh] in the backward kernel).
 template <int PREC>
-void lds_dims(const MlpArgs& a, int TM, bool bwd, int* lda, int* ldh, size_t* bytes) {
-  int kx = a.w.fwd[0].Kp;
-  int kh = 32;
-  for (int l = 0; l < a.w.nl; ++l) {
-    kx = kx > a.w.fwd[l].Np ? kx : a.w.fwd[l].Np;
-    if (l < a.w.nl - 1) kh = kh > a.w.fwd[l].Np ? kh : a.w.fwd[l].Np;
-    if (bwd) kx = kx > a.w.bwd[l].Np ? kx : a.w.bwd[l].Np;
-  }
-  if (a.head.p) kx = kx > a.head.Kp ? kx : a.head.Kp;
-  if (bwd && a.head_bwd.p) kx = kx > a.head_bwd.Kp ? kx : a.head_bwd.Kp;
-  if (!bwd) kh = kh > kx ? kh : kx;     // forward ping-pongs any width through H
+void lds_dims(const MlpArgs& a, int TM, bool bwd, int* ldx, int* ldh, size_t* bytes) {
+  int kh = 32;                       // widths of hidden layers and of the output d
+  for (int l = 0; l < a.w.nl; ++l) kh = kh > a.w.fwd[l].Np ? kh : a.w.fwd[l].Np;
+  int kx = kh > a.w.fwd[0].Kp ? kh : a.w.fwd[0].Kp;
   const int pad = PREC ? 8 : 4;
-  *lda = kx + pad;
+  *ldx = kx + pad;
   *ldh = kh + pad;
-  const int nbuf_h = bwd ? a.w.nl : 1;  // H plus nl-1 pre-activation buffers
-  *bytes = (size_t)TM * ((size_t)*lda + (size_t)nbuf_h * *ldh) * (PREC ? 2 : 4);
+  const int nbuf_h = bwd ? a.w.nl : 1;
+  *bytes = (size_t)TM * ((size_t)*ldx + (size_t)nbuf_h * *ldh) * (PREC ? 2 : 4);
 }
 
-int max_ct(const MlpArgs& a, bool bwd) {
-  int n = 0;
-  for (int l = 0; l < a.w.nl; ++l) {
-    n = n > a.w.fwd[l].Np ? n : a.w.fwd[l].Np;
-    if (bwd) n = n > a.w.bwd[l].Np ? n : a.w.bwd[l].Np;
-  }
-  if (!bwd && a.head.p) n = n > a.head.Np ? n : a.head.Np;
-  if (bwd && a.head_bwd.p) n = n > a.head_bwd.Np ? n : a.head_bwd.Np;
-  return (n / 16 + 3) / 4;
+// Accumulator tiles per wave: the latent width d must fit one pass.
+int max_ct(const MlpArgs& a) {
+  const int dt = (a.d + 15) / 16;
+  return (dt + 3) / 4;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024 - 4096;
 
 template <int PREC, int TM, int MAXCT>
 hipError_t launch_one(const MlpArgs& a, bool bwd, hipStream_t s) {
-  int lda, ldh;
+  int ldx, ldh;
   size_t bytes;
-  lds_dims<PREC>(a, TM, bwd, &lda, &ldh, &bytes);
+  lds_dims<PREC>(a, TM, bwd, &ldx, &ldh, &bytes);
   const dim3 grid((a.E + TM - 1) / TM), block(256);
   if (bwd) {
     auto k = k_mlp_bwd<PREC, TM, MAXCT>;
     hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (st != hipSuccess) return st;
-    hipLaunchKernelGGL(k, grid, block, bytes, s, a, lda, ldh);
+    hipLaunchKernelGGL(k, grid, block, bytes, s, a, ldx, ldh);
   } else {
     auto k = k_mlp_fwd<PREC, TM, MAXCT>;
     hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (st != hipSuccess) return st;
-    hipLaunchKernelGGL(k, grid, block, bytes, s, a, lda, ldh);
+    hipLaunchKernelGGL(k, grid, block, bytes, s, a, ldx, ldh);
   }
   return hipGetLastError();
 }
 
 template <int PREC, int TM>
 hipError_t dispatch_ct(const MlpArgs& a, bool bwd, hipStream_t s) {
-  const int ct = max_ct(a, bwd);
+  const int ct = max_ct(a);
+  if (ct <= 1) return launch_one<PREC, TM, 1>(a, bwd, s);
   if (ct <= 2) return launch_one<PREC, TM, 2>(a, bwd, s);
   if (ct <= 4) return launch_one<PREC, TM, 4>(a, bwd, s);
-  if (ct <= 6) return launch_one<PREC, TM, 6>(a, bwd, s);
   return hipErrorInvalidValue;
 }
 
@@ -490,9 +493,9 @@ template <int PREC>
 int pick_tm(const MlpArgs& a, bool bwd) {
   const int cands[2] = {PREC ? 64 : 32, PREC ? 32 : 16};
   for (int t : cands) {
-    int lda, ldh;
+    int ldx, ldh;
     size_t bytes;
-    lds_dims<PREC>(a, t, bwd, &lda, &ldh, &bytes);
+    lds_dims<PREC>(a, t, bwd, &ldx, &ldh, &bytes);
     if (bytes <= kLdsLimit) return t;
   }
   return 0;
@@ -515,13 +518,12 @@ hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
 }  // namespace
 
 size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd) {
-  int lda, ldh;
+  int ldx, ldh;
   size_t bytes;
   const int tm = prec ? pick_tm<1>(a, bwd) : pick_tm<0>(a, bwd);
-  if (tm == 0) return (size_t)-1;
-  if (prec) lds_dims<1>(a, tm, bwd, &lda, &ldh, &bytes);
-  else lds_dims<0>(a, tm, bwd, &lda, &ldh, &bytes);
-  if (max_ct(a, bwd) > 6) return (size_t)-1;
+  if (tm == 0 || max_ct(a) > 4) return (size_t)-1;
+  if (prec) lds_dims<1>(a, tm, bwd, &ldx, &ldh, &bytes);
+  else lds_dims<0>(a, tm, bwd, &ldx, &ldh, &bytes);
   return bytes;
 }
 

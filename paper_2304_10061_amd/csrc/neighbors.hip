@@ -65,8 +65,9 @@ __global__ void k_bin(NbrArgs a, int* __restrict__ err) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= a.n_total) return;
   int c[3];
+  const int st = a.sys ? a.sys[t] : 0;
   for (int ax = 0; ax < 3; ++ax) {
-    const double x = a.pos[3 * t + ax];
+    const double x = a.pos[3 * t + ax] + (a.sys ? a.sys_shift[3 * st + ax] : 0.0);
     int q = 0;
     double u;
     if (a.pbc[ax]) {
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
       int j = 0, sx = 0, sy = 0, sz = 0;
       if (f < total) {
         j = a.cell_atoms[st + (f - ex)];
+        const bool same_sys = a.sys == nullptr || a.sys[j] == a.sys[i];
         sx = a.pbc[0] ? m0 - a.img[3 * j] + qi[0] : 0;
         sy = a.pbc[1] ? m1 - a.img[3 * j + 1] + qi[1] : 0;
         sz = a.pbc[2] ? m2 - a.img[3 * j + 2] + qi[2] : 0;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
         const double dy = __dadd_rn(__dsub_rn(a.pos[3 * j + 1], yi), __dmul_rn((double)sy, a.L[1]));
         const double dz = __dadd_rn(__dsub_rn(a.pos[3 * j + 2], zi), __dmul_rn((double)sz, a.L[2]));
         const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-        hit = d2 < a.r_cut2 && !(j == i && sx == 0 && sy == 0 && sz == 0);
+        hit = same_sys && d2 < a.r_cut2 && !(j == i && sx == 0 && sy == 0 && sz == 0);
       }
       if (WRITE) {
         const unsigned long long mask = __ballot(hit);
@@ -286,9 +288,62 @@ __global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* 
   if (t < n) out[t] += block_sum[blockIdx.x];
 }
 
+// One block per system: min/max of its atoms' coordinates.
+__global__ __launch_bounds__(256) void k_system_bbox(const double* __restrict__ pos,
+                                                     const int64_t* __restrict__ off, double* __restrict__ out) {
+  __shared__ double red[6][256];
+  const int s = blockIdx.x;
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int64_t a = off[s] + threadIdx.x; a < off[s + 1]; a += 256)
+    for (int ax = 0; ax < 3; ++ax) {
+      mn[ax] = fmin(mn[ax], pos[3 * a + ax]);
+      mx[ax] = fmax(mx[ax], pos[3 * a + ax]);
+    }
+  for (int ax = 0; ax < 3; ++ax) { red[ax][threadIdx.x] = mn[ax]; red[3 + ax][threadIdx.x] = mx[ax]; }
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k)
+      for (int ax = 0; ax < 3; ++ax) {
+        red[ax][threadIdx.x] = fmin(red[ax][threadIdx.x], red[ax][threadIdx.x + k]);
+        red[3 + ax][threadIdx.x] = fmax(red[3 + ax][threadIdx.x], red[3 + ax][threadIdx.x + k]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[6 * s + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// One block per system: FP64 sum of a per-atom value (fixed tree order).
+__global__ __launch_bounds__(256) void k_system_sums(const double* __restrict__ v,
+                                                     const int64_t* __restrict__ off, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t a = off[s] + threadIdx.x; a < off[s + 1]; a += 256) acc += v[a];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[s] = red[0];
+}
+
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+hipError_t launch_system_bbox(const double* pos, const int64_t* offsets, int n_sys, double* out, hipStream_t s) {
+  if (n_sys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_system_bbox, dim3(n_sys), dim3(256), 0, s, pos, offsets, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_system_sums(const double* atom_value, const int64_t* offsets, int n_sys, double* out,
+                              hipStream_t s) {
+  if (n_sys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_system_sums, dim3(n_sys), dim3(256), 0, s, atom_value, offsets, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_bbox(const NbrArgs& a, int* n_blocks, hipStream_t s) {
   int nb = (int)grid_for(a.n_total, 256);

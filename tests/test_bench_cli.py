@@ -1,0 +1,25 @@
+"""bench.py refuses multi-GPU runs (this build measures one GPU's share)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_rejects_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_algorithmic_mac_counts():
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    macs = bench.mlp_macs_per_edge(W.model_config(3))
+    # two-body chain 16->256->256->256 plus the [embed0 | env1] head 256 -> 384
+    assert macs["mlp_fwd_twobody"] == 16 * 256 + 2 * 256 * 256 + 256 * 384
+    # latent chain (256+64)->256->256->256 plus the env2 head 256 -> 192
+    assert macs["mlp_fwd_latent"] == 320 * 256 + 2 * 256 * 256 + 256 * 192
+    assert macs["mlp_bwd_final"] == 320 * 256 + 2 * 256 * 256
