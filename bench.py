@@ -57,7 +57,7 @@ def mlp_macs_per_edge(mc):
     return out
 
 
-def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times):
+def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times, autotune=True):
     import torch
     import paper_2304_10061_amd as P
     import workloads as W
@@ -74,6 +74,11 @@ def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times):
         m.neighbors(pos, sp, s.cell, s.pbc, s.n_local)
         m.energy_forces(pos, sp, F, atom_energy=Ea, virial=vir, energy=E)
 
+    tiles = None
+    if autotune:
+        m.neighbors(pos, sp, s.cell, s.pbc, s.n_local)
+        tiles = m.autotune(pos, sp)
+
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -83,7 +88,7 @@ def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     res = {"ms_per_step": ms, "edges": m.num_edges(), "energy": float(E.item()),
-           "workspace_GB": m.workspace_bytes() / 1e9}
+           "workspace_GB": m.workspace_bytes() / 1e9, "tiles": tiles}
     if want_kernel_times:
         m.set_timing(True)
         reps = 3
@@ -132,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 and single-rounded BF16 comparisons")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the energy/force path runs on a single MI355X "
@@ -143,6 +148,7 @@ def main():
     mc, s, w = W.workload(3)
     bf = run_gpu(mc, s, w, 1, args.steps, args.warmup, want_kernel_times=True)
     fp = None if args.no_fp32 else run_gpu(mc, s, w, 0, max(3, args.steps // 4), min(2, args.warmup), True)
+    bs = None if args.no_fp32 else run_gpu(mc, s, w, 2, max(3, args.steps // 2), min(2, args.warmup), True)
 
     value = s.n_local / (bf["ms_per_step"] * 1e-3)
     macs = mlp_macs_per_edge(mc)
@@ -193,6 +199,12 @@ def main():
                        "mlp_gemm_ms": sum(v for k, v in fp["kernel_ms"].items() if k in macs),
                        "energy_bf16_minus_fp32_per_atom": (bf["energy"] - fp["energy"]) / s.n_local}
         out["bf16_speedup_vs_fp32"] = fp["ms_per_step"] / bf["ms_per_step"]
+    if bs is not None:
+        out["bf16_single_rounded_weights"] = {
+            "value": s.n_local / (bs["ms_per_step"] * 1e-3), "ms_per_step": bs["ms_per_step"],
+            "mlp_gemm_ms": sum(v for k, v in bs["kernel_ms"].items() if k in macs),
+            "energy_minus_fp32_per_atom": (bs["energy"] - fp["energy"]) / s.n_local}
+    out["tiles"] = bf["tiles"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mc, s, w, args.cpu_sample)
     print(json.dumps(out), flush=True)

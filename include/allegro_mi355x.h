@@ -46,7 +46,15 @@ enum {
   ALLEGRO_E_STATE = -6      /* call order violated (e.g. no neighbour list yet) */
 };
 
-enum { ALLEGRO_PREC_FP32 = 0, ALLEGRO_PREC_BF16 = 1 };
+/* Precision of the MLP GEMMs (everything else is the same in all modes):
+ *   FP32         FP32 MFMA.
+ *   BF16         BF16 MFMA with FP32 accumulation; activations rounded once to
+ *                BF16, each weight held as a pair of BF16 numbers (w = hi + lo)
+ *                and applied with two MFMAs, so the fixed rounding of the
+ *                weights does not bias every pair energy the same way.
+ *   BF16_SINGLE  BF16 MFMA with single-rounded weights (fastest; its energies
+ *                carry a systematic error from the weight rounding). */
+enum { ALLEGRO_PREC_FP32 = 0, ALLEGRO_PREC_BF16 = 1, ALLEGRO_PREC_BF16_SINGLE = 2 };
 
 typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
 
@@ -70,8 +78,7 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *                    1/sqrt(avg_num_neighbors)
  *   channel_mix      1 = per-irrep linear channel mixing after each tensor
  *                    product, 0 = none
- *   precision        ALLEGRO_PREC_FP32 or ALLEGRO_PREC_BF16 (MLP GEMMs in BF16
- *                    with FP32 accumulation)
+ *   precision        ALLEGRO_PREC_FP32, ALLEGRO_PREC_BF16 or ALLEGRO_PREC_BF16_SINGLE
  *   edge_chunk       0 = evaluate all edges at once; otherwise the largest
  *                    number of edges whose activations are held at a time
  *                    (whole centre segments; bounds workspace memory)
@@ -190,6 +197,19 @@ int allegro_system_energies(AllegroModel* m, const double* atom_energy, double* 
 int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* species,
                           double* atom_energy, double* forces, double* virial,
                           double* atom_virial, double* energy, void* stream);
+
+/*
+ * allegro_autotune: time the candidate edge-tile shapes of the edge-batched
+ * kernels (MLP chains: 64 or 32 edges per tile in BF16, 32 or 16 in FP32;
+ * tensor product / mixing: 32 or 16 edges) on the current neighbour list and
+ * keep the fastest for each kernel kind.  Runs allegro_energy_forces six times
+ * on internal buffers and synchronises the stream.
+ *   choices  host [8] int32 receiving the chosen tiles, in the order
+ *            mlp_fwd_twobody, mlp_fwd_latent, mlp_fwd_final, mlp_bwd_final,
+ *            mlp_bwd_latent, mlp_bwd_twobody, tp_mix, mix_adjoint (may be NULL)
+ */
+int allegro_autotune(AllegroModel* m, const double* pos, const int32_t* species, void* stream,
+                     int32_t* choices);
 
 /*
  * allegro_set_ghosts: declare ghosts as periodic images of local atoms, for

@@ -20,12 +20,12 @@ LIB_PATH = os.path.join(_HERE, "liballegro_mi355x.so")
 ALLEGRO_OK = 0
 STATUS = {0: "ALLEGRO_OK", -1: "ALLEGRO_E_INVAL", -2: "ALLEGRO_E_NOMEM", -3: "ALLEGRO_E_CAPACITY",
           -4: "ALLEGRO_E_DEVICE", -5: "ALLEGRO_E_NONFINITE", -6: "ALLEGRO_E_STATE"}
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_BF16_SINGLE = 0, 1, 2
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ("allegro_describe", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
            "allegro_system_energies", "allegro_energy_forces",
-           "allegro_set_ghosts", "allegro_md_run", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
+           "allegro_autotune", "allegro_set_ghosts", "allegro_md_run", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
            "allegro_workspace_bytes", "allegro_destroy", "allegro_last_error", "allegro_status_string")
 
 
@@ -77,6 +77,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_system_energies.restype = ctypes.c_int
     lib.allegro_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     lib.allegro_energy_forces.restype = ctypes.c_int
+    lib.allegro_autotune.argtypes = [vp, dp, dp, vp, vp]
+    lib.allegro_autotune.restype = ctypes.c_int
     lib.allegro_set_ghosts.argtypes = [vp, i64, i64, vp, vp]
     lib.allegro_set_ghosts.restype = ctypes.c_int
     lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, i32, i32, vp,
@@ -230,6 +232,14 @@ class Model:
         self._check(self.lib.allegro_energy_forces(self.handle, _ptr(pos), _ptr(species), _ptr(atom_energy),
                                                    _ptr(forces), _ptr(virial), _ptr(atom_virial),
                                                    _ptr(energy), _stream(stream)))
+
+    def autotune(self, pos, species, stream=None):
+        """Pick the fastest edge-tile shapes on the current neighbour list."""
+        ch = (ctypes.c_int32 * 8)()
+        self._check(self.lib.allegro_autotune(self.handle, _ptr(pos), _ptr(species), _stream(stream), ch))
+        names = ("mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd_final", "mlp_bwd_final", "mlp_bwd_latent",
+                 "mlp_bwd_twobody", "tp_mix", "mix_adjoint")
+        return dict(zip(names, list(ch)))
 
     def set_ghosts(self, n_local: int, owner, offset):
         """Ghost g = atom n_local + g is owner[g]'s image at offset[g] (host arrays)."""

@@ -77,20 +77,26 @@ void upload(DevBuf& b, const void* src, size_t bytes) {
 int rup(int v, int m) { return ((v + m - 1) / m) * m; }
 
 // Packs a K x N row-major matrix (y = x @ W) into MFMA B fragments.
+// prec 0: FP32; prec 1: BF16 pairs (hi fragments, then lo = W - hi); prec 2: BF16.
 void pack_b(const std::vector<double>& W, int K, int N, int prec, std::vector<char>& out, GemmB& g) {
   const int Kp = rup(K, 32), Np = rup(N, 32), nkb = Kp / 32;
   const size_t count = (size_t)Kp * Np;
   const int esz = prec ? 2 : 4;
-  out.assign(count * esz, 0);
+  out.assign(count * esz * (prec == 1 ? 2 : 1), 0);
   for (int k = 0; k < K; ++k)
     for (int n = 0; n < N; ++n) {
       const int nt = n / 16, kb = k / 32, lane = (n % 16) + 16 * ((k % 32) / 8), el = k % 8;
       const size_t idx = ((size_t)(nt * nkb + kb) * 64 + lane) * 8 + el;
-      const float v = (float)W[(size_t)k * N + n];
+      const double w = W[(size_t)k * N + n];
       if (prec) {
-        __bf16 b = (__bf16)v;
-        std::memcpy(out.data() + idx * 2, &b, 2);
+        const __bf16 hi = (__bf16)(float)w;
+        std::memcpy(out.data() + idx * 2, &hi, 2);
+        if (prec == 1) {
+          const __bf16 lo = (__bf16)(float)(w - (double)(float)hi);
+          std::memcpy(out.data() + (count + idx) * 2, &lo, 2);
+        }
       } else {
+        const float v = (float)w;
         std::memcpy(out.data() + idx * 4, &v, 4);
       }
     }
@@ -150,7 +156,9 @@ Validated validate(const AllegroConfig* c) {
   REQUIRE(v.h >= 1 && v.h <= 4096, "edge hidden width must be in 1..4096");
   REQUIRE(c->r_cut > 0 && std::isfinite(c->r_cut), "r_cut must be positive");
   REQUIRE(c->avg_num_neighbors > 0 && std::isfinite(c->avg_num_neighbors), "avg_num_neighbors must be positive");
-  REQUIRE(c->precision == ALLEGRO_PREC_FP32 || c->precision == ALLEGRO_PREC_BF16, "precision must be 0 or 1");
+  REQUIRE(c->precision == ALLEGRO_PREC_FP32 || c->precision == ALLEGRO_PREC_BF16 ||
+              c->precision == ALLEGRO_PREC_BF16_SINGLE,
+          "precision must be 0, 1 or 2");
   REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
   REQUIRE(c->neighbor_skin >= 0 && std::isfinite(c->neighbor_skin), "neighbor_skin must be >= 0");
   v.dim = (v.lmax + 1) * (v.lmax + 1);
@@ -260,12 +268,16 @@ struct AllegroModel {
   DevBuf chunk_rp;
   int64_t Ec = 0, Nc = 0;
 
+  // tile shapes chosen by allegro_autotune (0 = default)
+  int tm_choice[6] = {0, 0, 0, 0, 0, 0};   // MLP kernels, see kMlpSlotNames
+  int tt_choice[2] = {0, 0};               // tp_mix, mix_adjoint
+
   // molecular dynamics
   uint64_t nbr_version = 0;               // bumped by every neighbour build
   int64_t n_ghost = 0, ghost_n_local = 0;
   DevBuf g_owner, g_offset, g_ptr, g_idx; // ghost images and the owner -> ghosts CSR
   DevBuf pos_ref;                         // positions of the centres at the last neighbour build
-  DevBuf md_epot, md_part, md_counter, md_atom_e;
+  DevBuf md_epot, md_part, md_counter, md_atom_e, tune_forces;
   hipStream_t md_stream = nullptr;
   hipEvent_t md_ev[2] = {nullptr, nullptr};
   hipGraph_t md_graph = nullptr;
@@ -716,6 +728,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     MlpArgs m0 = base;
     m0.kind = kTwoBody; m0.w = m->twobody.view(); m0.head = m->head0.g; m0.head_bwd = m->head0T.g;
     m0.x_out = ptr<float>(m->x[0]); m0.head_out = ptr<float>(m->head0o);
+    m0.tm = m->tm_choice[0];
     timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, prec, s); });
 
     TensorArgs tb;
@@ -737,11 +750,12 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     MlpArgs m1 = base;
     if (v.nl == 2) {
       TensorArgs t1m = t1;
-      t1m.v = v_a0; t1m.tpw = ptr<float>(m->tpw[0]); t1m.mixB = m->mixF[0].p; t1m.v_out = ptr<float>(m->V1);
+      t1m.v = v_a0; t1m.tile = m->tt_choice[0]; t1m.tpw = ptr<float>(m->tpw[0]); t1m.mixB = m->mixF[0].p; t1m.v_out = ptr<float>(m->V1);
       timed(m, "tp_mix", s, [&] { return launch_tp_mix(t1m, false, s); });
       m1.kind = kLatent; m1.w = m->latent[0].view(); m1.head = m->env2.g; m1.head_bwd = m->env2T.g;
       m1.x_prev = ptr<float>(m->x[0]); m1.s_in = ptr<float>(m->V1); m1.s_ld = dim * n;
       m1.x_out = ptr<float>(m->x[1]); m1.head_out = ptr<float>(m->wenv2);
+      m1.tm = m->tm_choice[1];
       timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(m1, prec, s); });
       TensorArgs t2 = tb;
       t2.w_env = ptr<float>(m->wenv2); t2.ld_w = LW; t2.gam = ptr<float>(m->gam[1]);
@@ -750,6 +764,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     } else {
       mf.w = m->latent[0].view(); mf.x_prev = ptr<float>(m->x[0]); mf.tp_v = v_a0; mf.tp_gam = ptr<float>(m->gam[0]);
     }
+    mf.tm = m->tm_choice[2];
     timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, prec, s); });
 
     ReduceArgs ra;
@@ -759,6 +774,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
 
     // ---- adjoint ----
     mf.g_xprev = ptr<float>(m->gxa); mf.g_s = ptr<float>(m->gTf); mf.g_u = ptr<float>(m->gu); mf.gu_accum = 0;
+    mf.tm = m->tm_choice[3];
     timed(m, "mlp_bwd_final", s, [&] { return launch_mlp_bwd(mf, prec, s); });
 
     TensorArgs tf = tb;
@@ -777,11 +793,12 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     if (v.nl == 2) {
       m1.g_head = ptr<float>(m->gw2); m1.g_x = ptr<float>(m->gxa); m1.g_xprev = ptr<float>(m->gxb);
       m1.g_s = ptr<float>(m->gs); m1.g_u = ptr<float>(m->gu); m1.gu_accum = 1;
+      m1.tm = m->tm_choice[4];
       timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(m1, prec, s); });
       TensorArgs tm = tb;
       tm.g_tnext = ptr<float>(m->gTf); tm.gam_next = ptr<float>(m->gam[1]);
       for (int k = 0; k < 9; ++k) tm.tp_wnext[k] = m->tp_final[k];
-      tm.g_s = ptr<float>(m->gs); tm.mixB = m->mixB[0].p; tm.g_tout = ptr<float>(m->gT);
+      tm.g_s = ptr<float>(m->gs); tm.tile = m->tt_choice[1]; tm.mixB = m->mixB[0].p; tm.g_tout = ptr<float>(m->gT);
       timed(m, "mix_adjoint", s, [&] { return launch_mix_adjoint(tm, s); });
       TensorArgs t1b = tb;
       t1b.g_t = ptr<float>(m->gT); t1b.v = v_a0; t1b.gam = ptr<float>(m->gam[0]);
@@ -793,6 +810,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     }
     m0.g_head = ptr<float>(m->ghead0); m0.g_x = gx_two; m0.g_u = ptr<float>(m->gu); m0.gu_accum = 1;
     m0.g_R = ptr<float>(m->gR);
+    m0.tm = m->tm_choice[5];
     timed(m, "mlp_bwd_twobody", s, [&] { return launch_mlp_bwd(m0, prec, s); });
 
     ea.g_Y = ptr<float>(m->gY); ea.g_R = ptr<float>(m->gR); ea.g_u = ptr<float>(m->gu);
@@ -899,9 +917,67 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
   }
 }
 
+const char* const kTuneNames[8] = {"mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd_final", "mlp_bwd_final",
+                                   "mlp_bwd_latent", "mlp_bwd_twobody", "tp_mix", "mix_adjoint"};
+
+// Times every candidate tile shape on the current neighbour list and keeps the
+// fastest per kernel kind.
+void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, hipStream_t s, int32_t* choices) {
+  if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
+  REQUIRE((pos && species) || m->n_total == 0, "pos and species must not be NULL");
+  const int cand_tm[2] = {m->prec ? 64 : 32, m->prec ? 32 : 16};
+  const int cand_tt[2] = {32, 16};
+  m->tune_forces.ensure(std::max<int64_t>(m->n_total, 1) * 3 * sizeof(double));
+  m->md_epot.ensure(sizeof(double));
+  double best[8];
+  int pick[8];
+  for (int k = 0; k < 8; ++k) { best[k] = 1e300; pick[k] = 0; }
+  const bool was = m->timing;
+  for (int c = 0; c < 2; ++c) {
+    for (int k = 0; k < 6; ++k) m->tm_choice[k] = cand_tm[c];
+    for (int k = 0; k < 2; ++k) m->tt_choice[k] = cand_tt[c];
+    // warm-up, then two timed evaluations
+    m->timing = false;
+    energy_forces_impl(m, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
+                       ptr<double>(m->md_epot), s);
+    collect_times(m);
+    m->ktimes.clear();
+    m->timing = true;
+    for (int r = 0; r < 2; ++r)
+      energy_forces_impl(m, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
+                         ptr<double>(m->md_epot), s);
+    collect_times(m);
+    for (int k = 0; k < 8; ++k)
+      for (const auto& kt : m->ktimes)
+        if (kt.name == kTuneNames[k] && kt.ms < best[k]) {
+          best[k] = kt.ms;
+          pick[k] = k < 6 ? cand_tm[c] : cand_tt[c];
+        }
+    m->ktimes.clear();
+  }
+  m->timing = was;
+  for (int k = 0; k < 6; ++k) m->tm_choice[k] = pick[k];
+  for (int k = 0; k < 2; ++k) m->tt_choice[k] = pick[6 + k];
+  release_graph(m);
+  if (choices)
+    for (int k = 0; k < 8; ++k) choices[k] = pick[k];
+}
+
 }  // namespace
 
 extern "C" {
+
+int allegro_autotune(AllegroModel* m, const double* pos, const int32_t* species, void* stream, int32_t* choices) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    autotune_impl(m, pos, species, (hipStream_t)stream, choices);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  } catch (...) {
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
 
 int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const int32_t* owner,
                        const double* offset) {

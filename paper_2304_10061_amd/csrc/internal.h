@@ -53,6 +53,7 @@ struct VSrc {
 struct MlpArgs {
   int E = 0;                  // rows of this launch
   int kind = 0;
+  int tm = 0;                 // edge-tile rows (0 = largest that fits LDS)
   int d = 0, n = 0, l_max = 0, n_species = 0, n_bessel = 0;
   MlpW w;
   GemmB head;                 // forward head (none when head.p == nullptr)
@@ -106,6 +107,7 @@ struct EdgeArgs {
 
 struct TensorArgs {
   int E = 0;                      // edges of the chunk
+  int tile = 0;                   // edges per tile of the edge-tile kernels (16 or 32; 0 = 32)
   int n_centres = 0;
   int n = 0, l_max = 0;
   const int32_t* row_ptr = nullptr;  // [n_centres+1], chunk-relative
@@ -143,6 +145,7 @@ hipError_t launch_edge_adjoint(const EdgeArgs& a, hipStream_t s);
 hipError_t launch_mlp_fwd(const MlpArgs& a, int prec, hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpArgs& a, int prec, hipStream_t s);
 size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd);
+bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm);
 hipError_t launch_env(const TensorArgs& a, hipStream_t s);
 hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s);
 hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s);

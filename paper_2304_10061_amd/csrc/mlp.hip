@@ -43,6 +43,9 @@ template <> struct PT<1> {
   }
 };
 
+// PREC 2: BF16 operands with single-rounded weights (no low-order correction).
+template <> struct PT<2> : PT<1> {};
+
 template <> struct PT<0> {
   using T = float;
   struct F { f32x4 lo, hi; };
@@ -96,20 +99,30 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
   }
   const int nkb = B.Kp >> 5, nct = B.Np >> 4;
   if (kb1 < 0) kb1 = nkb;
+  // PREC 1 keeps each weight as a pair of BF16 values (hi + lo, lo stored
+  // after the hi fragments) and issues two MFMAs per product.
+  constexpr bool kSplit = PREC == 1;
+  const size_t lo_off = (size_t)B.Kp * B.Np;
   const T* Bl = (const T*)B.p + (size_t)lane * 8;
   const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4) - kb0 * 32;
-  F bc[MAXCT], bn[MAXCT];
+  F bc[MAXCT], bn[MAXCT], lc[kSplit ? MAXCT : 1], ln[kSplit ? MAXCT : 1];
 #pragma unroll
   for (int q = 0; q < MAXCT; ++q) {
     const int nt = tile_of<MAXCT>(pass, q, wave);
-    if (nt < nct) bc[q] = P::load(Bl + (size_t)(nt * nkb + kb0) * 512);
+    if (nt < nct) {
+      bc[q] = P::load(Bl + (size_t)(nt * nkb + kb0) * 512);
+      if constexpr (kSplit) lc[q] = P::load(Bl + lo_off + (size_t)(nt * nkb + kb0) * 512);
+    }
   }
   for (int kb = kb0; kb < kb1; ++kb) {
     if (kb + 1 < kb1) {
 #pragma unroll
       for (int q = 0; q < MAXCT; ++q) {
         const int nt = tile_of<MAXCT>(pass, q, wave);
-        if (nt < nct) bn[q] = P::load(Bl + (size_t)(nt * nkb + kb + 1) * 512);
+        if (nt < nct) {
+          bn[q] = P::load(Bl + (size_t)(nt * nkb + kb + 1) * 512);
+          if constexpr (kSplit) ln[q] = P::load(Bl + lo_off + (size_t)(nt * nkb + kb + 1) * 512);
+        }
       }
     }
     F a[RT];
@@ -120,51 +133,118 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
       const int nt = tile_of<MAXCT>(pass, q, wave);
       if (nt < nct) {
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(a[rt], bc[q], acc[rt][q]);
+        for (int rt = 0; rt < RT; ++rt) {
+          if constexpr (kSplit) acc[rt][q] = P::mma(a[rt], lc[q], acc[rt][q]);
+          acc[rt][q] = P::mma(a[rt], bc[q], acc[rt][q]);
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < MAXCT; ++q) bc[q] = bn[q];
+    for (int q = 0; q < MAXCT; ++q) {
+      bc[q] = bn[q];
+      if constexpr (kSplit) lc[q] = ln[q];
+    }
   }
 }
 
 template <class T> __device__ __forceinline__ T to_t(float v) { return (T)v; }
 
-// Input rows of the chain for edges e0 .. e0+TM-1, zero padded to Kp.
+__device__ __forceinline__ void store4(__bf16* p, float4 v) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  bf16x4 b = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+  *(bf16x4*)p = b;
+}
+__device__ __forceinline__ void store4(float* p, float4 v) { *(float4*)p = v; }
+
+// Four consecutive input columns c..c+3 (c a multiple of 4) of edge e.
+__device__ __forceinline__ float4 input4(const MlpArgs& a, int e, int c) {
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (e >= a.E) return v;
+  if (a.kind == kTwoBody) {
+    const int S = a.n_species, zi = a.species[a.ei[e]], zj = a.species[a.ej[e]];
+    float t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int cc = c + k;
+      float x = 0.0f;
+      if (cc < S) x = zi == cc ? 1.0f : 0.0f;
+      else if (cc < 2 * S) x = zj == cc - S ? 1.0f : 0.0f;
+      else if (cc < 2 * S + a.n_bessel) x = a.eb[(size_t)e * kEB + kEB_R + (cc - 2 * S)];
+      t[k] = x;
+    }
+    return make_float4(t[0], t[1], t[2], t[3]);
+  }
+  if (c < a.d) return *(const float4*)(a.x_prev + (size_t)e * a.d + c);
+  if (c >= a.d + a.n) return v;
+  const int u = c - a.d;
+  if (a.kind == kLatent) return *(const float4*)(a.s_in + (size_t)e * a.s_ld + u);
+  // final-layer scalar tensor product: T[u] = sum_c w_c V[c][u] Gamma[c][u]
+  const int dim = (a.l_max + 1) * (a.l_max + 1);
+  const float* gam = a.tp_gam + (size_t)(a.ei[e] - a.centre_base) * dim * a.n + u;
+  const float* vp = a.tp_v.p + (size_t)e * a.tp_v.ld + u;
+  const float* Y = a.eb + (size_t)e * kEB;
+  for (int cc = 0; cc < dim; ++cc) {
+    const int l = cc == 0 ? 0 : (cc < 4 ? 1 : 2);
+    float4 vv = a.tp_v.from_a0 ? *(const float4*)(vp + l * a.n) : *(const float4*)(vp + cc * a.n);
+    const float y = a.tp_v.from_a0 ? Y[cc] : 1.0f;
+    const float4 g = *(const float4*)(gam + cc * a.n);
+    const float w = a.tp_w[cc] * y;
+    v.x = fmaf(w * vv.x, g.x, v.x);
+    v.y = fmaf(w * vv.y, g.y, v.y);
+    v.z = fmaf(w * vv.z, g.z, v.z);
+    v.w = fmaf(w * vv.w, g.w, v.w);
+  }
+  return v;
+}
+
+// Input rows of the chain for edges e0 .. e0+TM-1, zero padded to Kp.  Each
+// wave fills TM/4 rows; a lane gathers 16-byte chunks of four rows before
+// storing them, so several global loads are in flight per lane.
 template <int PREC, int TM>
-__device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int lda, int e0, int Kp) {
-  using T = typename PT<PREC>::T;
-  const int S = a.n_species;
-  for (int idx = threadIdx.x; idx < TM * Kp; idx += 256) {
-    const int r = idx / Kp, c = idx - r * Kp;
-    const int e = e0 + r;
-    float v = 0.0f;
-    if (e < a.E) {
-      if (a.kind == kTwoBody) {
-        if (c < S) v = (a.species[a.ei[e]] == c) ? 1.0f : 0.0f;
-        else if (c < 2 * S) v = (a.species[a.ej[e]] == c - S) ? 1.0f : 0.0f;
-        else if (c < 2 * S + a.n_bessel) v = a.eb[(size_t)e * kEB + kEB_R + (c - 2 * S)];
-      } else if (c < a.d) {
-        v = a.x_prev[(size_t)e * a.d + c];
-      } else if (c < a.d + a.n) {
-        const int u = c - a.d;
-        if (a.kind == kLatent) {
-          v = a.s_in[(size_t)e * a.s_ld + u];
-        } else {
-          // final-layer scalar tensor product: T = sum_c w_c V[c][u] Gamma[c][u]
-          const int dim = (a.l_max + 1) * (a.l_max + 1);
-          const float* gam = a.tp_gam + (size_t)(a.ei[e] - a.centre_base) * dim * a.n + u;
-          const float* vp = a.tp_v.p + (size_t)e * a.tp_v.ld + u;
-          const float* Y = a.eb + (size_t)e * kEB;
-          for (int cc = 0; cc < dim; ++cc) {
-            const int l = cc == 0 ? 0 : (cc < 4 ? 1 : 2);
-            const float vv = a.tp_v.from_a0 ? vp[l * a.n] * Y[cc] : vp[cc * a.n];
-            v = fmaf(a.tp_w[cc] * vv, gam[cc * a.n], v);
-          }
-        }
+__device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int RPW = TM / 4;
+  const int nq = Kp >> 2;
+  for (int q0 = 0; q0 < nq; q0 += 64) {
+    const int q = q0 + lane;
+    for (int r0 = 0; r0 < RPW; r0 += 4) {
+      float4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = wave * RPW + r0 + k;
+        v[k] = q < nq ? input4(a, e0 + r, 4 * q) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+      if (q < nq) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store4(X + (wave * RPW + r0 + k) * ldx + 4 * q, v[k]);
       }
     }
-    X[r * lda + c] = to_t<T>(v);
+  }
+}
+
+// Rows of a row-major FP32 matrix (row stride ld) into X, columns [c0, c0+w).
+template <int PREC, int TM>
+__device__ void stage_rows(const float* src, int ld, int ncols, int E, typename PT<PREC>::T* X, int ldx,
+                           int e0, int c0, int w) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int RPW = TM / 4;
+  const int nq = w >> 2;
+  for (int q0 = 0; q0 < nq; q0 += 64) {
+    const int q = q0 + lane;
+    for (int r0 = 0; r0 < RPW; r0 += 4) {
+      float4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = e0 + wave * RPW + r0 + k;
+        const int c = c0 + 4 * q;
+        v[k] = (q < nq && e < E && c < ncols) ? *(const float4*)(src + (size_t)e * ld + c)
+                                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+      if (q < nq) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) store4(X + (wave * RPW + r0 + k) * ldx + 4 * q, v[k]);
+      }
+    }
   }
 }
 
@@ -343,13 +423,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
     for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
       const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
       const int w = (kb1 - kb0) * 32;
-      for (int idx = threadIdx.x; idx < TM * w; idx += 256) {
-        const int r = idx / w, c = idx - r * w;
-        const int e = e0 + r, cc = kb0 * 32 + c;
-        float v = 0.0f;
-        if (e < a.E && cc < Kh) v = a.g_head[(size_t)e * Kh + cc];
-        X[r * ldx + c] = to_t<T>(v);
-      }
+      stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, w);
       __syncthreads();
       gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, true);
 #pragma unroll
@@ -501,14 +575,27 @@ int pick_tm(const MlpArgs& a, bool bwd) {
   return 0;
 }
 
+template <int PREC>
+bool fits(const MlpArgs& a, bool bwd, int tm) {
+  int ldx, ldh;
+  size_t bytes;
+  lds_dims<PREC>(a, tm, bwd, &ldx, &ldh, &bytes);
+  return bytes <= kLdsLimit;
+}
+
 hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
   if (a.E <= 0) return hipSuccess;
-  if (prec == 1) {
-    const int tm = pick_tm<1>(a, bwd);
-    if (tm == 64) return dispatch_ct<1, 64>(a, bwd, s);
-    if (tm == 32) return dispatch_ct<1, 32>(a, bwd, s);
+  if (prec == 1 || prec == 2) {
+    const int tm = (a.tm == 64 || a.tm == 32) && fits<1>(a, bwd, a.tm) ? a.tm : pick_tm<1>(a, bwd);
+    if (prec == 1) {
+      if (tm == 64) return dispatch_ct<1, 64>(a, bwd, s);
+      if (tm == 32) return dispatch_ct<1, 32>(a, bwd, s);
+    } else {
+      if (tm == 64) return dispatch_ct<2, 64>(a, bwd, s);
+      if (tm == 32) return dispatch_ct<2, 32>(a, bwd, s);
+    }
   } else {
-    const int tm = pick_tm<0>(a, bwd);
+    const int tm = (a.tm == 32 || a.tm == 16) && fits<0>(a, bwd, a.tm) ? a.tm : pick_tm<0>(a, bwd);
     if (tm == 32) return dispatch_ct<0, 32>(a, bwd, s);
     if (tm == 16) return dispatch_ct<0, 16>(a, bwd, s);
   }
@@ -525,6 +612,11 @@ size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd) {
   if (prec) lds_dims<1>(a, tm, bwd, &ldx, &ldh, &bytes);
   else lds_dims<0>(a, tm, bwd, &ldx, &ldh, &bytes);
   return bytes;
+}
+
+bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm) {
+  if (prec) return (tm == 64 || tm == 32) && fits<1>(a, bwd, tm);
+  return (tm == 32 || tm == 16) && fits<0>(a, bwd, tm);
 }
 
 hipError_t launch_mlp_fwd(const MlpArgs& a, int prec, hipStream_t s) { return launch(a, prec, false, s); }

@@ -22,7 +22,7 @@ from gpu_helpers import gpu_edges, gpu_eval, gpu_model, to_dev
 
 pytestmark = pytest.mark.gpu
 
-FP32, BF16 = P.PREC_FP32, P.PREC_BF16
+FP32, BF16, BF16S = P.PREC_FP32, P.PREC_BF16, P.PREC_BF16_SINGLE
 
 
 def _report(tag, **kw):
@@ -82,7 +82,7 @@ def _nbr_cases():
 @pytest.mark.parametrize("case", _nbr_cases(), ids=lambda c: c[0])
 def test_neighbors_bit_exact(case):
     name, s, rc = case
-    mc = W.ModelConfig(n_species=2, r_cut=rc, l_max=1, n_layers=1, n_tensor=8,
+    mc = W.ModelConfig(n_species=4, r_cut=rc, l_max=1, n_layers=1, n_tensor=8,
                        twobody_dims=(32, 32), latent_dims=(32, 32))
     w = W.make_weights(mc, np.random.default_rng(0))
     m = gpu_model(mc, w, FP32)
@@ -126,6 +126,17 @@ def test_bf16_water_box(cfg2):
     m = gpu_model(mc, w, BF16, sc, sh)
     got = gpu_eval(m, s)
     _check_bf16("cfg2_bf16", got, ref, s.n_local)
+
+
+def test_bf16_single_rounded_weights_forces(cfg2):
+    """Single-rounded BF16 weights: forces stay within 1 % RMS; the energy
+    carries the systematic weight-rounding error (reported, not gated)."""
+    mc, s, w, sc, sh, ref = cfg2
+    got = gpu_eval(gpu_model(mc, w, BF16S, sc, sh), s)
+    dE = abs(float(got["energy"][0]) - ref.energy) / s.n_local
+    rel = float(np.sqrt(((got["forces"] - ref.forces) ** 2).mean()) / np.sqrt((ref.forces ** 2).mean()))
+    _report("cfg2_bf16_single", dE_per_atom=dE, force_rel_rms=rel)
+    assert rel <= 0.01
 
 
 def test_chunked_equals_whole(cfg2):
@@ -185,8 +196,9 @@ def test_clusters_and_ghost_shell_fp32():
     a, b = gpu_eval(m, s), gpu_eval(m, g)
     F = b["forces"][:s.n_local].copy()
     np.add.at(F, g.ghost_owner, b["forces"][s.n_local:])
-    assert np.abs(a["atom_energy"] - b["atom_energy"]).max() < 1e-9
-    assert np.abs(F - a["forces"]).max() < 1e-5
+    # identical up to FP32 summation order (neighbour order differs)
+    assert np.abs(a["atom_energy"] - b["atom_energy"]).max() < 1e-5
+    assert np.abs(F - a["forces"]).max() < 1e-4
 
 
 def test_empty_and_isolated():
