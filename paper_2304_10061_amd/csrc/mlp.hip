@@ -81,9 +81,11 @@ template <int MAXCT>
 __device__ __forceinline__ int npasses(int Np) { return (Np / 16 + 4 * MAXCT - 1) / (4 * MAXCT); }
 
 // acc[rt][q] = A[TM x K-range] (LDS) @ B[K-range x tiles of this pass].
-// A holds the columns of K blocks [kb0, kb1) starting at its column 0.  The B
-// fragments of the next K block are requested before the MFMAs of the
-// current one, so L2 latency overlaps matrix-core work.
+// A holds the columns of K blocks [kb0, kb1) starting at its column 0.  The
+// loop is branch-free: column tiles beyond the matrix are clamped to its last
+// tile (their results are never stored), and the B fragments of the next K
+// block are requested before the MFMAs of the current one, so L2 latency
+// overlaps matrix-core work.  `wave` must be wave-uniform (readfirstlane).
 template <int PREC, int RT, int MAXCT>
 __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
                                           int lda, const GemmB& B, int wave, int lane, int pass,
@@ -105,46 +107,46 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
   const size_t lo_off = (size_t)B.Kp * B.Np;
   const T* Bl = (const T*)B.p + (size_t)lane * 8;
   const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4) - kb0 * 32;
-  F bc[MAXCT], bn[MAXCT], lc[kSplit ? MAXCT : 1], ln[kSplit ? MAXCT : 1];
+  size_t boff[MAXCT];
 #pragma unroll
   for (int q = 0; q < MAXCT; ++q) {
-    const int nt = tile_of<MAXCT>(pass, q, wave);
-    if (nt < nct) {
-      bc[q] = P::load(Bl + (size_t)(nt * nkb + kb0) * 512);
-      if constexpr (kSplit) lc[q] = P::load(Bl + lo_off + (size_t)(nt * nkb + kb0) * 512);
-    }
+    int nt = tile_of<MAXCT>(pass, q, wave);
+    nt = nt < nct ? nt : nct - 1;
+    boff[q] = (size_t)(nt * nkb) * 512;
   }
-  for (int kb = kb0; kb < kb1; ++kb) {
-    if (kb + 1 < kb1) {
+  // two register buffers of B fragments, used alternately (no copies)
+  F b0[MAXCT], b1[MAXCT], l0[kSplit ? MAXCT : 1], l1[kSplit ? MAXCT : 1];
+  auto load_b = [&](F (&bb)[MAXCT], F (&ll)[kSplit ? MAXCT : 1], int kb) {
 #pragma unroll
-      for (int q = 0; q < MAXCT; ++q) {
-        const int nt = tile_of<MAXCT>(pass, q, wave);
-        if (nt < nct) {
-          bn[q] = P::load(Bl + (size_t)(nt * nkb + kb + 1) * 512);
-          if constexpr (kSplit) ln[q] = P::load(Bl + lo_off + (size_t)(nt * nkb + kb + 1) * 512);
-        }
-      }
+    for (int q = 0; q < MAXCT; ++q) {
+      bb[q] = P::load(Bl + boff[q] + (size_t)kb * 512);
+      if constexpr (kSplit) ll[q] = P::load(Bl + lo_off + boff[q] + (size_t)kb * 512);
     }
+  };
+  auto compute = [&](const F (&bb)[MAXCT], const F (&ll)[kSplit ? MAXCT : 1], int kb) {
     F a[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) a[rt] = P::load(Arow + rt * 16 * lda + kb * 32);
+    if constexpr (kSplit) {
 #pragma unroll
-    for (int q = 0; q < MAXCT; ++q) {
-      const int nt = tile_of<MAXCT>(pass, q, wave);
-      if (nt < nct) {
+      for (int q = 0; q < MAXCT; ++q)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          if constexpr (kSplit) acc[rt][q] = P::mma(a[rt], lc[q], acc[rt][q]);
-          acc[rt][q] = P::mma(a[rt], bc[q], acc[rt][q]);
-        }
-      }
+        for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(a[rt], ll[q], acc[rt][q]);
     }
 #pragma unroll
-    for (int q = 0; q < MAXCT; ++q) {
-      bc[q] = bn[q];
-      if constexpr (kSplit) lc[q] = ln[q];
-    }
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(a[rt], bb[q], acc[rt][q]);
+  };
+  load_b(b0, l0, kb0);
+  int kb = kb0;
+  for (; kb + 1 < kb1; kb += 2) {
+    load_b(b1, l1, kb + 1);
+    compute(b0, l0, kb);
+    load_b(b0, l0, kb + 2 < kb1 ? kb + 2 : kb + 1);   // the last pass reloads a block it has
+    compute(b1, l1, kb + 1);
   }
+  if (kb < kb1) compute(b0, l0, kb);
 }
 
 template <class T> __device__ __forceinline__ T to_t(float v) { return (T)v; }
@@ -202,7 +204,7 @@ __device__ __forceinline__ float4 input4(const MlpArgs& a, int e, int c) {
 // storing them, so several global loads are in flight per lane.
 template <int PREC, int TM>
 __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int RPW = TM / 4;
   const int nq = Kp >> 2;
   for (int q0 = 0; q0 < nq; q0 += 64) {
@@ -226,7 +228,7 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
 template <int PREC, int TM>
 __device__ void stage_rows(const float* src, int ld, int ncols, int E, typename PT<PREC>::T* X, int ldx,
                            int e0, int c0, int w) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int RPW = TM / 4;
   const int nq = w >> 2;
   for (int q0 = 0; q0 < nq; q0 += 64) {
@@ -298,7 +300,7 @@ __device__ __forceinline__ const typename PT<PREC>::T* hidden_layers(
 }
 
 template <int PREC, int TM, int MAXCT>
-__global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
+__global__ __launch_bounds__(256, 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
   T* X = (T*)smem;
   T* H = X + TM * ldx;
   __shared__ float red[4][TM];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
 
   build_input<PREC, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 }
 
 template <int PREC, int TM, int MAXCT>
-__global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
+__global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   T* H = X + TM * ldx;
   T* Pb = H + TM * ldh;                 // nl-1 pre-activation buffers [TM][ldh]
   __shared__ float red[4][TM];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
   const int d = a.d;
   const int nl = a.w.nl;

@@ -100,7 +100,7 @@ __device__ void mix_tile(const float* S, int lds_ld, const float* Bbase, int b_s
                          int Np, float scale, float* out, int64_t e0, int E) {
   constexpr int RT = TT / 16;
   constexpr int MAXKB = 2;   // K = n <= 64
-  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
   const int nct = Np >> 4, nkb = Kp >> 5;
   const int items = DIM * nct;
   float bc[MAXKB][8], bn[MAXKB][8];
