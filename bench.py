@@ -130,6 +130,101 @@ def cpu_baseline(mc, s, w, n_centres):
                       f"edges, energy + edge gradients in FP64), {t:.1f} s"}
 
 
+def md_workload(kind, steps, warmup, dt_fs, precision=1):
+    """One GPU's MD share: the 1M-atom subdomain with its ghost shell (rebuild
+    every step), or 512 uneven clusters in one batched evaluation (hipGraph
+    replay between neighbour rebuilds)."""
+    import torch
+    import paper_2304_10061_amd as P
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    cfg = 4 if kind == "subdomain" else 5
+    mc = W.model_config(cfg)
+    w = W.make_weights(mc, W.seeds(cfg)[3])
+    t_gen = time.perf_counter()
+    if kind == "subdomain":
+        base = W.jittered_lattice_box(1_000_000, 215.0, 0.5, W.PROTEIN_MIX, 4, sites_per_side=100)
+        sysm = W.ghost_shell(base, 6.0)
+        skin, rebuild = 0.3, 1
+        chunk = 8_000_000
+        masses = base.masses
+    else:
+        sysm = W.clusters(512, 5)
+        skin, rebuild = 1.0, 10
+        chunk = 0
+        masses = sysm.masses
+    t_gen = time.perf_counter() - t_gen
+    nl = sysm.n_local
+    free0, total = torch.cuda.mem_get_info()
+    m = P.Model(P.config_from(mc, precision=precision, edge_chunk=chunk, neighbor_skin=skin), W.pack_weights(mc, w))
+    pos = torch.as_tensor(sysm.pos, dtype=torch.float64, device=dev)
+    sp = torch.as_tensor(sysm.species, dtype=torch.int32, device=dev)
+    vel = torch.as_tensor(W.maxwell_boltzmann(masses, 300.0, W.seeds(cfg)[4]), dtype=torch.float64, device=dev)
+    mass = torch.as_tensor(masses, dtype=torch.float64, device=dev)
+    F = torch.zeros((sysm.n_total, 3), dtype=torch.float64, device=dev)
+    n_total_steps = warmup + steps
+    thermo = torch.zeros((n_total_steps, 2), dtype=torch.float64, device=dev)
+
+    def build():
+        if kind == "subdomain":
+            return m.neighbors(pos, sp, sysm.cell, sysm.pbc, nl)
+        return m.neighbors_batched(sysm.atom_offsets, pos, sp)
+
+    tiles = None
+    if kind == "subdomain":
+        own = sysm.ghost_owner
+        m.set_ghosts(nl, own, sysm.pos[nl:] - base.pos[own])
+    build()
+    if kind == "clusters":
+        tiles = m.autotune(pos, sp)
+    disp_max, edges = 0.0, []
+    done = 0
+    first = True
+    torch.cuda.synchronize()
+    t0 = None
+    while done < n_total_steps:
+        if done == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        k = min(rebuild, n_total_steps - done)
+        if done % rebuild == 0 and not first:
+            edges.append(build())
+        elif first:
+            edges.append(m.num_edges())
+        d = m.md_run(k, dt_fs, mass, pos, vel, F, sp, thermo=thermo[done:done + k], init_forces=first,
+                     use_graph=(kind == "clusters"), want_max_disp=True)
+        disp_max = max(disp_max, d)
+        first = False
+        done += k
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    free1, _ = torch.cuda.mem_get_info()
+    th = thermo.cpu().numpy()
+    etot = th[:, 0] + th[:, 1]
+    ms = elapsed * 1e3 / steps
+    out = {
+        "metric": "atom-steps/s (E+forces+FP64 velocity Verlet)",
+        "value": nl / (ms * 1e-3), "unit": "atom-steps/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": ("1,000,000-atom protein-like subdomain (215 A) + 6 A periodic-image ghost shell, "
+                                "model r_c 4 A, n 32, latent [128,128], neighbour list rebuilt every step"
+                                if kind == "subdomain" else
+                                "512 non-periodic clusters (20-2000 atoms, log-uniform), batched, hipGraph replay "
+                                "of the velocity-Verlet step, neighbour rebuild every 10 steps"),
+                   "atoms": int(nl), "ghosts": int(sysm.n_total - nl), "dt_fs": dt_fs,
+                   "neighbor_skin": skin, "edges_mean": float(np.mean(edges)) if edges else None},
+        "peak_hbm_GB": (free0 - free1) / 1e9,
+        "library_workspace_GB": m.workspace_bytes() / 1e9,
+        "energy_drift_per_atom": float((etot[-1] - etot[0]) / nl),
+        "energy_fluct_per_atom": float(np.std(etot) / nl),
+        "max_displacement_between_rebuilds": disp_max,
+        "tiles": tiles, "setup_s": t_gen,
+    }
+    m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,11 +233,18 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 and single-rounded BF16 comparisons")
+    ap.add_argument("--workload", default="protein-box", choices=["protein-box", "subdomain", "clusters"],
+                    help="protein-box (default, the headline); subdomain / clusters run MD")
+    ap.add_argument("--dt", type=float, default=1.0, help="MD time step (fs) for the MD workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the energy/force path runs on a single MI355X "
               "(spatial decomposition across GPUs is not part of this build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload != "protein-box":
+        print(json.dumps(md_workload(args.workload, args.steps, args.warmup, args.dt)), flush=True)
+        return
 
     import workloads as W
     mc, s, w = W.workload(3)

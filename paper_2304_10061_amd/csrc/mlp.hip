@@ -147,6 +147,13 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
     compute(b1, l1, kb + 1);
   }
   if (kb < kb1) compute(b0, l0, kb);
+  // tiles clamped onto the last one hold copies: zero them so that register
+  // uses of acc (gradients, dot products) see exact zeros there
+#pragma unroll
+  for (int q = 0; q < MAXCT; ++q)
+    if (tile_of<MAXCT>(pass, q, wave) >= nct)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 }
 
 template <class T> __device__ __forceinline__ T to_t(float v) { return (T)v; }
