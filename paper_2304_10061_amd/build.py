@@ -20,6 +20,9 @@ ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: avoids AGPR<->VGPR copies of
+         # the accumulators around the GEMM loops
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-result"]
 
 SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "tensor.hip", "md.hip"]

@@ -250,6 +250,7 @@ struct AllegroModel {
   DevBuf mixF[2], mixB[2];                // packed FP32 mixing matrices per layer
   int mix_stride = 0;
   DevBuf tpw[2];                          // fused coupling non-zeros per layer
+  std::vector<float> tpw_host[2];
   float tp_final[9] = {0};                // final-layer diagonal weights
   DevBuf we, gconst, scale, shift;
   double c_norm = 1.0;
@@ -411,6 +412,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     int nnz = 0;
     std::vector<float> vals = fused_values_rt(v.lmax, fin, alpha[L].data(), &nnz);
     upload(m->tpw[L], vals.data(), vals.size() * sizeof(float));
+    m->tpw_host[L] = vals;
     if (fin) {
       // final pattern entries are (a, a, 0) in ascending a
       for (int k = 0; k < 9; ++k) m->tp_final[k] = k < nnz ? vals[k] : 0.0f;
@@ -451,6 +453,10 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
 }
 
 template <class T> T* ptr(const DevBuf& b, int64_t off = 0) { return b.as<T>() + off; }
+
+void set_tpw(TensorArgs& t, const std::vector<float>& v) {
+  for (size_t k = 0; k < v.size() && k < 83; ++k) t.tpw_v[k] = v[k];
+}
 
 // Runs `launch` and, when timing is on, brackets it with events on `s`.
 template <class Fn>
@@ -750,7 +756,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     MlpArgs m1 = base;
     if (v.nl == 2) {
       TensorArgs t1m = t1;
-      t1m.v = v_a0; t1m.tile = m->tt_choice[0]; t1m.tpw = ptr<float>(m->tpw[0]); t1m.mixB = m->mixF[0].p; t1m.v_out = ptr<float>(m->V1);
+      t1m.v = v_a0; t1m.tile = m->tt_choice[0]; t1m.tpw = ptr<float>(m->tpw[0]); set_tpw(t1m, m->tpw_host[0]); t1m.mixB = m->mixF[0].p; t1m.v_out = ptr<float>(m->V1);
       timed(m, "tp_mix", s, [&] { return launch_tp_mix(t1m, false, s); });
       m1.kind = kLatent; m1.w = m->latent[0].view(); m1.head = m->env2.g; m1.head_bwd = m->env2T.g;
       m1.x_prev = ptr<float>(m->x[0]); m1.s_in = ptr<float>(m->V1); m1.s_ld = dim * n;
@@ -780,6 +786,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     TensorArgs tf = tb;
     tf.g_t = ptr<float>(m->gTf); tf.g_Y = ptr<float>(m->gY); tf.gy_accum = 0;
     tf.tpw = ptr<float>(m->tpw[v.nl - 1]);
+    set_tpw(tf, m->tpw_host[v.nl - 1]);
     if (v.nl == 2) {
       tf.v = v_1; tf.gam = ptr<float>(m->gam[1]); tf.w_env = ptr<float>(m->wenv2); tf.ld_w = LW;
       tf.g_w = ptr<float>(m->gw2); tf.ld_gw = LW;
@@ -802,7 +809,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
       timed(m, "mix_adjoint", s, [&] { return launch_mix_adjoint(tm, s); });
       TensorArgs t1b = tb;
       t1b.g_t = ptr<float>(m->gT); t1b.v = v_a0; t1b.gam = ptr<float>(m->gam[0]);
-      t1b.w_env = ptr<float>(m->head0o) + LW; t1b.ld_w = 2 * LW; t1b.tpw = ptr<float>(m->tpw[0]);
+      t1b.w_env = ptr<float>(m->head0o) + LW; t1b.ld_w = 2 * LW; t1b.tpw = ptr<float>(m->tpw[0]); set_tpw(t1b, m->tpw_host[0]);
       t1b.g_w = ptr<float>(m->ghead0) + LW; t1b.ld_gw = 2 * LW; t1b.g_a0 = ptr<float>(m->ghead0);
       t1b.g_Y = ptr<float>(m->gY); t1b.gy_accum = 1;
       timed(m, "tp_env_adjoint", s, [&] { return launch_tp_env_adjoint(t1b, false, s); });

@@ -49,9 +49,12 @@ __device__ __forceinline__ float group_inner_sum(float v, int width) {
   return v;
 }
 
-__device__ __forceinline__ float silu(float x) { return x / (1.0f + __expf(-x)); }
+// SiLU and its derivative with the hardware reciprocal (1 ulp) instead of an
+// IEEE division.
+__device__ __forceinline__ float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+__device__ __forceinline__ float silu(float x) { return x * sigmoid(x); }
 __device__ __forceinline__ float silu_grad(float x) {
-  const float s = 1.0f / (1.0f + __expf(-x));
+  const float s = sigmoid(x);
   return s * (1.0f + x * (1.0f - s));
 }
 

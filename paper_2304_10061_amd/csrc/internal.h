@@ -120,6 +120,7 @@ struct TensorArgs {
   float* gam = nullptr;           // [n_centres][dim][n]
   VSrc v;                         // tensor-product input
   const float* tpw = nullptr;     // device: non-zero weights of the fused table
+  float tpw_v[83] = {0};          // the same values, passed by value (kernel argument)
   const void* mixB = nullptr;     // packed FP32 mixing matrices, one GemmB block per l
   int mix_stride = 0;             // floats between consecutive l blocks
   int channel_mix = 1;

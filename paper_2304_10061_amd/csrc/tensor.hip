@@ -128,9 +128,10 @@ __device__ void mix_tile(const float* S, int lds_ld, const float* Bbase, int b_s
         const float* ap = S + (size_t)c * TT * lds_ld + (lane & 15) * lds_ld + kb * 32 + 8 * (lane >> 4);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-          float af[8];
-#pragma unroll
-          for (int s = 0; s < 8; ++s) af[s] = ap[rt * 16 * lds_ld + s];
+          // two 16-byte LDS reads (row stride = 4 mod 64 banks: conflict-free)
+          const float4 lo = *(const float4*)(ap + rt * 16 * lds_ld);
+          const float4 hi = *(const float4*)(ap + rt * 16 * lds_ld + 4);
+          const float af[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
           acc[rt] = mma8(af, bc[kb], acc[rt]);
         }
       }
@@ -160,9 +161,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
   extern __shared__ __align__(16) float S[];   // [DIM][TT][lds_ld]
   const int64_t e0 = (int64_t)blockIdx.x * TT;
   const int n = a.n;
-  float w[Pat::NNZ];
-#pragma unroll
-  for (int k = 0; k < Pat::NNZ; ++k) w[k] = a.tpw[k];
+  const float* w = a.tpw_v;   // kernel-argument array: uniform, read with scalar loads
   // TT * Kp is a multiple of 512: two (edge, channel) items per thread per step,
   // loads of both issued before either is used
   for (int p0 = threadIdx.x; p0 < TT * Kp; p0 += 512) {
@@ -291,9 +290,7 @@ __global__ __launch_bounds__(256) void k_tp_env_adjoint(TensorArgs a) {
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.n_centres) return;
   const int n = a.n, G = kWave / n, u = lane & (n - 1), g = lane / n;
-  float w[Pat::NNZ];
-#pragma unroll
-  for (int k = 0; k < Pat::NNZ; ++k) w[k] = a.tpw[k];
+  const float* w = a.tpw_v;   // kernel-argument array: uniform, read with scalar loads
   float Gm[DIM], gG[DIM];
   {
     const float* gp = a.gam + (size_t)c * DIM * n + u;
