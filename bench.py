@@ -30,6 +30,113 @@ sys.path.insert(0, ROOT)
 
 BF16_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 MFMA
 FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 MFMA
+HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
+
+# Kernel symbol (as rocprofv3 prints it) of each timed MLP launch kind, for
+# precision p: template arguments <precision, kind, tile rows, column tiles>.
+MLP_KIND = {"twobody": 0, "latent": 1, "final": 2}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_protein_box.md")
+
+
+def mlp_symbol(launch, precision, tile_rows, latent):
+    """'mlp_bwd_final', 1, 32, 256 -> 'k_mlp_bwd<1, 2, 32, 4>' (the kernel's name
+    without namespace and arguments; the last argument is ceil(d / 64))."""
+    _, fb, kind = launch.split("_", 2)
+    ct = -(-(-(-latent // 16)) // 4)
+    return f"k_mlp_{fb}<{precision}, {MLP_KIND[kind]}, {tile_rows}, {ct}>"
+
+
+def calibration_copy(mib):
+    """A plain device-to-device copy of `mib` MiB (three times): the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def summarize_profiles(stats_dir, fetch_dir, write_dir, copy_mib, commands):
+    """Markdown summary of a --kernel-trace --stats run and two --pmc runs
+    (FETCH_SIZE, WRITE_SIZE): per-kernel average duration and counter values
+    per dispatch, the copy-kernel scale factors, and the source hash."""
+    import csv
+    import glob
+
+    def one(pattern):
+        f = glob.glob(os.path.join(pattern, "**", "*.csv"), recursive=True)
+        return f
+
+    stats = {}
+    for f in one(stats_dir):
+        if f.endswith("kernel_stats.csv"):
+            for r in csv.DictReader(open(f)):
+                stats[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6)
+
+    def counters(d, name):
+        per = {}
+        for f in one(d):
+            if f.endswith("counter_collection.csv"):
+                for r in csv.DictReader(open(f)):
+                    if r["Counter_Name"] == name:
+                        per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    copy_kib = float(copy_mib) * 1024
+    cf = max((v for k, vs in fetch.items() if "copyBuffer" in k for v in vs), default=None)
+    cw = max((v for k, vs in write.items() if "copyBuffer" in k for v in vs), default=None)
+    blob = {"source_hash": kernel_source_hash(), "copy_MiB": copy_mib,
+            "copy_fetch_KiB": cf, "copy_write_KiB": cw,
+            "fetch_scale": copy_kib / cf if cf else None, "write_scale": copy_kib / cw if cw else None,
+            "kernels": {}}
+    lines = ["# rocprofv3 summary: protein-like box (23,558 atoms, 2.05M edges), BF16 step", ""]
+    for c in commands:
+        lines.append(f"    {c}")
+    lines += ["", "| kernel | calls | avg us | total ms | FETCH KiB/dispatch | WRITE KiB/dispatch |",
+              "|---|---|---|---|---|---|"]
+    for name, (calls, avg, tot) in sorted(stats.items(), key=lambda kv: -kv[1][2])[:24]:
+        fv, wv = fetch.get(name), write.get(name)
+        fa = sum(fv) / len(fv) if fv else None
+        wa = sum(wv) / len(wv) if wv else None
+        short = name.replace("allegro::", "").replace("(anonymous namespace)::", "")[:90]
+        lines.append(f"| `{short}` | {calls} | {avg:.1f} | {tot:.3f} | "
+                     f"{'' if fa is None else f'{fa:.0f}'} | {'' if wa is None else f'{wa:.0f}'} |")
+        if fa is not None and wa is not None and "k_mlp" in name:
+            blob["kernels"][short] = {"avg_us": avg, "fetch_KiB": fa, "write_KiB": wa}
+    lines += ["", "Counter scale factors from the plain copy of %d MiB (bytes per counted byte):" % copy_mib,
+              "", "```json", json.dumps(blob, indent=1), "```", ""]
+    return "\n".join(lines)
+
+
+def kernel_source_hash():
+    """SHA-256 over the HIP sources and headers of the library."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2304_10061_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(symbol):
+    """HBM bytes per launch of `symbol` from the committed counter summary,
+    or None when it is missing or the sources changed since it was taken."""
+    try:
+        txt = open(TRAFFIC_SUMMARY).read()
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_hash") != kernel_source_hash():
+        return None
+    for name, k in blob.get("kernels", {}).items():
+        if symbol in name:
+            return k["fetch_KiB"] * 1024 * blob["fetch_scale"] + k["write_KiB"] * 1024 * blob["write_scale"]
+    return None
 
 
 def mlp_macs_per_edge(mc):
@@ -236,7 +343,15 @@ def main():
     ap.add_argument("--workload", default="protein-box", choices=["protein-box", "subdomain", "clusters"],
                     help="protein-box (default, the headline); subdomain / clusters run MD")
     ap.add_argument("--dt", type=float, default=1.0, help="MD time step (fs) for the MD workloads")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="run a plain copy of this many MiB first (counter calibration under rocprofv3 --pmc)")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="print the markdown summary of rocprofv3 outputs and exit")
+    ap.add_argument("--command", action="append", default=[], help="profiling command (for --summarize)")
     args = ap.parse_args()
+    if args.summarize:
+        print(summarize_profiles(*args.summarize, args.calibration_copy_mib, args.command))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the energy/force path runs on a single MI355X "
               "(spatial decomposition across GPUs is not part of this build)", file=sys.stderr)
@@ -247,6 +362,8 @@ def main():
         return
 
     import workloads as W
+    if args.calibration_copy_mib:
+        calibration_copy(args.calibration_copy_mib)
     mc, s, w = W.workload(3)
     bf = run_gpu(mc, s, w, 1, args.steps, args.warmup, want_kernel_times=True)
     fp = None if args.no_fp32 else run_gpu(mc, s, w, 0, max(3, args.steps // 4), min(2, args.warmup), True)
@@ -260,8 +377,9 @@ def main():
     if dom in macs:
         flops = 2.0 * macs[dom] * bf["edges"] * bf["kernel_launches"].get(dom, 1)
         achieved = flops / (kms[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+        sym = mlp_symbol(dom, 1, (bf["tiles"] or {}).get(dom, 0), mc.latent)
+        roof = {"kernel": dom, "symbol": sym, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": traffic_per_launch(sym),
                 "flops_per_launch": flops / max(1, bf["kernel_launches"].get(dom, 1)),
                 "avg_launch_ms": kms[dom] / max(1, bf["kernel_launches"].get(dom, 1))}
     else:

@@ -25,7 +25,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-result"]
 
-SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "tensor.hip", "md.hip"]
+SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "mlp_fp32.hip", "mlp_bf16.hip", "mlp_bf16s.hip",
+           "tensor.hip", "md.hip"]
 
 
 def _hipcc() -> str:

@@ -1,0 +1,738 @@
+// mlp_kernels.h - fused, edge-batched MLP chains on MFMA (the scalar track).
+//
+// The scalar track carries most of the model's capacity as dense MLPs over
+// ordered pairs (section "Allegro: Scalable Equivariant Deep Learning": the two
+// tracks; section "Training details": two-body and later latent MLPs with SiLU,
+// a linear environment embedding, an edge-energy MLP with no nonlinearity).
+// The matrix products are the bulk of the cost (section "Mixed-precision
+// calculations"), so each MLP chain runs as one kernel per tile of TM edges:
+// activations stay in LDS, weights stream from L2 in a pre-packed MFMA operand
+// layout, and the linear map that consumes the MLP output (environment
+// embedding of the next layer, or the edge energy) is fused as a "head".
+//
+// Precision: PREC 1 = BF16 operands (v_mfma_f32_16x16x32_bf16) with FP32
+// accumulation, PREC 0 = FP32 (v_mfma_f32_16x16x4_f32).  The residual stream
+// and all epilogues are FP32.
+//
+// Kinds (x_prev, u from the edge record, rs = 1/sqrt(2)):
+//   two-body      x0 = u * MLP([onehot(Z_i), onehot(Z_j), R])        head: [a0 | w^1]
+//   latent        x^L = rs (x^{L-1} + u * MLP([x^{L-1}, V^L[0]]))     head: w^{L+1}
+//   latent-final  same with the final scalar tensor product computed in the
+//                 prologue from V^{L-1} and Gamma^L; the edge energy
+//                 E_ij = x^L . we (edge MLP folded into one vector) is the head.
+// The backward kernel recomputes the chain from its inputs (no stored
+// activations), then propagates input gradients only (no weight gradients).
+//
+// The kernel templates are instantiated per precision in mlp_fp32.hip,
+// mlp_bf16.hip and mlp_bf16s.hip (compiled in parallel); mlp.hip holds the
+// host-side tile selection.
+#pragma once
+
+#include "devutil.h"
+#include "internal.h"
+
+#ifndef ALLEGRO_PF
+#define ALLEGRO_PF 1
+#endif
+
+namespace allegro {
+namespace mlpk {
+
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct PT;
+
+template <> struct PT<1> {
+  using T = __bf16;
+  struct F { bf16x8 v; };
+  static __device__ __forceinline__ F load(const T* p) { F f; f.v = *(const bf16x8*)p; return f; }
+  static __device__ __forceinline__ f32x4 mma(const F& a, const F& b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
+  }
+};
+
+// PREC 2: BF16 operands with single-rounded weights (no low-order correction).
+template <> struct PT<2> : PT<1> {};
+
+template <> struct PT<0> {
+  using T = float;
+  struct F { f32x4 lo, hi; };
+  static __device__ __forceinline__ F load(const T* p) {
+    F f;
+    f.lo = *(const f32x4*)p;
+    f.hi = *(const f32x4*)(p + 4);
+    return f;
+  }
+  // Eight K=4 steps; step s takes k = 8 (lane/16) + s from each lane group, so
+  // the 32-wide K block is covered exactly once with the same fragment layout
+  // as the BF16 instruction.
+  static __device__ __forceinline__ f32x4 mma(const F& a, const F& b, f32x4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[0], b.lo[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[1], b.lo[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[2], b.lo[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[3], b.lo[3], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi[0], b.hi[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi[1], b.hi[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi[2], b.hi[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.hi[3], b.hi[3], c, 0, 0, 0);
+    return c;
+  }
+};
+
+// Column tiles of a GEMM output are dealt to the four waves round-robin; pass
+// p covers nt = wave + 4 (p MAXCT + q), q < MAXCT, so wide outputs run in
+// several passes with a bounded accumulator set.
+template <int MAXCT>
+__device__ __forceinline__ int tile_of(int pass, int q, int wave) { return wave + 4 * (pass * MAXCT + q); }
+
+template <int MAXCT>
+__device__ __forceinline__ int npasses(int Np) { return (Np / 16 + 4 * MAXCT - 1) / (4 * MAXCT); }
+
+// acc[rt][q] = A[TM x K-range] (LDS) @ B[K-range x tiles of this pass].
+// A holds the columns of K blocks [kb0, kb1) starting at its column 0.  The
+// loop is branch-free: column tiles beyond the matrix are clamped to its last
+// tile (their results are never stored), and the B fragments of the next K
+// block are requested before the MFMAs of the current one, so L2 latency
+// overlaps matrix-core work.  `wave` must be wave-uniform (readfirstlane).
+template <int PREC, int RT, int MAXCT>
+__device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
+                                          int lda, const GemmB& B, int wave, int lane, int pass,
+                                          int kb0 = 0, int kb1 = -1, bool zero = true) {
+  using P = PT<PREC>;
+  using T = typename P::T;
+  using F = typename P::F;
+  if (zero) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  const int nkb = B.Kp >> 5, nct = B.Np >> 4;
+  if (kb1 < 0) kb1 = nkb;
+  // PREC 1 keeps each weight as a pair of BF16 values (hi + lo, lo stored
+  // after the hi fragments) and issues two MFMAs per product.
+  constexpr bool kSplit = PREC == 1;
+  const size_t lo_off = (size_t)B.Kp * B.Np;
+  const T* Bl = (const T*)B.p + (size_t)lane * 8;
+  const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4) - kb0 * 32;
+  size_t boff[MAXCT];
+#pragma unroll
+  for (int q = 0; q < MAXCT; ++q) {
+    int nt = tile_of<MAXCT>(pass, q, wave);
+    nt = nt < nct ? nt : nct - 1;
+    boff[q] = (size_t)(nt * nkb) * 512;
+  }
+  // Register buffers of A and B fragments, used in rotation: the fragments
+  // of K block kb + PF are requested before the MFMAs of block kb.
+  // Scheduling barriers keep the compiler from sinking those loads next to
+  // their first use.
+  F a0[RT], a1[RT], b0[MAXCT], b1[MAXCT], l0[kSplit ? MAXCT : 1], l1[kSplit ? MAXCT : 1];
+  auto load = [&](F (&aa)[RT], F (&bb)[MAXCT], F (&ll)[kSplit ? MAXCT : 1], int kb) {
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      bb[q] = P::load(Bl + boff[q] + (size_t)kb * 512);
+      if constexpr (kSplit) ll[q] = P::load(Bl + lo_off + boff[q] + (size_t)kb * 512);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) aa[rt] = P::load(Arow + rt * 16 * lda + kb * 32);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto compute = [&](const F (&aa)[RT], const F (&bb)[MAXCT], const F (&ll)[kSplit ? MAXCT : 1]) {
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(aa[rt], ll[q], acc[rt][q]);
+    }
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(aa[rt], bb[q], acc[rt][q]);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto clampk = [&](int k) { return k < kb1 ? k : kb1 - 1; };   // tail re-requests a loaded block
+#if ALLEGRO_PF == 2
+  F a2[RT], b2[MAXCT], l2[kSplit ? MAXCT : 1];
+  load(a0, b0, l0, kb0);
+  load(a1, b1, l1, clampk(kb0 + 1));
+  int kb = kb0;
+  for (; kb + 2 < kb1; kb += 3) {
+    load(a2, b2, l2, kb + 2);
+    compute(a0, b0, l0);
+    load(a0, b0, l0, clampk(kb + 3));
+    compute(a1, b1, l1);
+    load(a1, b1, l1, clampk(kb + 4));
+    compute(a2, b2, l2);
+  }
+  if (kb < kb1) compute(a0, b0, l0);
+  if (kb + 1 < kb1) compute(a1, b1, l1);
+#else
+  load(a0, b0, l0, kb0);
+  int kb = kb0;
+  for (; kb + 1 < kb1; kb += 2) {
+    load(a1, b1, l1, kb + 1);
+    compute(a0, b0, l0);
+    load(a0, b0, l0, clampk(kb + 2));
+    compute(a1, b1, l1);
+  }
+  if (kb < kb1) compute(a0, b0, l0);
+#endif
+  // tiles clamped onto the last one hold copies: zero them so that register
+  // uses of acc (gradients, dot products) see exact zeros there
+#pragma unroll
+  for (int q = 0; q < MAXCT; ++q)
+    if (tile_of<MAXCT>(pass, q, wave) >= nct)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+template <class T> __device__ __forceinline__ T to_t(float v) { return (T)v; }
+
+__device__ __forceinline__ void store4(__bf16* p, float4 v) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  bf16x4 b = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+  *(bf16x4*)p = b;
+}
+__device__ __forceinline__ void store4(float* p, float4 v) { *(float4*)p = v; }
+
+// 32-bit element offsets: one launch never addresses more than 2^31 floats
+// of any edge-major array (the host splits larger edge sets into chunks).
+__device__ __forceinline__ float4 ld4(const float* base, uint32_t off) { return *(const float4*)(base + off); }
+
+// Copies float4 chunks of edge rows into X: for each row r of this wave's
+// TM/4 rows and chunk q < w4, X[r][c0 + 4q ..] = *src(e, c0 + 4q) for edges
+// e0 + r < E (zero otherwise).  The (row, chunk) items are spread over the
+// lanes and processed eight at a time with every load issued before the
+// first store, so eight loads per lane are in flight.  `src` must return an
+// in-range address for any e < E and column of the range.
+template <int PREC, int TM, class Src>
+__device__ __forceinline__ void gather_rows(typename PT<PREC>::T* X, int ldx, int e0, int E, int c0, int w4,
+                                            Src src) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  constexpr int RPW = TM / 4;
+  const int total = RPW * w4;
+  for (int t0 = 0; t0 < total; t0 += 64 * 8) {
+    float4 v[8];
+    int off[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int t = t0 + lane + 64 * j;
+      const int r = t / w4, q = t - r * w4;
+      const int row = wave * RPW + (r < RPW ? r : RPW - 1);
+      const int e = e0 + row;
+      const bool ok = t < total && e < E;
+      v[j] = src(ok ? e : E - 1, c0 + 4 * q);
+      if (!ok) v[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      off[j] = t < total ? row * ldx + c0 + 4 * q : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (off[j] >= 0) store4(X + off[j], v[j]);
+  }
+}
+
+// Zero columns [c0, c0 + 4 w4) of this wave's rows.
+template <int PREC, int TM>
+__device__ __forceinline__ void zero_cols(typename PT<PREC>::T* X, int ldx, int c0, int w4) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  constexpr int RPW = TM / 4;
+  for (int t = lane; t < RPW * w4; t += 64) {
+    const int r = t / w4, q = t - r * w4;
+    store4(X + (wave * RPW + r) * ldx + c0 + 4 * q, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  }
+}
+
+// Final-layer scalar tensor product for channels u..u+3 of edge e:
+// T[u] = sum_c w_c V[c][u] Gamma[c][u] (V either stored or the rank-1
+// first-layer form a0[l(c)][u] Y_c).
+__device__ __forceinline__ float4 final_tp4(const MlpArgs& a, int e, int u) {
+  const int dim = (a.l_max + 1) * (a.l_max + 1);
+  const uint32_t gbase = (uint32_t)(a.ei[e] - a.centre_base) * dim * a.n + u;
+  const uint32_t vbase = (uint32_t)e * a.tp_v.ld + u;
+  float4 g[9], vv[9];
+  float wy[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const bool on = c < dim;               // components beyond dim weigh zero
+    const int cc = on ? c : 0;
+    const int l = c == 0 ? 0 : (c < 4 ? 1 : 2);
+    g[c] = ld4(a.tp_gam, gbase + cc * a.n);
+    vv[c] = ld4(a.tp_v.p, vbase + (a.tp_v.from_a0 ? (on ? l : 0) : cc) * a.n);
+    wy[c] = on ? a.tp_w[c] * (a.tp_v.from_a0 ? a.eb[(uint32_t)e * kEB + cc] : 1.0f) : 0.0f;
+  }
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const float w = wy[c];
+    v.x = fmaf(w * vv[c].x, g[c].x, v.x);
+    v.y = fmaf(w * vv[c].y, g[c].y, v.y);
+    v.z = fmaf(w * vv[c].z, g[c].z, v.z);
+    v.w = fmaf(w * vv[c].w, g[c].w, v.w);
+  }
+  return v;
+}
+
+// Input rows of the chain for edges e0 .. e0+TM-1, zero padded to Kp.
+//   two-body: [onehot(Z_i), onehot(Z_j), R_0..R_{nb-1}]
+//   latent:   [x^{L-1}, V^L[0] (or the final scalar tensor product)]
+template <int PREC, int KIND, int TM>
+__device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp) {
+  using T = typename PT<PREC>::T;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  constexpr int RPW = TM / 4;
+  if constexpr (KIND == kTwoBody) {
+    // one row per lane pass: the row's species pair, then its columns
+    const int S = a.n_species, nb = a.n_bessel;
+    for (int t = lane; t < RPW * (Kp >> 2); t += 64) {
+      const int r = t / (Kp >> 2), q = t - r * (Kp >> 2);
+      const int row = wave * RPW + r, e = e0 + row;
+      const bool ok = e < a.E;
+      const int ec = ok ? e : a.E - 1;
+      const int zi = a.species[a.ei[ec]], zj = a.species[a.ej[ec]];
+      float x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = 4 * q + k;
+        const int rc = c - 2 * S;
+        const float rv = a.eb[(uint32_t)ec * kEB + kEB_R + (rc >= 0 && rc < nb ? rc : 0)];
+        float v = c < S ? (zi == c ? 1.0f : 0.0f)
+                        : c < 2 * S ? (zj == c - S ? 1.0f : 0.0f) : (rc < nb ? rv : 0.0f);
+        x[k] = ok ? v : 0.0f;
+      }
+      store4(X + row * ldx + 4 * q, make_float4(x[0], x[1], x[2], x[3]));
+    }
+  } else {
+  const int d = a.d, n = a.n;
+  gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, d >> 2,
+                        [&](int e, int c) { return ld4(a.x_prev, (uint32_t)e * d + c); });
+  if constexpr (KIND == kLatent) {
+    gather_rows<PREC, TM>(X, ldx, e0, a.E, d, n >> 2,
+                          [&](int e, int c) { return ld4(a.s_in, (uint32_t)e * a.s_ld + (c - d)); });
+  } else {
+    // final layer: one (row, 4 channels) item per lane at a time; each
+    // gathers 2 dim float4s before combining them
+    const int w4 = n >> 2;
+    for (int t = lane; t < RPW * w4; t += 64) {
+      const int r = t / w4, q = t - r * w4;
+      const int row = wave * RPW + r, e = e0 + row;
+      float4 v = final_tp4(a, e < a.E ? e : a.E - 1, 4 * q);
+      if (e >= a.E) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      store4(X + row * ldx + d + 4 * q, v);
+    }
+  }
+  if (Kp > d + n) zero_cols<PREC, TM>(X, ldx, d + n, (Kp - d - n) >> 2);
+  }
+}
+
+// Rows of a row-major FP32 matrix (row stride ld, ncols columns, a multiple
+// of 4) into X, columns [c0, c0+w) (zero beyond ncols).
+template <int PREC, int TM>
+__device__ void stage_rows(const float* src, int ld, int ncols, int E, typename PT<PREC>::T* X, int ldx,
+                           int e0, int c0, int w) {
+  gather_rows<PREC, TM>(X, ldx, e0, E, 0, w >> 2, [&](int e, int c) {
+    const int cc = c0 + c;
+    float4 v = ld4(src, (uint32_t)e * ld + (cc < ncols ? cc : ncols - 4));
+    if (cc >= ncols) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return v;
+  });
+}
+
+// Writes f(acc) of pass `pass` into an LDS tile (row-major, T) for columns < Np.
+template <int PREC, int RT, int MAXCT, class Fn>
+__device__ __forceinline__ void store_tile(const f32x4 (&acc)[RT][MAXCT], typename PT<PREC>::T* out,
+                                           int ldo, int Np, int wave, int lane, int pass, Fn fn) {
+  using T = typename PT<PREC>::T;
+#pragma unroll
+  for (int q = 0; q < MAXCT; ++q) {
+    const int nt = tile_of<MAXCT>(pass, q, wave);
+    if (nt * 16 >= Np) continue;
+    const int col = nt * 16 + (lane & 15);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rt * 16 + 4 * (lane >> 4) + i;
+        out[row * ldo + col] = to_t<T>(fn(acc[rt][q][i], row, col));
+      }
+  }
+}
+
+// Hidden layers of the chain: `in` -> SiLU -> alternate buffer, optionally
+// keeping the pre-activations.  Returns the buffer holding the last hidden
+// activation (the input of the last layer).
+template <int PREC, int TM, int MAXCT>
+__device__ __forceinline__ const typename PT<PREC>::T* hidden_layers(
+    const MlpArgs& a, typename PT<PREC>::T* X, int ldx, typename PT<PREC>::T* H, int ldh,
+    typename PT<PREC>::T* Pb, int ldp, int* ldin, int wave, int lane) {
+  using T = typename PT<PREC>::T;
+  constexpr int RT = TM / 16;
+  const T* in = X;
+  *ldin = ldx;
+  f32x4 acc[RT][MAXCT];
+  for (int l = 0; l + 1 < a.w.nl; ++l) {
+    T* out = (in == X) ? H : X;
+    const int ldo = (in == X) ? ldh : ldx;
+    const GemmB& B = a.w.fwd[l];
+    for (int p = 0; p < npasses<MAXCT>(B.Np); ++p) {
+      gemm_tile<PREC, RT, MAXCT>(acc, in, *ldin, B, wave, lane, p);
+      if (Pb) store_tile<PREC, RT, MAXCT>(acc, Pb + l * TM * ldp, ldp, B.Np, wave, lane, p,
+                                          [](float v, int, int) { return v; });
+      store_tile<PREC, RT, MAXCT>(acc, out, ldo, B.Np, wave, lane, p, [](float v, int, int) { return silu(v); });
+    }
+    __syncthreads();
+    in = out;
+    *ldin = ldo;
+  }
+  return in;
+}
+
+template <int PREC, int KIND, int TM, int MAXCT>
+__global__ __launch_bounds__(256, 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
+  using P = PT<PREC>;
+  using T = typename P::T;
+  constexpr int RT = TM / 16;
+  extern __shared__ __align__(16) char smem[];
+  T* X = (T*)smem;
+  T* H = X + TM * ldx;
+  __shared__ float red[4][TM];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int e0 = blockIdx.x * TM;
+
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  __syncthreads();
+  int ldin;
+  const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, nullptr, 0, &ldin, wave, lane);
+  const int nl = a.w.nl;
+  f32x4 acc[RT][MAXCT];
+  gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // N = d: one pass
+  // epilogue: x = u h (two-body) or rs (x_prev + u h) (latent), kept in acc.
+  // All loads are issued before the first store.
+  const int d = a.d;
+  float ur[RT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+      ur[rt][i] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
+    }
+  if constexpr (KIND != kTwoBody) {
+    float xp[RT][MAXCT][4];
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+      col = col < d ? col : d - 1;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          e = e < a.E ? e : a.E - 1;
+          xp[rt][q][i] = a.x_prev[(uint32_t)e * d + col];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[rt][q][i] = a.res_scale * (xp[rt][q][i] + ur[rt][i] * acc[rt][q][i]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[rt][q][i] = ur[rt][i] * acc[rt][q][i];
+  }
+  // rows beyond E and clamped column tiles hold zeros
+#pragma unroll
+  for (int q = 0; q < MAXCT; ++q) {
+    const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+        const bool ok = e < a.E && col < d;
+        if (!ok) acc[rt][q][i] = 0.0f;
+        if (ok && a.x_out) a.x_out[(uint32_t)e * d + col] = acc[rt][q][i];
+      }
+  }
+  if constexpr (KIND == kLatentFinal) {
+    // E_ij = x . we : per-lane partial over its columns, then across lanes and waves
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) {
+          const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+          if (col < d) sum = fmaf(acc[rt][q][i], a.we[col], sum);
+        }
+        sum = group_inner_sum(sum, 16);
+        if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
+      }
+    __syncthreads();
+    if ((int)threadIdx.x < TM) {
+      const int e = e0 + threadIdx.x;
+      if (e < a.E)
+        a.eij[e] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    }
+    return;
+  }
+  if (a.head.p == nullptr) return;
+  // head GEMM on x, staged in the buffer the last layer did not read
+  T* xb = (in == X) ? H : X;
+  const int ldxb = (in == X) ? ldh : ldx;
+  store_tile<PREC, RT, MAXCT>(acc, xb, ldxb, a.w.fwd[nl - 1].Np, wave, lane, 0, [](float v, int, int) { return v; });
+  __syncthreads();
+  const int Nh = a.head.N;
+  for (int p = 0; p < npasses<MAXCT>(a.head.Np); ++p) {
+    gemm_tile<PREC, RT, MAXCT>(acc, xb, ldxb, a.head, wave, lane, p);
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      const int col = tile_of<MAXCT>(p, q, wave) * 16 + (lane & 15);
+      if (col >= Nh) continue;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          if (e < a.E) a.head_out[(size_t)e * Nh + col] = acc[rt][q][i];
+        }
+    }
+  }
+}
+
+template <int PREC, int KIND, int TM, int MAXCT>
+__global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
+  using P = PT<PREC>;
+  using T = typename P::T;
+  constexpr int RT = TM / 16;
+  extern __shared__ __align__(16) char smem[];
+  T* X = (T*)smem;
+  T* H = X + TM * ldx;
+  T* Pb = H + TM * ldh;                 // nl-1 pre-activation buffers [TM][ldh]
+  __shared__ float red[4][TM];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int e0 = blockIdx.x * TM;
+  const int d = a.d;
+  const int nl = a.w.nl;
+
+  // 1. G = dE/dx_out (columns < d all lie in pass 0); loads first, then masks
+  f32x4 G[RT][MAXCT];
+  {
+    const float* gsrc = KIND == kLatentFinal ? a.g_const : a.g_x;
+    uint32_t rowoff[RT][4];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+        e = e < a.E ? e : a.E - 1;
+        rowoff[rt][i] = (uint32_t)(KIND == kLatentFinal ? a.species[a.ei[e]] : e) * d;
+      }
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+      const int cc = col < d ? col : d - 1;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) G[rt][q][i] = gsrc ? gsrc[rowoff[rt][i] + cc] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          if (!(e < a.E && col < d)) G[rt][q][i] = 0.0f;
+        }
+    }
+  }
+  // u of this lane's rows (zero beyond E)
+  float ur[RT][4];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+      ur[rt][i] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
+    }
+  f32x4 acc[RT][MAXCT];
+  if (KIND != kLatentFinal && a.head_bwd.p != nullptr) {
+    // G += g_head @ W_head^T, K staged through X in chunks of its width
+    const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5, chunk = ldx >> 5;
+    for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
+      const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
+      const int w = (kb1 - kb0) * 32;
+      stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, w);
+      __syncthreads();
+      gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, true);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) G[rt][q] += acc[rt][q];
+      __syncthreads();
+    }
+  }
+
+  // 2. recompute the chain, keeping hidden pre-activations
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  __syncthreads();
+  int ldin;
+  const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, Pb, ldh, &ldin, wave, lane);
+  gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // acc = h
+  const float rs = (KIND == kTwoBody) ? 1.0f : a.res_scale;
+  // dE/du = rs sum_c G h
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float sum = 0.0f;
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) sum = fmaf(G[rt][q][i], acc[rt][q][i], sum);
+      sum = group_inner_sum(sum, 16);
+      if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
+    }
+  __syncthreads();   // also: every wave is done reading `in`
+  if ((int)threadIdx.x < TM) {
+    const int e = e0 + threadIdx.x;
+    if (e < a.E) {
+      const float gu = rs * (((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                             red[3][threadIdx.x]);
+      a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
+    }
+  }
+  // dE/dh = rs u G into the buffer the last layer did not read
+  T* cur = (in == X) ? H : X;
+  int ldc = (in == X) ? ldh : ldx;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[rt][q][i] = rs * ur[rt][i] * G[rt][q][i];
+  store_tile<PREC, RT, MAXCT>(acc, cur, ldc, a.w.fwd[nl - 1].Np, wave, lane, 0,
+                              [](float v, int, int) { return v; });
+  __syncthreads();
+  // 3. back through the hidden layers (ping-pong between X and H)
+  for (int l = nl - 1; l > 0; --l) {
+    T* nxt = (cur == X) ? H : X;
+    const int ldn = (cur == X) ? ldh : ldx;
+    const T* Pl = Pb + (l - 1) * TM * ldh;
+    const GemmB& B = a.w.bwd[l];
+    for (int p = 0; p < npasses<MAXCT>(B.Np); ++p) {
+      gemm_tile<PREC, RT, MAXCT>(acc, cur, ldc, B, wave, lane, p);
+      store_tile<PREC, RT, MAXCT>(acc, nxt, ldn, B.Np, wave, lane, p, [&](float v, int row, int col) {
+        return v * silu_grad((float)Pl[row * ldh + col]);
+      });
+    }
+    __syncthreads();
+    cur = nxt;
+    ldc = ldn;
+  }
+  // 4. dE/dz, written straight to the outputs
+  const int S = a.n_species;
+  const GemmB& B0 = a.w.bwd[0];
+  for (int p = 0; p < npasses<MAXCT>(B0.Np); ++p) {
+    gemm_tile<PREC, RT, MAXCT>(acc, cur, ldc, B0, wave, lane, p);
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      const int col = tile_of<MAXCT>(p, q, wave) * 16 + (lane & 15);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          if (e >= a.E) continue;
+          const float g = acc[rt][q][i];
+          if constexpr (KIND == kTwoBody) {
+            if (col >= 2 * S && col < 2 * S + a.n_bessel) a.g_R[(size_t)e * a.n_bessel + col - 2 * S] = g;
+          } else if (col < d) {
+            a.g_xprev[(size_t)e * d + col] = rs * G[rt][q][i] + g;   // p == 0 here
+          } else if (col < d + a.n) {
+            a.g_s[(size_t)e * a.n + col - d] = g;
+          }
+        }
+    }
+  }
+}
+
+// LDS layout: X [TM][ldx] and H [TM][ldh] (+ nl-1 pre-activation buffers of
+// [TM][ldh] in the backward kernel).
+template <int PREC>
+void lds_dims(const MlpArgs& a, int TM, bool bwd, int* ldx, int* ldh, size_t* bytes) {
+  int kh = 32;                       // widths of hidden layers and of the output d
+  for (int l = 0; l < a.w.nl; ++l) kh = kh > a.w.fwd[l].Np ? kh : a.w.fwd[l].Np;
+  int kx = kh > a.w.fwd[0].Kp ? kh : a.w.fwd[0].Kp;
+  const int pad = PREC ? 8 : 4;
+  *ldx = kx + pad;
+  *ldh = kh + pad;
+  const int nbuf_h = bwd ? a.w.nl : 1;
+  *bytes = (size_t)TM * ((size_t)*ldx + (size_t)nbuf_h * *ldh) * (PREC ? 2 : 4);
+}
+
+// Accumulator tiles per wave: the latent width d must fit one pass.
+inline int max_ct(const MlpArgs& a) {
+  const int dt = (a.d + 15) / 16;
+  return (dt + 3) / 4;
+}
+
+constexpr size_t kLdsLimit = 160 * 1024 - 4096;
+
+template <int PREC, int KIND, int TM, int MAXCT>
+hipError_t launch_one(const MlpArgs& a, bool bwd, hipStream_t s) {
+  int ldx, ldh;
+  size_t bytes;
+  lds_dims<PREC>(a, TM, bwd, &ldx, &ldh, &bytes);
+  const dim3 grid((a.E + TM - 1) / TM), block(256);
+  auto k = bwd ? k_mlp_bwd<PREC, KIND, TM, MAXCT> : k_mlp_fwd<PREC, KIND, TM, MAXCT>;
+  hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (st != hipSuccess) return st;
+  hipLaunchKernelGGL(k, grid, block, bytes, s, a, ldx, ldh);
+  return hipGetLastError();
+}
+
+template <int PREC, int KIND, int TM>
+hipError_t dispatch_ct(const MlpArgs& a, bool bwd, hipStream_t s) {
+  const int ct = max_ct(a);
+  if (ct <= 1) return launch_one<PREC, KIND, TM, 1>(a, bwd, s);
+  if (ct <= 2) return launch_one<PREC, KIND, TM, 2>(a, bwd, s);
+  if (ct <= 4) return launch_one<PREC, KIND, TM, 4>(a, bwd, s);
+  return hipErrorInvalidValue;
+}
+
+// Tile rows per precision: {larger, smaller}.
+template <int PREC> constexpr int kTileRows[2] = {PREC ? 64 : 32, PREC ? 32 : 16};
+
+// Launches the chain of `a` (kind a.kind) with TM rows per tile (one of
+// kTileRows<PREC>); instantiated once per precision in its own source file.
+template <int PREC>
+hipError_t launch_prec(const MlpArgs& a, int tm, bool bwd, hipStream_t s) {
+  constexpr int T0 = kTileRows<PREC>[0], T1 = kTileRows<PREC>[1];
+  switch (a.kind) {
+    case kTwoBody:
+      return tm == T0 ? dispatch_ct<PREC, kTwoBody, T0>(a, bwd, s) : dispatch_ct<PREC, kTwoBody, T1>(a, bwd, s);
+    case kLatent:
+      return tm == T0 ? dispatch_ct<PREC, kLatent, T0>(a, bwd, s) : dispatch_ct<PREC, kLatent, T1>(a, bwd, s);
+    case kLatentFinal:
+      return tm == T0 ? dispatch_ct<PREC, kLatentFinal, T0>(a, bwd, s)
+                      : dispatch_ct<PREC, kLatentFinal, T1>(a, bwd, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+extern template hipError_t launch_prec<0>(const MlpArgs&, int, bool, hipStream_t);
+extern template hipError_t launch_prec<1>(const MlpArgs&, int, bool, hipStream_t);
+extern template hipError_t launch_prec<2>(const MlpArgs&, int, bool, hipStream_t);
+
+}  // namespace mlpk
+}  // namespace allegro
