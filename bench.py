@@ -57,7 +57,7 @@ def calibration_copy(mib):
     torch.cuda.synchronize()
 
 
-def summarize_profiles(stats_dir, fetch_dir, write_dir, copy_mib, commands):
+def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, commands):
     """Markdown summary of a --kernel-trace --stats run and two --pmc runs
     (FETCH_SIZE, WRITE_SIZE): per-kernel average duration and counter values
     per dispatch, the copy-kernel scale factors, and the source hash."""
@@ -87,7 +87,11 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, copy_mib, commands):
     copy_kib = float(copy_mib) * 1024
     cf = max((v for k, vs in fetch.items() if "copyBuffer" in k for v in vs), default=None)
     cw = max((v for k, vs in write.items() if "copyBuffer" in k for v in vs), default=None)
-    blob = {"source_hash": kernel_source_hash(), "copy_MiB": copy_mib,
+    src_hash = None
+    for line in open(bench_log):
+        if line.startswith("{"):
+            src_hash = json.loads(line).get("source_hash")
+    blob = {"source_hash": src_hash, "copy_MiB": copy_mib,
             "copy_fetch_KiB": cf, "copy_write_KiB": cw,
             "fetch_scale": copy_kib / cf if cf else None, "write_scale": copy_kib / cw if cw else None,
             "kernels": {}}
@@ -345,8 +349,8 @@ def main():
     ap.add_argument("--dt", type=float, default=1.0, help="MD time step (fs) for the MD workloads")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration under rocprofv3 --pmc)")
-    ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
-                    help="print the markdown summary of rocprofv3 outputs and exit")
+    ap.add_argument("--summarize", nargs=4, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "BENCH_LOG"),
+                    help="print the markdown summary of rocprofv3 outputs (and the profiled run's output) and exit")
     ap.add_argument("--command", action="append", default=[], help="profiling command (for --summarize)")
     args = ap.parse_args()
     if args.summarize:
@@ -413,6 +417,7 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in sorted(kms.items(), key=lambda kv: -kv[1])},
         "neighbors_ms": bf["neighbors_ms"],
         "workspace_GB": bf["workspace_GB"],
+        "source_hash": kernel_source_hash(),
     }
     if fp is not None:
         out["fp32"] = {"value": s.n_local / (fp["ms_per_step"] * 1e-3), "ms_per_step": fp["ms_per_step"],

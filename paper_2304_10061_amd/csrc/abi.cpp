@@ -242,6 +242,7 @@ struct AllegroModel {
   AllegroConfig cfg{};
   Validated v{};
   int prec = 1;
+  int prec_two = 1, prec_lat = 1;   // kernel precision of the two-body / later MLPs (0 FP32, 1 pairs, 2 BF16)
   std::string err;
   int device = 0;
 
@@ -293,6 +294,7 @@ struct AllegroModel {
 
   // workspace
   DevBuf eb, x[2], head0o, wenv2, V1, gam[2], eij, gxa, gxb, gTf, gs, ghead0, gw2, gT, gY, gu, gR;
+  DevBuf ggam;   // dE/dGamma of the layer being differentiated [centres][dim][n]
   DevBuf g_e, atom_e, partial;
 };
 
@@ -325,7 +327,6 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
                                         std::to_string(v.n_weights));
   for (int64_t k = 0; k < n_weights; ++k) REQUIRE(std::isfinite(w[k]), "weights contain non-finite values");
   HIP_OK(hipGetDevice(&m->device));
-  const int prec = m->prec;
   const int n = v.n, d = v.d, LW = v.LW, L1 = v.lmax + 1;
   int64_t off = 0;
   // two-body MLP
@@ -335,7 +336,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     Ws.push_back(slice(w, off, (int64_t)dims.back() * wd));
     dims.push_back(wd);
   }
-  build_mlp(m->twobody, Ws, dims, prec);
+  build_mlp(m->twobody, Ws, dims, m->prec_two);
   const std::vector<double> embed0 = slice(w, off, (int64_t)d * LW);
   std::vector<double> env[2], alpha[2], mix[2];
   std::vector<std::vector<double>> mlpW[2];
@@ -372,7 +373,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   }
   std::vector<int> ldims{d + n};
   for (int wd : v.dimsL) ldims.push_back(wd);
-  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, prec);
+  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, m->prec_lat);
 
   // heads: [embed0 | env1] after the two-body MLP, env2 after the first latent MLP
   {
@@ -382,11 +383,11 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
         H[(size_t)r * 2 * LW + c] = embed0[(size_t)r * LW + c];
         H[(size_t)r * 2 * LW + LW + c] = env[0][(size_t)r * LW + c];
       }
-    make_packed(m->head0, H, d, 2 * LW, prec);
-    make_packed(m->head0T, transpose(H, d, 2 * LW), 2 * LW, d, prec);
+    make_packed(m->head0, H, d, 2 * LW, m->prec_two);
+    make_packed(m->head0T, transpose(H, d, 2 * LW), 2 * LW, d, m->prec_two);
     if (v.nl == 2) {
-      make_packed(m->env2, env[1], d, LW, prec);
-      make_packed(m->env2T, transpose(env[1], d, LW), LW, d, prec);
+      make_packed(m->env2, env[1], d, LW, m->prec_lat);
+      make_packed(m->env2T, transpose(env[1], d, LW), LW, d, m->prec_lat);
     }
   }
   // channel mixing matrices of non-final layers (FP32): forward W[u][v] = M[v][u],
@@ -441,13 +442,14 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   // check the MLP kernels fit in LDS for this configuration
   MlpArgs probe;
   probe.d = d; probe.n = n; probe.w = m->twobody.view(); probe.head = m->head0.g; probe.head_bwd = m->head0T.g;
-  REQUIRE(mlp_lds_bytes(probe, prec, false) != (size_t)-1 && mlp_lds_bytes(probe, prec, true) != (size_t)-1,
+  REQUIRE(mlp_lds_bytes(probe, m->prec_two, false) != (size_t)-1 &&
+              mlp_lds_bytes(probe, m->prec_two, true) != (size_t)-1,
           "two-body MLP too wide for the fused kernel");
   for (int L = 0; L < v.nl; ++L) {
     MlpArgs q;
     q.d = d; q.n = n; q.w = m->latent[L].view();
     if (L + 1 < v.nl) { q.head = m->env2.g; q.head_bwd = m->env2T.g; }
-    REQUIRE(mlp_lds_bytes(q, prec, false) != (size_t)-1 && mlp_lds_bytes(q, prec, true) != (size_t)-1,
+    REQUIRE(mlp_lds_bytes(q, m->prec_lat, false) != (size_t)-1 && mlp_lds_bytes(q, m->prec_lat, true) != (size_t)-1,
             "latent MLP too wide for the fused kernel");
   }
 }
@@ -684,6 +686,7 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
     m->gs.ensure(Ec * v.n * f);
   }
   for (int L = 0; L < v.nl; ++L) m->gam[L].ensure(Nc * v.dim * v.n * f);
+  m->ggam.ensure(Nc * v.dim * v.n * f);
   m->eij.ensure(Ec * f);
   m->gxa.ensure(Ec * v.d * f);
   m->gTf.ensure(Ec * v.n * f);
@@ -706,7 +709,6 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE((pos && species && forces) || m->n_total == 0, "pos, species and forces must not be NULL");
   const Validated& v = m->v;
-  const int prec = m->prec;
   const int d = v.d, n = v.n, LW = v.LW, dim = v.dim;
   double* aE = atom_energy ? atom_energy : ptr<double>(m->atom_e);
   const int32_t* ei = ptr<int32_t>(m->ei);
@@ -735,7 +737,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     m0.kind = kTwoBody; m0.w = m->twobody.view(); m0.head = m->head0.g; m0.head_bwd = m->head0T.g;
     m0.x_out = ptr<float>(m->x[0]); m0.head_out = ptr<float>(m->head0o);
     m0.tm = m->tm_choice[0];
-    timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, prec, s); });
+    timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, m->prec_two, s); });
 
     TensorArgs tb;
     tb.E = E; tb.n_centres = nc; tb.n = n; tb.l_max = v.lmax; tb.row_ptr = drp; tb.ei = ei + eA;
@@ -762,7 +764,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
       m1.x_prev = ptr<float>(m->x[0]); m1.s_in = ptr<float>(m->V1); m1.s_ld = dim * n;
       m1.x_out = ptr<float>(m->x[1]); m1.head_out = ptr<float>(m->wenv2);
       m1.tm = m->tm_choice[1];
-      timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(m1, prec, s); });
+      timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(m1, m->prec_lat, s); });
       TensorArgs t2 = tb;
       t2.w_env = ptr<float>(m->wenv2); t2.ld_w = LW; t2.gam = ptr<float>(m->gam[1]);
       timed(m, "env", s, [&] { return launch_env(t2, s); });
@@ -771,7 +773,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
       mf.w = m->latent[0].view(); mf.x_prev = ptr<float>(m->x[0]); mf.tp_v = v_a0; mf.tp_gam = ptr<float>(m->gam[0]);
     }
     mf.tm = m->tm_choice[2];
-    timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, prec, s); });
+    timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, m->prec_lat, s); });
 
     ReduceArgs ra;
     ra.n_centres = nc; ra.centre_base = (int)cA; ra.row_ptr = drp; ra.eij = ptr<float>(m->eij);
@@ -781,10 +783,10 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     // ---- adjoint ----
     mf.g_xprev = ptr<float>(m->gxa); mf.g_s = ptr<float>(m->gTf); mf.g_u = ptr<float>(m->gu); mf.gu_accum = 0;
     mf.tm = m->tm_choice[3];
-    timed(m, "mlp_bwd_final", s, [&] { return launch_mlp_bwd(mf, prec, s); });
+    timed(m, "mlp_bwd_final", s, [&] { return launch_mlp_bwd(mf, m->prec_lat, s); });
 
     TensorArgs tf = tb;
-    tf.g_t = ptr<float>(m->gTf); tf.g_Y = ptr<float>(m->gY); tf.gy_accum = 0;
+    tf.g_t = ptr<float>(m->gTf); tf.g_Y = ptr<float>(m->gY); tf.gy_accum = 0; tf.g_gam = ptr<float>(m->ggam);
     tf.tpw = ptr<float>(m->tpw[v.nl - 1]);
     set_tpw(tf, m->tpw_host[v.nl - 1]);
     if (v.nl == 2) {
@@ -801,7 +803,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
       m1.g_head = ptr<float>(m->gw2); m1.g_x = ptr<float>(m->gxa); m1.g_xprev = ptr<float>(m->gxb);
       m1.g_s = ptr<float>(m->gs); m1.g_u = ptr<float>(m->gu); m1.gu_accum = 1;
       m1.tm = m->tm_choice[4];
-      timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(m1, prec, s); });
+      timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(m1, m->prec_lat, s); });
       TensorArgs tm = tb;
       tm.g_tnext = ptr<float>(m->gTf); tm.gam_next = ptr<float>(m->gam[1]);
       for (int k = 0; k < 9; ++k) tm.tp_wnext[k] = m->tp_final[k];
@@ -811,14 +813,14 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
       t1b.g_t = ptr<float>(m->gT); t1b.v = v_a0; t1b.gam = ptr<float>(m->gam[0]);
       t1b.w_env = ptr<float>(m->head0o) + LW; t1b.ld_w = 2 * LW; t1b.tpw = ptr<float>(m->tpw[0]); set_tpw(t1b, m->tpw_host[0]);
       t1b.g_w = ptr<float>(m->ghead0) + LW; t1b.ld_gw = 2 * LW; t1b.g_a0 = ptr<float>(m->ghead0);
-      t1b.g_Y = ptr<float>(m->gY); t1b.gy_accum = 1;
+      t1b.g_Y = ptr<float>(m->gY); t1b.gy_accum = 1; t1b.g_gam = ptr<float>(m->ggam);
       timed(m, "tp_env_adjoint", s, [&] { return launch_tp_env_adjoint(t1b, false, s); });
       gx_two = ptr<float>(m->gxb);
     }
     m0.g_head = ptr<float>(m->ghead0); m0.g_x = gx_two; m0.g_u = ptr<float>(m->gu); m0.gu_accum = 1;
     m0.g_R = ptr<float>(m->gR);
     m0.tm = m->tm_choice[5];
-    timed(m, "mlp_bwd_twobody", s, [&] { return launch_mlp_bwd(m0, prec, s); });
+    timed(m, "mlp_bwd_twobody", s, [&] { return launch_mlp_bwd(m0, m->prec_two, s); });
 
     ea.g_Y = ptr<float>(m->gY); ea.g_R = ptr<float>(m->gR); ea.g_u = ptr<float>(m->gu);
     ea.g_e = ptr<float>(m->g_e) + 3 * eA;
@@ -1072,6 +1074,8 @@ int allegro_create(const AllegroConfig* cfg, const float* weights, int64_t n_wei
     m->cfg = *cfg;
     m->v = v;
     m->prec = cfg->precision;
+    // kernel precision per MLP (the same for all MLPs in the current modes)
+    m->prec_two = m->prec_lat = m->prec;
     create_impl(m, weights, n_weights, species_scale, species_shift);
     *out = m;
     return ALLEGRO_OK;

@@ -138,6 +138,7 @@ struct TensorArgs {
   float* g_a0 = nullptr;          // [E][(l_max+1) n] at row stride ld_gw (layer 1 only)
   float* g_Y = nullptr;           // [E][9]
   int gy_accum = 0;
+  float* g_gam = nullptr;         // [n_centres][dim][n] dE/dGamma (without the factor c)
 };
 
 // Kernel launchers (each returns hipSuccess or the launch error).

@@ -93,63 +93,67 @@ __device__ __forceinline__ f32x4 mma8(const float* a, const float* b, f32x4 c) {
 }
 
 // out[e][c][v] = scale * sum_k S[c][e][k] B_{l(c)}[k][v]   for the tile rows.
-// Work items (c, column tile) are dealt to the four waves; the B fragments of
-// the next item are loaded while the current one runs on the matrix cores.
-template <int DIM, int TT>
+// Each wave owns one 16-wide column tile of the output (with fewer column
+// tiles than waves, the waves also split the components): the B fragments of
+// that column tile for every l are loaded once into registers, then the wave
+// runs through its components with A fragments read from LDS.
+template <int LMAX, int TT>
 __device__ void mix_tile(const float* S, int lds_ld, const float* Bbase, int b_stride, int n, int Kp,
                          int Np, float scale, float* out, int64_t e0, int E) {
+  constexpr int DIM = (LMAX + 1) * (LMAX + 1);
   constexpr int RT = TT / 16;
   constexpr int MAXKB = 2;   // K = n <= 64
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
   const int nct = Np >> 4, nkb = Kp >> 5;
-  const int items = DIM * nct;
-  float bc[MAXKB][8], bn[MAXKB][8];
-  auto load_b = [&](int it, float (&dst)[MAXKB][8]) {
-    const int c = it / nct, nt = it - c * nct;
-    const float* B = Bbase + (size_t)lof(c) * b_stride;
+  // column tiles per wave pass and component stride between the waves sharing one
+  const int wpt = nct >= 4 ? 1 : 4 / nct;          // waves per column tile
+  for (int nt = wave % nct; nt < nct; nt += (nct >= 4 ? 4 : nct)) {
+    const int csub = nct >= 4 ? 0 : wave / nct;     // this wave's component offset
+    float b[LMAX + 1][MAXKB][8];
 #pragma unroll
-    for (int kb = 0; kb < MAXKB; ++kb)
-      if (kb < nkb) {
-        const float* bp = B + ((size_t)(nt * nkb + kb) * 64 + lane) * 8;
+    for (int l = 0; l <= LMAX; ++l)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) dst[kb][s] = bp[s];
+      for (int kb = 0; kb < MAXKB; ++kb) {
+        const int kk = kb < nkb ? kb : 0;
+        const float* bp = Bbase + (size_t)l * b_stride + ((size_t)(nt * nkb + kk) * 64 + lane) * 8;
+        const float4 lo = *(const float4*)bp, hi = *(const float4*)(bp + 4);
+        b[l][kb][0] = lo.x; b[l][kb][1] = lo.y; b[l][kb][2] = lo.z; b[l][kb][3] = lo.w;
+        b[l][kb][4] = hi.x; b[l][kb][5] = hi.y; b[l][kb][6] = hi.z; b[l][kb][7] = hi.w;
       }
-  };
-  if (wave < items) load_b(wave, bc);
-  for (int it = wave; it < items; it += 4) {
-    if (it + 4 < items) load_b(it + 4, bn);
-    const int c = it / nct, nt = it - c * nct;
-    f32x4 acc[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0, 0, 0, 0};
-#pragma unroll
-    for (int kb = 0; kb < MAXKB; ++kb) {
-      if (kb < nkb) {
-        const float* ap = S + (size_t)c * TT * lds_ld + (lane & 15) * lds_ld + kb * 32 + 8 * (lane >> 4);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          // two 16-byte LDS reads (row stride = 4 mod 64 banks: conflict-free)
-          const float4 lo = *(const float4*)(ap + rt * 16 * lds_ld);
-          const float4 hi = *(const float4*)(ap + rt * 16 * lds_ld + 4);
-          const float af[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-          acc[rt] = mma8(af, bc[kb], acc[rt]);
-        }
-      }
-    }
     const int col = nt * 16 + (lane & 15);
-    if (col < n) {
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
+    for (int l = 0; l <= LMAX; ++l) {
+#pragma unroll 1
+      for (int c = l * l; c < (l + 1) * (l + 1); ++c) {
+        if (c % wpt != csub) continue;
+        f32x4 acc[RT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = rt * 16 + 4 * (lane >> 4) + i;
-          if (e0 + r < E) out[((size_t)(e0 + r) * DIM + c) * n + col] = acc[rt][i] * scale;
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int kb = 0; kb < MAXKB; ++kb) {
+          if (kb < nkb) {
+            const float* ap = S + (size_t)c * TT * lds_ld + (lane & 15) * lds_ld + kb * 32 + 8 * (lane >> 4);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+              // two 16-byte LDS reads (row stride = 4 mod 64 banks: conflict-free)
+              const float4 lo = *(const float4*)(ap + rt * 16 * lds_ld);
+              const float4 hi = *(const float4*)(ap + rt * 16 * lds_ld + 4);
+              const float af[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+              acc[rt] = mma8(af, b[l][kb], acc[rt]);
+            }
+          }
         }
+        if (col < n) {
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = rt * 16 + 4 * (lane >> 4) + i;
+              if (e0 + r < E) out[((size_t)(e0 + r) * DIM + c) * n + col] = acc[rt][i] * scale;
+            }
+        }
+      }
     }
-#pragma unroll
-    for (int kb = 0; kb < MAXKB; ++kb)
-#pragma unroll
-      for (int s = 0; s < 8; ++s) bc[kb][s] = bn[kb][s];
   }
 }
 
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
   }
   __syncthreads();
   if (a.channel_mix) {
-    mix_tile<DIM, TT>(S, lds_ld, (const float*)a.mixB, a.mix_stride, n, Kp, Np, a.mix_scale, a.v_out, e0, a.E);
+    mix_tile<LMAX, TT>(S, lds_ld, (const float*)a.mixB, a.mix_stride, n, Kp, Np, a.mix_scale, a.v_out, e0, a.E);
   } else {
     for (int p = threadIdx.x; p < TT * DIM * n; p += 256) {
       const int r = p / (DIM * n), rem = p - r * DIM * n, c = rem / n, u = rem - c * n;
@@ -242,7 +246,7 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
   }
   __syncthreads();
   if (a.channel_mix) {
-    mix_tile<DIM, TT>(S, lds_ld, (const float*)a.mixB, a.mix_stride, n, Kp, Np, a.mix_scale, a.g_tout, e0, a.E);
+    mix_tile<LMAX, TT>(S, lds_ld, (const float*)a.mixB, a.mix_stride, n, Kp, Np, a.mix_scale, a.g_tout, e0, a.E);
   } else {
     for (int p = threadIdx.x; p < TT * DIM * n; p += 256) {
       const int r = p / (DIM * n), rem = p - r * DIM * n, c = rem / n, u = rem - c * n;
@@ -252,158 +256,212 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the tensor product and the environment sum: one wavefront per
-// centre, lane = channel (with n < 64, 64/n groups of lanes take interleaved
-// edges).  Pass 1 accumulates dE/dGamma over the centre's edges (and, when V
-// is built from a0 Y, emits dE/da0 and that part of dE/dY).  Pass 2 emits
-// dE/dw and the environment part of dE/dY.  Edges are processed in batches of
-// kBatch per group so that their loads are in flight together; the per-edge
-// sums over channels needed for dE/dY go through a padded LDS transpose
-// (one lane per (edge, component) row) instead of cross-lane shuffles.
+// Adjoint of the tensor product and the environment sum, in two kernels.
+//
+// k_tp_adjoint_gamma (one wavefront per centre; lane = channel u, and with
+// n < 64 the G = 64/n lane groups take interleaved edges) accumulates
+//   dE/dGamma_i[b][u] = sum_{e in N(i)} sum_{a,c} W[a][b][c] V_e[a][u] dE/dT_e[c][u]
+// in registers and writes it once per centre (without the factor c).
+//
+// k_tp_adjoint_edges (edge-parallel; G edges per wavefront step, each wave a
+// contiguous run of edges) then produces the per-edge gradients:
+//   dE/dw_e[l][u] = c sum_{b: l(b)=l} dE/dGamma_i[b][u] Y_e[b]
+//   dE/dY_e[b]   += c sum_u dE/dGamma_i[b][u] w_e[l(b)][u]
+// and, when V_e = a0_e[l(a)][u] Y_e[a] (first layer),
+//   dE/dV_e[a][u] = sum_{b,c} W[a][b][c] Gamma_i[b][u] dE/dT_e[c][u]
+//   dE/da0_e[l][u] = sum_{a: l(a)=l} dE/dV_e[a][u] Y_e[a]
+//   dE/dY_e[a]   += sum_u dE/dV_e[a][u] a0_e[l(a)][u].
+// The sums over channels are a reduce-scatter across the n lanes of a group
+// (17 exchanges for 16 values), in a fixed order: deterministic.
 constexpr int kBatch = 4;
-constexpr int kRedPerWave = 2600;   // >= kBatch * 9 * (64 + 64/n) for n in {8,...,64}
 
-template <int DIM>
-__device__ __forceinline__ void reduce_rows(const float* red, int rows, int n, int eb0, int eb1, int G,
-                                            int t, float* gY, bool keep, float scale, int lane) {
-  for (int idx = lane; idx < rows; idx += kWave) {
-    const int slot = idx / DIM, b = idx - slot * DIM;
-    const int j = slot / G, g = slot - j * G;
-    const int e = eb0 + g + G * (t * kBatch + j);
-    float sum = 0.0f;
-    const float* r = red + idx * (n + 1);
-    for (int u = 0; u < n; ++u) sum += r[u];
-    if (e < eb1) {
-      float* o = gY + (size_t)e * 9 + b;
-      *o = (keep ? *o : 0.0f) + sum * scale;
-    }
-  }
-}
-
-template <int LMAX, bool FINAL>
-__global__ __launch_bounds__(256) void k_tp_env_adjoint(TensorArgs a) {
+template <int LMAX, bool FINAL, int G>
+__global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
   using Pat = TpPattern<LMAX, FINAL>;
   constexpr int DIM = Pat::DIM, DOUT = Pat::DOUT;
-  __shared__ float red_all[4][kRedPerWave];
+  constexpr int n = kWave / G;
   const int lane = lane_id();
-  float* red = red_all[threadIdx.x >> 6];
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.n_centres) return;
-  const int n = a.n, G = kWave / n, u = lane & (n - 1), g = lane / n;
-  const float* w = a.tpw_v;   // kernel-argument array: uniform, read with scalar loads
-  float Gm[DIM], gG[DIM];
-  {
-    const float* gp = a.gam + (size_t)c * DIM * n + u;
+  const int u = lane & (n - 1), g = lane / n;
+  const float* w = a.tpw_v;
+  float gG[DIM];
 #pragma unroll
-    for (int b = 0; b < DIM; ++b) { Gm[b] = gp[b * n]; gG[b] = 0.0f; }
-  }
+  for (int b = 0; b < DIM; ++b) gG[b] = 0.0f;
   const int eb0 = a.row_ptr[c], eb1 = a.row_ptr[c + 1];
-  const int nbatch = (eb1 - eb0 + G * kBatch - 1) / (G * kBatch);   // uniform within the wave
-  const int rows = kBatch * G * DIM;
   const bool from_a0 = a.v.from_a0 != 0;
-  // ---- pass 1
-  for (int t = 0; t < nbatch; ++t) {
-    float V[kBatch][DIM], gT[kBatch][DOUT], a0v[kBatch][LMAX + 1], Yv[kBatch][DIM];
+  for (int e0 = eb0; e0 < eb1; e0 += G * kBatch) {
+    float V[kBatch][DIM], gT[kBatch][DOUT];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
-      const int e = eb0 + g + G * (t * kBatch + j);
+      const int e = e0 + g + G * j;
       const bool act = e < eb1;
-      const int ee = act ? e : eb0;
-      const float* Y = a.eb + (size_t)ee * kEB;
-      const float* vp = a.v.p + (size_t)ee * a.v.ld + u;
-      const float* gtp = a.g_t + (size_t)ee * DOUT * n + u;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) Yv[j][k] = Y[k];
+      const uint32_t ee = act ? e : eb0;
+      const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
+      const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
       if (from_a0) {
+        const float* Y = a.eb + ee * kEB;
+        float a0v[LMAX + 1];
 #pragma unroll
-        for (int l = 0; l <= LMAX; ++l) a0v[j][l] = act ? vp[l * n] : 0.0f;
+        for (int l = 0; l <= LMAX; ++l) a0v[l] = vp[l * n];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) V[j][k] = a0v[j][lof(k)] * Yv[j][k];
+        for (int k = 0; k < DIM; ++k) V[j][k] = a0v[lof(k)] * Y[k];
       } else {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) V[j][k] = act ? vp[k * n] : 0.0f;
+        for (int k = 0; k < DIM; ++k) V[j][k] = vp[k * n];
       }
 #pragma unroll
       for (int k = 0; k < DOUT; ++k) gT[j][k] = act ? gtp[k * n] : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) tp_adjoint_g<Pat>(V[j], gT[j], gG, w, std::make_index_sequence<Pat::NNZ>{});
-    if (from_a0) {
+  }
+  if constexpr (G > 1) {
 #pragma unroll
-      for (int j = 0; j < kBatch; ++j) {
-        const int e = eb0 + g + G * (t * kBatch + j);
-        const bool act = e < eb1;
-        float gV[DIM];
+    for (int b = 0; b < DIM; ++b) gG[b] = group_cross_sum(gG[b], n);
+  }
+  if (g == 0) {
+    float* out = a.g_gam + (size_t)c * DIM * n + u;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) gV[k] = 0.0f;
-        tp_adjoint_v<Pat>(Gm, gT[j], gV, w, std::make_index_sequence<Pat::NNZ>{});
-        float ga[LMAX + 1];
+    for (int b = 0; b < DIM; ++b) out[b * n] = gG[b];
+  }
+}
+
+// Sum of v[k] (k < 16) over the n lanes of each aligned lane group; on return
+// the lane with (lane & 15) == r holds the total of value index
+// k = 8 (r & 1) + 4 ((r >> 1) & 1) + 2 ((r >> 2) & 1) + ((r >> 3) & 1).
+template <int n>
+__device__ __forceinline__ float reduce_scatter16(float (&v)[16], int lane) {
+  static_assert(n >= 16, "groups of at least 16 lanes");
 #pragma unroll
-        for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
+  for (int h = 8, m = 1; h >= 1; h >>= 1, m <<= 1) {
+    const bool up = (lane & m) != 0;   // keep the upper half of the current values
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          ga[lof(k)] = fmaf(gV[k], Yv[j][k], ga[lof(k)]);
-          red[((j * G + g) * DIM + k) * (n + 1) + u] = gV[k] * a0v[j][lof(k)];
-        }
-        if (act) {
-#pragma unroll
-          for (int l = 0; l <= LMAX; ++l) a.g_a0[(size_t)e * a.ld_gw + l * n + u] = ga[l];
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      reduce_rows<DIM>(red, rows, n, eb0, eb1, G, t, a.g_Y, a.gy_accum != 0, 1.0f, lane);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = 0; j < h; ++j) {
+      const float keep = up ? v[j + h] : v[j];
+      const float send = up ? v[j] : v[j + h];
+      v[j] = keep + __shfl_xor(send, m, kWave);
     }
   }
+  float t = v[0];
 #pragma unroll
-  for (int b = 0; b < DIM; ++b) gG[b] = group_cross_sum(gG[b], n);
-  // ---- pass 2
-  const bool keep_gy = a.gy_accum || from_a0;
-  for (int t = 0; t < nbatch; ++t) {
-    float Yv[kBatch][DIM], wv[kBatch][LMAX + 1];
+  for (int m = 16; m < n; m <<= 1) t += __shfl_xor(t, m, kWave);
+  return t;
+}
+
+__device__ __forceinline__ int scatter_index(int lane) {
+  return 8 * (lane & 1) + 4 * ((lane >> 1) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 3) & 1);
+}
+
+constexpr int kEdgesPerWave = 32;
+
+// A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a].
+template <int LMAX, bool FINAL, int G, bool A0>
+__global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
+  using Pat = TpPattern<LMAX, FINAL>;
+  constexpr int DIM = Pat::DIM, DOUT = Pat::DOUT;
+  constexpr int n = kWave / G;
+  constexpr int KB = A0 ? 2 : 4;   // edges per lane group whose loads are issued together
+  const int lane = lane_id();
+  const int u = lane & (n - 1), g = lane / n;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t w0 = (int64_t)wave * kEdgesPerWave;
+  const float* w = a.tpw_v;
+  const bool keep_gy = a.gy_accum != 0;
+  const float cn = a.c_norm;
+  // centres of the wave's edges: one load per lane, read out per edge
+  const int64_t el = w0 + (lane & (kEdgesPerWave - 1));
+  const int ci_lane = el < a.E ? a.ei[el] - a.centre_base : 0;
+  for (int j0 = 0; j0 < kEdgesPerWave; j0 += G * KB) {
+    float gG[KB][DIM], Yv[KB][DIM], wv[KB][LMAX + 1];
+    float Gm[A0 ? KB : 1][DIM], gT[A0 ? KB : 1][DOUT], a0v[A0 ? KB : 1][LMAX + 1];
+    bool act[KB];
+    uint32_t eev[KB];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const int e = eb0 + g + G * (t * kBatch + j);
-      const bool act = e < eb1;
-      const int ee = act ? e : eb0;
-      const float* Y = a.eb + (size_t)ee * kEB;
-      const float* wp = a.w_env + (size_t)ee * a.ld_w + u;
+    for (int q = 0; q < KB; ++q) {
+      const int jj = j0 + g + G * q;
+      const int64_t e = w0 + jj;
+      act[q] = jj < kEdgesPerWave && e < a.E;
+      const uint32_t ee = act[q] ? (uint32_t)e : 0u;
+      eev[q] = ee;
+      const uint32_t ci = (uint32_t)__shfl(ci_lane, jj & (kEdgesPerWave - 1), kWave);
+      const float* ggp = a.g_gam + ci * (uint32_t)(DIM * n) + u;
+      const float* Y = a.eb + ee * kEB;
+      const float* wp = a.w_env + ee * (uint32_t)a.ld_w + u;
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) Yv[j][k] = Y[k];
+      for (int b = 0; b < DIM; ++b) { gG[q][b] = ggp[b * n]; Yv[q][b] = Y[b]; }
 #pragma unroll
-      for (int l = 0; l <= LMAX; ++l) wv[j][l] = act ? wp[l * n] : 0.0f;
+      for (int l = 0; l <= LMAX; ++l) wv[q][l] = wp[l * n];
+      if constexpr (A0) {
+        const float* gmp = a.gam + ci * (uint32_t)(DIM * n) + u;
+        const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
+        const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) Gm[q][b] = gmp[b * n];
+#pragma unroll
+        for (int k = 0; k < DOUT; ++k) gT[q][k] = gtp[k * n];
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) a0v[q][l] = vp[l * n];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const int e = eb0 + g + G * (t * kBatch + j);
+    for (int q = 0; q < KB; ++q) {
+      const uint32_t ee = eev[q];
+      float r[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) r[k] = 0.0f;
       float gw[LMAX + 1];
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) gw[l] = 0.0f;
 #pragma unroll
       for (int b = 0; b < DIM; ++b) {
-        gw[lof(b)] = fmaf(gG[b], Yv[j][b], gw[lof(b)]);
-        red[((j * G + g) * DIM + b) * (n + 1) + u] = gG[b] * wv[j][lof(b)];
+        gw[lof(b)] = fmaf(gG[q][b], Yv[q][b], gw[lof(b)]);
+        r[b] = cn * gG[q][b] * wv[q][lof(b)];
       }
-      if (e < eb1) {
+      if constexpr (A0) {
+        float gV[DIM];
 #pragma unroll
-        for (int l = 0; l <= LMAX; ++l) a.g_w[(size_t)e * a.ld_gw + l * n + u] = gw[l] * a.c_norm;
-        if (u == 0) {
+        for (int k = 0; k < DIM; ++k) gV[k] = 0.0f;
+        tp_adjoint_v<Pat>(Gm[q], gT[q], gV, w, std::make_index_sequence<Pat::NNZ>{});
+        float ga[LMAX + 1];
 #pragma unroll
-          for (int b = DIM; b < 9; ++b) a.g_Y[(size_t)e * 9 + b] = 0.0f;
+        for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          ga[lof(k)] = fmaf(gV[k], Yv[q][k], ga[lof(k)]);
+          r[k] = fmaf(gV[k], a0v[q][lof(k)], r[k]);
+        }
+        if (act[q]) {
+#pragma unroll
+          for (int l = 0; l <= LMAX; ++l) a.g_a0[ee * (uint32_t)a.ld_gw + l * n + u] = ga[l];
+        }
+      }
+      if (act[q]) {
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) a.g_w[ee * (uint32_t)a.ld_gw + l * n + u] = gw[l] * cn;
+      }
+      // sums over the group's channels
+      if constexpr (n >= 16) {
+        const float t = reduce_scatter16<n>(r, lane);
+        const int k = scatter_index(lane);
+        if (act[q] && u < 16 && k < 9) {
+          float* o = a.g_Y + ee * 9u + k;
+          const float val = k < DIM ? t : 0.0f;
+          *o = (keep_gy && k < DIM) ? *o + val : val;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) r[k] = group_inner_sum(r[k], n);
+        if (act[q] && u == 0) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            float* o = a.g_Y + ee * 9u + k;
+            const float val = k < DIM ? r[k] : 0.0f;
+            *o = (keep_gy && k < DIM) ? *o + val : val;
+          }
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    reduce_rows<DIM>(red, rows, n, eb0, eb1, G, t, a.g_Y, keep_gy, a.c_norm, lane);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -465,17 +523,32 @@ hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s) {
   return a.tile == 16 ? launch_mix_adjoint_tt<16>(a, s) : launch_mix_adjoint_tt<32>(a, s);
 }
 
-hipError_t launch_tp_env_adjoint(const TensorArgs& a, bool final_layer, hipStream_t s) {
-  if (a.n_centres <= 0) return hipSuccess;
-  const dim3 grid(blocks(a.n_centres, 4)), block(256);
-  if (a.l_max == 1) {
-    if (final_layer) hipLaunchKernelGGL((k_tp_env_adjoint<1, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_tp_env_adjoint<1, false>), grid, block, 0, s, a);
-  } else {
-    if (final_layer) hipLaunchKernelGGL((k_tp_env_adjoint<2, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_tp_env_adjoint<2, false>), grid, block, 0, s, a);
+template <int LMAX, bool FINAL, int G>
+hipError_t launch_adjoint_g(const TensorArgs& a, hipStream_t s) {
+  if (a.n_centres > 0)
+    hipLaunchKernelGGL((k_tp_adjoint_gamma<LMAX, FINAL, G>), dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
+  if (a.E > 0) {
+    const dim3 grid(blocks(a.E, 4 * kEdgesPerWave));
+    if (a.v.from_a0) hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G, false>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <int LMAX, bool FINAL>
+hipError_t launch_adjoint_n(const TensorArgs& a, hipStream_t s) {
+  switch (a.n) {
+    case 64: return launch_adjoint_g<LMAX, FINAL, 1>(a, s);
+    case 32: return launch_adjoint_g<LMAX, FINAL, 2>(a, s);
+    case 16: return launch_adjoint_g<LMAX, FINAL, 4>(a, s);
+    case 8: return launch_adjoint_g<LMAX, FINAL, 8>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tp_env_adjoint(const TensorArgs& a, bool final_layer, hipStream_t s) {
+  if (a.l_max == 1) return final_layer ? launch_adjoint_n<1, true>(a, s) : launch_adjoint_n<1, false>(a, s);
+  return final_layer ? launch_adjoint_n<2, true>(a, s) : launch_adjoint_n<2, false>(a, s);
 }
 
 }  // namespace allegro
