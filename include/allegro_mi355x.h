@@ -200,16 +200,25 @@ int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* spe
 
 /*
  * allegro_autotune: time the candidate edge-tile shapes of the edge-batched
- * kernels (MLP chains: 64 or 32 edges per tile in BF16, 32 or 16 in FP32;
- * tensor product / mixing: 32 or 16 edges) on the current neighbour list and
- * keep the fastest for each kernel kind.  Runs allegro_energy_forces six times
- * on internal buffers and synchronises the stream.
+ * kernels (MLP chains: 128, 64 or 32 edges per tile in BF16, 32 or 16 in
+ * FP32; tensor product / mixing: 32 or 16 edges) on the current neighbour list
+ * and keep the fastest for each kernel kind.  Runs allegro_energy_forces three
+ * times per candidate on internal buffers and synchronises the stream.
  *   choices  host [8] int32 receiving the chosen tiles, in the order
  *            mlp_fwd_twobody, mlp_fwd_latent, mlp_fwd_final, mlp_bwd_final,
  *            mlp_bwd_latent, mlp_bwd_twobody, tp_mix, mix_adjoint (may be NULL)
  */
 int allegro_autotune(AllegroModel* m, const double* pos, const int32_t* species, void* stream,
                      int32_t* choices);
+
+/*
+ * allegro_set_tiles: set the edge-tile shapes directly (same order and values
+ * as allegro_autotune's choices; 0 = the library's default, which for BF16
+ * MLP chains is the 128-edge tile where it fits in LDS).  Host array of 8
+ * int32, copied.  Returns ALLEGRO_E_INVAL for a value not available in the
+ * model's precision.
+ */
+int allegro_set_tiles(AllegroModel* m, const int32_t* tiles);
 
 /*
  * allegro_set_ghosts: declare ghosts as periodic images of local atoms, for

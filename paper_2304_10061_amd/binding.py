@@ -25,7 +25,7 @@ PREC_FP32, PREC_BF16, PREC_BF16_SINGLE = 0, 1, 2
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ("allegro_describe", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
            "allegro_system_energies", "allegro_energy_forces",
-           "allegro_autotune", "allegro_set_ghosts", "allegro_md_run", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
+           "allegro_autotune", "allegro_set_tiles", "allegro_set_ghosts", "allegro_md_run", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
            "allegro_workspace_bytes", "allegro_destroy", "allegro_last_error", "allegro_status_string")
 
 
@@ -79,6 +79,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_energy_forces.restype = ctypes.c_int
     lib.allegro_autotune.argtypes = [vp, dp, dp, vp, vp]
     lib.allegro_autotune.restype = ctypes.c_int
+    lib.allegro_set_tiles.argtypes = [vp, vp]
+    lib.allegro_set_tiles.restype = ctypes.c_int
     lib.allegro_set_ghosts.argtypes = [vp, i64, i64, vp, vp]
     lib.allegro_set_ghosts.restype = ctypes.c_int
     lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, i32, i32, vp,
@@ -233,13 +235,21 @@ class Model:
                                                    _ptr(forces), _ptr(virial), _ptr(atom_virial),
                                                    _ptr(energy), _stream(stream)))
 
+    TILE_KINDS = ("mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd_final", "mlp_bwd_final", "mlp_bwd_latent",
+                  "mlp_bwd_twobody", "tp_mix", "mix_adjoint")
+
     def autotune(self, pos, species, stream=None):
         """Pick the fastest edge-tile shapes on the current neighbour list."""
         ch = (ctypes.c_int32 * 8)()
         self._check(self.lib.allegro_autotune(self.handle, _ptr(pos), _ptr(species), _stream(stream), ch))
-        names = ("mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd_final", "mlp_bwd_final", "mlp_bwd_latent",
-                 "mlp_bwd_twobody", "tp_mix", "mix_adjoint")
-        return dict(zip(names, list(ch)))
+        return dict(zip(self.TILE_KINDS, list(ch)))
+
+    def set_tiles(self, tiles):
+        """Set edge-tile shapes: a dict over TILE_KINDS (missing = 0, the default) or 8 ints."""
+        if isinstance(tiles, dict):
+            tiles = [int(tiles.get(k, 0)) for k in self.TILE_KINDS]
+        arr = (ctypes.c_int32 * 8)(*[int(t) for t in tiles])
+        self._check(self.lib.allegro_set_tiles(self.handle, arr))
 
     def set_ghosts(self, n_local: int, owner, offset):
         """Ghost g = atom n_local + g is owner[g]'s image at offset[g] (host arrays)."""

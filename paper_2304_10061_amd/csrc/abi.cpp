@@ -295,6 +295,7 @@ struct AllegroModel {
   // workspace
   DevBuf eb, x[2], head0o, wenv2, V1, gam[2], eij, gxa, gxb, gTf, gs, ghead0, gw2, gT, gY, gu, gR;
   DevBuf ggam;   // dE/dGamma of the layer being differentiated [centres][dim][n]
+  DevBuf zscr;   // hidden pre-activations of the 128-row backward MLP kernels
   DevBuf g_e, atom_e, partial;
 };
 
@@ -694,6 +695,7 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   m->gY.ensure(Ec * 9 * f);
   m->gu.ensure(Ec * f);
   m->gR.ensure(Ec * v.nb * f);
+  if (m->prec != ALLEGRO_PREC_FP32) m->zscr.ensure(mlp_tall_scratch_bytes(Ec, v.d));
   m->g_e.ensure(Ee * 3 * f);
   m->atom_e.ensure(std::max<int64_t>(n_local, 1) * sizeof(double));
   m->partial.ensure(((nt + 255) / 256) * 10 * sizeof(double));
@@ -782,6 +784,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
 
     // ---- adjoint ----
     mf.g_xprev = ptr<float>(m->gxa); mf.g_s = ptr<float>(m->gTf); mf.g_u = ptr<float>(m->gu); mf.gu_accum = 0;
+    mf.g_store = mf.g_xprev; mf.act_scratch = m->zscr.p;
     mf.tm = m->tm_choice[3];
     timed(m, "mlp_bwd_final", s, [&] { return launch_mlp_bwd(mf, m->prec_lat, s); });
 
@@ -802,6 +805,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     if (v.nl == 2) {
       m1.g_head = ptr<float>(m->gw2); m1.g_x = ptr<float>(m->gxa); m1.g_xprev = ptr<float>(m->gxb);
       m1.g_s = ptr<float>(m->gs); m1.g_u = ptr<float>(m->gu); m1.gu_accum = 1;
+      m1.g_store = m1.g_xprev; m1.act_scratch = m->zscr.p;
       m1.tm = m->tm_choice[4];
       timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(m1, m->prec_lat, s); });
       TensorArgs tm = tb;
@@ -819,6 +823,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     }
     m0.g_head = ptr<float>(m->ghead0); m0.g_x = gx_two; m0.g_u = ptr<float>(m->gu); m0.gu_accum = 1;
     m0.g_R = ptr<float>(m->gR);
+    m0.g_store = gx_two; m0.act_scratch = m->zscr.p;   // the two-body backward reuses its g_x rows
     m0.tm = m->tm_choice[5];
     timed(m, "mlp_bwd_twobody", s, [&] { return launch_mlp_bwd(m0, m->prec_two, s); });
 
@@ -934,7 +939,9 @@ const char* const kTuneNames[8] = {"mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd
 void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, hipStream_t s, int32_t* choices) {
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE((pos && species) || m->n_total == 0, "pos and species must not be NULL");
-  const int cand_tm[2] = {m->prec ? 64 : 32, m->prec ? 32 : 16};
+  // MLP tile rows: BF16 {128 (tall tiles), 64, 32}, FP32 {32, 16}; tensor tiles {32, 16}
+  const int ntm = m->prec ? 3 : 2;
+  const int cand_tm[3] = {m->prec ? 128 : 32, m->prec ? 64 : 16, 32};
   const int cand_tt[2] = {32, 16};
   m->tune_forces.ensure(std::max<int64_t>(m->n_total, 1) * 3 * sizeof(double));
   m->md_epot.ensure(sizeof(double));
@@ -942,9 +949,9 @@ void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, h
   int pick[8];
   for (int k = 0; k < 8; ++k) { best[k] = 1e300; pick[k] = 0; }
   const bool was = m->timing;
-  for (int c = 0; c < 2; ++c) {
+  for (int c = 0; c < ntm; ++c) {
     for (int k = 0; k < 6; ++k) m->tm_choice[k] = cand_tm[c];
-    for (int k = 0; k < 2; ++k) m->tt_choice[k] = cand_tt[c];
+    for (int k = 0; k < 2; ++k) m->tt_choice[k] = cand_tt[c < 2 ? c : 1];
     // warm-up, then two timed evaluations
     m->timing = false;
     energy_forces_impl(m, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
@@ -958,7 +965,7 @@ void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, h
     collect_times(m);
     for (int k = 0; k < 8; ++k)
       for (const auto& kt : m->ktimes)
-        if (kt.name == kTuneNames[k] && kt.ms < best[k]) {
+        if (kt.name == kTuneNames[k] && kt.ms < best[k] && (k < 6 || c < 2)) {
           best[k] = kt.ms;
           pick[k] = k < 6 ? cand_tm[c] : cand_tt[c];
         }
@@ -975,6 +982,27 @@ void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, h
 }  // namespace
 
 extern "C" {
+
+int allegro_set_tiles(AllegroModel* m, const int32_t* tiles) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    REQUIRE(tiles != nullptr, "tiles is NULL");
+    for (int k = 0; k < 6; ++k) {
+      const int t = tiles[k];
+      const bool ok = t == 0 || (m->prec ? (t == 128 || t == 64 || t == 32) : (t == 32 || t == 16));
+      REQUIRE(ok, std::string("tile rows ") + std::to_string(t) + " not available for " + kTuneNames[k]);
+    }
+    for (int k = 6; k < 8; ++k)
+      REQUIRE(tiles[k] == 0 || tiles[k] == 16 || tiles[k] == 32,
+              std::string("tile rows ") + std::to_string(tiles[k]) + " not available for " + kTuneNames[k]);
+    for (int k = 0; k < 6; ++k) m->tm_choice[k] = tiles[k];
+    for (int k = 0; k < 2; ++k) m->tt_choice[k] = tiles[6 + k];
+    release_graph(m);
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
+  }
+}
 
 int allegro_autotune(AllegroModel* m, const double* pos, const int32_t* species, void* stream, int32_t* choices) {
   if (!m) return ALLEGRO_E_INVAL;

@@ -86,6 +86,9 @@ struct MlpArgs {
   float* g_u = nullptr;           // [E]
   int gu_accum = 0;
   float* g_R = nullptr;           // two-body: [E][n_bessel]
+  // tall-tile backward only
+  float* g_store = nullptr;       // [E][d] receives dE/dx_out (g_xprev, or g_x itself for two-body)
+  void* act_scratch = nullptr;    // hidden pre-activations of the recomputation (fragment order)
 };
 
 struct EdgeArgs {
@@ -148,6 +151,7 @@ hipError_t launch_mlp_fwd(const MlpArgs& a, int prec, hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpArgs& a, int prec, hipStream_t s);
 size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd);
 bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm);
+size_t mlp_tall_scratch_bytes(int64_t E, int d);   // scratch of the 128-row backward kernels
 hipError_t launch_env(const TensorArgs& a, hipStream_t s);
 hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s);
 hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s);

@@ -28,9 +28,20 @@ bool fits(const MlpArgs& a, bool bwd, int tm) {
   return bytes <= kLdsLimit;
 }
 
+bool tall_fits(const MlpArgs& a, int prec, bool bwd) {
+  if (!tall_ok(a, prec, bwd)) return false;
+  int ldx;
+  size_t bytes;
+  tall_dims(a, &ldx, &bytes);
+  return bytes <= kLdsLimit;
+}
+
 hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
   if (a.E <= 0) return hipSuccess;
   if (prec == 1 || prec == 2) {
+    // tall tiles by default (tm == 0) or on request, where they fit
+    if ((a.tm == kTallRows || a.tm == 0) && tall_fits(a, prec, bwd))
+      return prec == 1 ? launch_prec<1>(a, kTallRows, bwd, s) : launch_prec<2>(a, kTallRows, bwd, s);
     const int tm = (a.tm == 64 || a.tm == 32) && fits<1>(a, bwd, a.tm) ? a.tm : pick_tm<1>(a, bwd);
     if (tm == 0) return hipErrorInvalidValue;
     return prec == 1 ? launch_prec<1>(a, tm, bwd, s) : launch_prec<2>(a, tm, bwd, s);
@@ -55,9 +66,12 @@ size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd) {
 }
 
 bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm) {
+  if (prec && tm == kTallRows) return tall_fits(a, prec, bwd);
   if (prec) return (tm == 64 || tm == 32) && fits<1>(a, bwd, tm);
   return (tm == 32 || tm == 16) && fits<0>(a, bwd, tm);
 }
+
+size_t mlp_tall_scratch_bytes(int64_t E, int d) { return tall_scratch_bytes(E, d); }
 
 hipError_t launch_mlp_fwd(const MlpArgs& a, int prec, hipStream_t s) { return launch(a, prec, false, s); }
 hipError_t launch_mlp_bwd(const MlpArgs& a, int prec, hipStream_t s) { return launch(a, prec, true, s); }

@@ -31,10 +31,6 @@
 #include "devutil.h"
 #include "internal.h"
 
-#ifndef ALLEGRO_PF
-#define ALLEGRO_PF 1
-#endif
-
 namespace allegro {
 namespace mlpk {
 
@@ -96,7 +92,11 @@ __device__ __forceinline__ int npasses(int Np) { return (Np / 16 + 4 * MAXCT - 1
 // tile (their results are never stored), and the B fragments of the next K
 // block are requested before the MFMAs of the current one, so L2 latency
 // overlaps matrix-core work.  `wave` must be wave-uniform (readfirstlane).
-template <int PREC, int RT, int MAXCT>
+//
+// PREF_A: the A fragments of the next K block are also requested ahead (two
+// register sets); without it (tall tiles, RT = 8) each row tile's A fragment
+// is read from LDS just before its MFMAs.
+template <int PREC, int RT, int MAXCT, bool PREF_A = true>
 __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
                                           int lda, const GemmB& B, int wave, int lane, int pass,
                                           int kb0 = 0, int kb1 = -1, bool zero = true) {
@@ -114,6 +114,7 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
   // PREC 1 keeps each weight as a pair of BF16 values (hi + lo, lo stored
   // after the hi fragments) and issues two MFMAs per product.
   constexpr bool kSplit = PREC == 1;
+  constexpr int NA = PREF_A ? RT : 1;
   const size_t lo_off = (size_t)B.Kp * B.Np;
   const T* Bl = (const T*)B.p + (size_t)lane * 8;
   const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4) - kb0 * 32;
@@ -124,61 +125,58 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
     nt = nt < nct ? nt : nct - 1;
     boff[q] = (size_t)(nt * nkb) * 512;
   }
-  // Register buffers of A and B fragments, used in rotation: the fragments
-  // of K block kb + PF are requested before the MFMAs of block kb.
+  // Register buffers of B (and A) fragments, used in rotation: the fragments
+  // of K block kb + 1 are requested before the MFMAs of block kb.
   // Scheduling barriers keep the compiler from sinking those loads next to
   // their first use.
-  F a0[RT], a1[RT], b0[MAXCT], b1[MAXCT], l0[kSplit ? MAXCT : 1], l1[kSplit ? MAXCT : 1];
-  auto load = [&](F (&aa)[RT], F (&bb)[MAXCT], F (&ll)[kSplit ? MAXCT : 1], int kb) {
+  F a0[NA], a1[NA], b0[MAXCT], b1[MAXCT], l0[kSplit ? MAXCT : 1], l1[kSplit ? MAXCT : 1];
+  auto load = [&](F (&aa)[NA], F (&bb)[MAXCT], F (&ll)[kSplit ? MAXCT : 1], int kb) {
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
       bb[q] = P::load(Bl + boff[q] + (size_t)kb * 512);
       if constexpr (kSplit) ll[q] = P::load(Bl + lo_off + boff[q] + (size_t)kb * 512);
     }
+    if constexpr (PREF_A) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) aa[rt] = P::load(Arow + rt * 16 * lda + kb * 32);
-    __builtin_amdgcn_sched_barrier(0);
-  };
-  auto compute = [&](const F (&aa)[RT], const F (&bb)[MAXCT], const F (&ll)[kSplit ? MAXCT : 1]) {
-    if constexpr (kSplit) {
-#pragma unroll
-      for (int q = 0; q < MAXCT; ++q)
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(aa[rt], ll[q], acc[rt][q]);
+      for (int rt = 0; rt < RT; ++rt) aa[rt] = P::load(Arow + rt * 16 * lda + kb * 32);
     }
-#pragma unroll
-    for (int q = 0; q < MAXCT; ++q)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt][q] = P::mma(aa[rt], bb[q], acc[rt][q]);
     __builtin_amdgcn_sched_barrier(0);
   };
   auto clampk = [&](int k) { return k < kb1 ? k : kb1 - 1; };   // tail re-requests a loaded block
-#if ALLEGRO_PF == 2
-  F a2[RT], b2[MAXCT], l2[kSplit ? MAXCT : 1];
-  load(a0, b0, l0, kb0);
-  load(a1, b1, l1, clampk(kb0 + 1));
-  int kb = kb0;
-  for (; kb + 2 < kb1; kb += 3) {
-    load(a2, b2, l2, kb + 2);
-    compute(a0, b0, l0);
-    load(a0, b0, l0, clampk(kb + 3));
-    compute(a1, b1, l1);
-    load(a1, b1, l1, clampk(kb + 4));
-    compute(a2, b2, l2);
-  }
-  if (kb < kb1) compute(a0, b0, l0);
-  if (kb + 1 < kb1) compute(a1, b1, l1);
-#else
+  // without PREF_A: the A fragment of the next (row tile, K block) step is
+  // read from LDS before the MFMAs of the current one
+  F anext;
+  if constexpr (!PREF_A) anext = P::load(Arow + kb0 * 32);
+  auto compute = [&](const F (&aa)[NA], const F (&bb)[MAXCT], const F (&ll)[kSplit ? MAXCT : 1], int kb) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      F a;
+      if constexpr (PREF_A) {
+        a = aa[PREF_A ? rt : 0];
+      } else {
+        a = anext;
+        anext = rt + 1 < RT ? P::load(Arow + (rt + 1) * 16 * lda + kb * 32)
+                            : P::load(Arow + clampk(kb + 1) * 32);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if constexpr (kSplit) {
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) acc[rt][q] = P::mma(a, ll[q], acc[rt][q]);
+      }
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) acc[rt][q] = P::mma(a, bb[q], acc[rt][q]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
   load(a0, b0, l0, kb0);
   int kb = kb0;
   for (; kb + 1 < kb1; kb += 2) {
     load(a1, b1, l1, kb + 1);
-    compute(a0, b0, l0);
+    compute(a0, b0, l0, kb);
     load(a0, b0, l0, clampk(kb + 2));
-    compute(a1, b1, l1);
+    compute(a1, b1, l1, kb + 1);
   }
-  if (kb < kb1) compute(a0, b0, l0);
-#endif
+  if (kb < kb1) compute(a0, b0, l0, kb);
   // tiles clamped onto the last one hold copies: zero them so that register
   // uses of acc (gradients, dot products) see exact zeros there
 #pragma unroll
@@ -473,7 +471,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh)
           const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
           if (col < d) sum = fmaf(acc[rt][q][i], a.we[col], sum);
         }
-        sum = group_inner_sum(sum, 16);
+        sum = group_sum_dpp<16>(sum);
         if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
       }
     __syncthreads();
@@ -575,13 +573,14 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh)
       const int w = (kb1 - kb0) * 32;
       stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, w);
       __syncthreads();
-      gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, true);
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int q = 0; q < MAXCT; ++q) G[rt][q] += acc[rt][q];
+      gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, kb0 == 0);
       __syncthreads();
     }
+    // the K sum continues across chunks in the accumulators; G = g_x + sum
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) G[rt][q] += acc[rt][q];
   }
 
   // 2. recompute the chain, keeping hidden pre-activations
@@ -599,7 +598,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh)
       float sum = 0.0f;
 #pragma unroll
       for (int q = 0; q < MAXCT; ++q) sum = fmaf(G[rt][q][i], acc[rt][q][i], sum);
-      sum = group_inner_sum(sum, 16);
+      sum = group_sum_dpp<16>(sum);
       if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
     }
   __syncthreads();   // also: every wave is done reading `in`
@@ -666,6 +665,306 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tall tiles: 128 edges per block.  Every wave computes all 128 rows of its
+// column tiles (RT = 8), so each weight fragment read from L2 feeds eight row
+// tiles (half the L2 traffic per MFMA of a 64-row tile).  Activations live in
+// one LDS buffer and are updated in place: a layer's output overwrites its
+// input after a barrier.  Requires every hidden width to fit one pass
+// (<= 64 MAXCT columns).  The backward kernel writes the hidden
+// pre-activations of its recomputation to a global scratch array in register
+// (fragment) order, and dE/dx_out to the output row it is added to at the
+// end.  Per element the arithmetic is the same as in the 64- and 32-row
+// kernels, so all tile shapes give identical results.
+constexpr int kTallRows = 128;
+
+// Scratch slot of fragment (rt, q) of this wave for hidden layer l.
+template <int MAXCT>
+__device__ __forceinline__ size_t zslot(int l, int wave, int q, int rt, int lane) {
+  return (((((size_t)blockIdx.x * 2 + l) * 4 + wave) * MAXCT + q) * 8 + rt) * 64 + lane;
+}
+
+template <int PREC, int KIND, int MAXCT>
+__global__ __launch_bounds__(256, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
+  using T = typename PT<PREC>::T;
+  constexpr int TM = kTallRows, RT = 8;
+  extern __shared__ __align__(16) char smem[];
+  T* X = (T*)smem;
+  __shared__ float red[4][TM];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int e0 = blockIdx.x * TM;
+  const int d = a.d, nl = a.w.nl;
+
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  __syncthreads();
+  f32x4 acc[RT][MAXCT];
+  for (int l = 0; l + 1 < nl; ++l) {
+    gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.fwd[l], wave, lane, 0);
+    __syncthreads();
+    store_tile<PREC, RT, MAXCT>(acc, X, ldx, a.w.fwd[l].Np, wave, lane, 0,
+                                [](float v, int, int) { return silu(v); });
+    __syncthreads();
+  }
+  gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.fwd[nl - 1], wave, lane, 0);
+  // epilogue in row-tile pairs (loads of a pair issued together):
+  // x = u h (two-body) or rs (x_prev + u h), zero beyond E and d
+#pragma unroll
+  for (int r0 = 0; r0 < RT; r0 += 2) {
+    float ur[2][4], xp[2][MAXCT][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
+        e = e < a.E ? e : a.E - 1;
+        ur[h][i] = a.eb[(uint32_t)e * kEB + kEB_U];
+        if constexpr (KIND != kTwoBody) {
+#pragma unroll
+          for (int q = 0; q < MAXCT; ++q) {
+            int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+            col = col < d ? col : d - 1;
+            xp[h][q][i] = a.x_prev[(uint32_t)e * d + col];
+          }
+        }
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) {
+        const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
+          float v = ur[h][i] * acc[r0 + h][q][i];
+          if constexpr (KIND != kTwoBody) v = a.res_scale * (xp[h][q][i] + v);
+          const bool ok = e < a.E && col < d;
+          v = ok ? v : 0.0f;
+          acc[r0 + h][q][i] = v;
+          if (ok && a.x_out) a.x_out[(uint32_t)e * d + col] = v;
+        }
+      }
+  }
+  if constexpr (KIND == kLatentFinal) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) {
+          const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+          if (col < d) sum = fmaf(acc[rt][q][i], a.we[col], sum);
+        }
+        sum = group_sum_dpp<16>(sum);
+        if ((lane & 15) == 0) red[wave][rt * 16 + 4 * (lane >> 4) + i] = sum;
+      }
+    __syncthreads();
+    if ((int)threadIdx.x < TM) {
+      const int e = e0 + threadIdx.x;
+      if (e < a.E)
+        a.eij[e] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    }
+    return;
+  } else {
+    if (a.head.p == nullptr) return;
+    __syncthreads();   // every wave is done reading X
+    store_tile<PREC, RT, MAXCT>(acc, X, ldx, a.w.fwd[nl - 1].Np, wave, lane, 0, [](float v, int, int) { return v; });
+    __syncthreads();
+    const int Nh = a.head.N;
+    for (int p = 0; p < npasses<MAXCT>(a.head.Np); ++p) {
+      gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.head, wave, lane, p);
+#pragma unroll
+      for (int q = 0; q < MAXCT; ++q) {
+        const int col = tile_of<MAXCT>(p, q, wave) * 16 + (lane & 15);
+        if (col >= Nh) continue;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+            if (e < a.E) a.head_out[(uint32_t)e * Nh + col] = acc[rt][q][i];
+          }
+      }
+    }
+  }
+}
+
+template <int PREC, int KIND, int MAXCT>
+__global__ __launch_bounds__(256, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, int) {
+  using T = typename PT<PREC>::T;
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  constexpr int TM = kTallRows, RT = 8;
+  extern __shared__ __align__(16) char smem[];
+  T* X = (T*)smem;
+  __shared__ float red[4][TM];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int e0 = blockIdx.x * TM;
+  const int d = a.d, nl = a.w.nl;
+  const float rs = (KIND == kTwoBody) ? 1.0f : a.res_scale;
+  bf16x4* zs = (bf16x4*)a.act_scratch;
+  float* gst = a.g_store;
+
+  // 1. G = dE/dx_out -> g_store (head part on MFMA, K staged through X)
+  f32x4 acc[RT][MAXCT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  if constexpr (KIND != kLatentFinal) {
+    if (a.head_bwd.p != nullptr) {
+      const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5, chunk = ldx >> 5;
+      for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
+        const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
+        stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, (kb1 - kb0) * 32);
+        __syncthreads();
+        gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, false);
+        __syncthreads();
+      }
+    }
+  }
+  {
+    const float* gsrc = KIND == kLatentFinal ? a.g_const : a.g_x;
+#pragma unroll
+    for (int r0 = 0; r0 < RT; r0 += 2) {
+      float gv[2][MAXCT][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
+          e = e < a.E ? e : a.E - 1;
+          const uint32_t ro = (uint32_t)(KIND == kLatentFinal ? a.species[a.ei[e]] : e) * d;
+#pragma unroll
+          for (int q = 0; q < MAXCT; ++q) {
+            int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+            col = col < d ? col : d - 1;
+            gv[h][q][i] = gsrc ? gsrc[ro + col] : 0.0f;
+          }
+        }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) {
+          const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
+            if (e < a.E && col < d) gst[(uint32_t)e * d + col] = gv[h][q][i] + acc[r0 + h][q][i];
+          }
+        }
+    }
+  }
+
+  // 2. recompute the chain; hidden pre-activations to the scratch array
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  __syncthreads();
+  for (int l = 0; l + 1 < nl; ++l) {
+    gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.fwd[l], wave, lane, 0);
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const f32x4 v = acc[rt][q];
+        zs[zslot<MAXCT>(l, wave, q, rt, lane)] = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+      }
+    __syncthreads();
+    store_tile<PREC, RT, MAXCT>(acc, X, ldx, a.w.fwd[l].Np, wave, lane, 0,
+                                [](float v, int, int) { return silu(v); });
+    __syncthreads();
+  }
+  gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.fwd[nl - 1], wave, lane, 0);   // acc = h
+
+  // 3. dE/du = rs sum_c G h ; dE/dh = rs u G
+#pragma unroll
+  for (int r0 = 0; r0 < RT; r0 += 2) {
+    float gv[2][MAXCT][4], ur[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
+        const bool ok = e < a.E;
+        e = ok ? e : a.E - 1;
+        ur[h][i] = ok ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) {
+          int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
+          const bool okc = ok && col < d;
+          col = col < d ? col : d - 1;
+          const float g = gst[(uint32_t)e * d + col];
+          gv[h][q][i] = okc ? g : 0.0f;
+        }
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < MAXCT; ++q) {
+          sum = fmaf(gv[h][q][i], acc[r0 + h][q][i], sum);
+          acc[r0 + h][q][i] = rs * ur[h][i] * gv[h][q][i];
+        }
+        sum = group_sum_dpp<16>(sum);
+        if ((lane & 15) == 0) red[wave][(r0 + h) * 16 + 4 * (lane >> 4) + i] = sum;
+      }
+  }
+  __syncthreads();   // red complete; every wave is done reading X
+  if ((int)threadIdx.x < TM) {
+    const int e = e0 + threadIdx.x;
+    if (e < a.E) {
+      const float gu = rs * (((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                             red[3][threadIdx.x]);
+      a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
+    }
+  }
+  store_tile<PREC, RT, MAXCT>(acc, X, ldx, a.w.fwd[nl - 1].Np, wave, lane, 0, [](float v, int, int) { return v; });
+  __syncthreads();
+
+  // 4. back through the hidden layers, in place
+  for (int l = nl - 1; l > 0; --l) {
+    gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.bwd[l], wave, lane, 0);
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const bf16x4 z = zs[zslot<MAXCT>(l - 1, wave, q, rt, lane)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[rt][q][i] *= silu_grad((float)z[i]);
+      }
+    __syncthreads();
+    store_tile<PREC, RT, MAXCT>(acc, X, ldx, a.w.bwd[l].Np, wave, lane, 0, [](float v, int, int) { return v; });
+    __syncthreads();
+  }
+
+  // 5. dE/dz, written to the outputs (g_xprev holds dE/dx_out)
+  const int S = a.n_species;
+  const GemmB& B0 = a.w.bwd[0];
+  for (int p = 0; p < npasses<MAXCT>(B0.Np); ++p) {
+    gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, B0, wave, lane, p);
+#pragma unroll
+    for (int q = 0; q < MAXCT; ++q) {
+      const int col = tile_of<MAXCT>(p, q, wave) * 16 + (lane & 15);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
+          if (e >= a.E) continue;
+          const float g = acc[rt][q][i];
+          if constexpr (KIND == kTwoBody) {
+            if (col >= 2 * S && col < 2 * S + a.n_bessel) a.g_R[(uint32_t)e * a.n_bessel + col - 2 * S] = g;
+          } else if (col < d) {
+            float* o = a.g_xprev + (uint32_t)e * d + col;
+            *o = rs * *o + g;
+          } else if (col < d + a.n) {
+            a.g_s[(uint32_t)e * a.n + col - d] = g;
+          }
+        }
+    }
+  }
+}
+
 // LDS layout: X [TM][ldx] and H [TM][ldh] (+ nl-1 pre-activation buffers of
 // [TM][ldh] in the backward kernel).
 template <int PREC>
@@ -686,6 +985,32 @@ inline int max_ct(const MlpArgs& a) {
   return (dt + 3) / 4;
 }
 
+// Tall tiles (BF16 only): one LDS buffer [128][ldx]; every hidden width and
+// d must fit one pass of 64 MAXCT columns; the backward kernel needs its
+// scratch arrays.
+inline bool tall_ok(const MlpArgs& a, int prec, bool bwd) {
+  if (prec == 0) return false;
+  const int cols = 64 * max_ct(a);
+  for (int l = 0; l < a.w.nl; ++l)
+    if (a.w.fwd[l].Np > cols) return false;
+  if (bwd && (a.g_store == nullptr || (a.w.nl > 1 && a.act_scratch == nullptr))) return false;
+  return a.w.nl <= 3;
+}
+
+inline void tall_dims(const MlpArgs& a, int* ldx, size_t* bytes) {
+  int k = a.w.fwd[0].Kp;
+  for (int l = 0; l < a.w.nl; ++l) k = k > a.w.fwd[l].Np ? k : a.w.fwd[l].Np;
+  *ldx = k + 8;
+  *bytes = (size_t)kTallRows * *ldx * 2;
+}
+
+// Bytes of the pre-activation scratch array for E rows (two hidden layers of
+// 64 MAXCT columns per 128-row tile, BF16).
+inline size_t tall_scratch_bytes(int64_t E, int d) {
+  const int ct = ((d + 15) / 16 + 3) / 4;
+  return (size_t)((E + kTallRows - 1) / kTallRows) * 2 * kTallRows * 64 * ct * 2;
+}
+
 constexpr size_t kLdsLimit = 160 * 1024 - 4096;
 
 template <int PREC, int KIND, int TM, int MAXCT>
@@ -699,6 +1024,28 @@ hipError_t launch_one(const MlpArgs& a, bool bwd, hipStream_t s) {
   if (st != hipSuccess) return st;
   hipLaunchKernelGGL(k, grid, block, bytes, s, a, ldx, ldh);
   return hipGetLastError();
+}
+
+template <int PREC, int KIND, int MAXCT>
+hipError_t launch_tall(const MlpArgs& a, bool bwd, hipStream_t s) {
+  int ldx;
+  size_t bytes;
+  tall_dims(a, &ldx, &bytes);
+  const dim3 grid((a.E + kTallRows - 1) / kTallRows), block(256);
+  auto k = bwd ? k_mlp_bwd_t<PREC, KIND, MAXCT> : k_mlp_fwd_t<PREC, KIND, MAXCT>;
+  hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (st != hipSuccess) return st;
+  hipLaunchKernelGGL(k, grid, block, bytes, s, a, ldx, 0);
+  return hipGetLastError();
+}
+
+template <int PREC, int KIND>
+hipError_t dispatch_tall(const MlpArgs& a, bool bwd, hipStream_t s) {
+  const int ct = max_ct(a);
+  if (ct <= 1) return launch_tall<PREC, KIND, 1>(a, bwd, s);
+  if (ct <= 2) return launch_tall<PREC, KIND, 2>(a, bwd, s);
+  if (ct <= 4) return launch_tall<PREC, KIND, 4>(a, bwd, s);
+  return hipErrorInvalidValue;
 }
 
 template <int PREC, int KIND, int TM>
@@ -718,6 +1065,16 @@ template <int PREC> constexpr int kTileRows[2] = {PREC ? 64 : 32, PREC ? 32 : 16
 template <int PREC>
 hipError_t launch_prec(const MlpArgs& a, int tm, bool bwd, hipStream_t s) {
   constexpr int T0 = kTileRows<PREC>[0], T1 = kTileRows<PREC>[1];
+  if constexpr (PREC != 0) {
+    if (tm == kTallRows) {
+      switch (a.kind) {
+        case kTwoBody: return dispatch_tall<PREC, kTwoBody>(a, bwd, s);
+        case kLatent: return dispatch_tall<PREC, kLatent>(a, bwd, s);
+        case kLatentFinal: return dispatch_tall<PREC, kLatentFinal>(a, bwd, s);
+      }
+      return hipErrorInvalidValue;
+    }
+  }
   switch (a.kind) {
     case kTwoBody:
       return tm == T0 ? dispatch_ct<PREC, kTwoBody, T0>(a, bwd, s) : dispatch_ct<PREC, kTwoBody, T1>(a, bwd, s);

@@ -271,8 +271,8 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
 //   dE/dV_e[a][u] = sum_{b,c} W[a][b][c] Gamma_i[b][u] dE/dT_e[c][u]
 //   dE/da0_e[l][u] = sum_{a: l(a)=l} dE/dV_e[a][u] Y_e[a]
 //   dE/dY_e[a]   += sum_u dE/dV_e[a][u] a0_e[l(a)][u].
-// The sums over channels are a reduce-scatter across the n lanes of a group
-// (17 exchanges for 16 values), in a fixed order: deterministic.
+// The sums over channels use DPP lane moves within each group of n lanes, in
+// a fixed order: deterministic.
 constexpr int kBatch = 4;
 
 template <int LMAX, bool FINAL, int G>
@@ -325,32 +325,6 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
 #pragma unroll
     for (int b = 0; b < DIM; ++b) out[b * n] = gG[b];
   }
-}
-
-// Sum of v[k] (k < 16) over the n lanes of each aligned lane group; on return
-// the lane with (lane & 15) == r holds the total of value index
-// k = 8 (r & 1) + 4 ((r >> 1) & 1) + 2 ((r >> 2) & 1) + ((r >> 3) & 1).
-template <int n>
-__device__ __forceinline__ float reduce_scatter16(float (&v)[16], int lane) {
-  static_assert(n >= 16, "groups of at least 16 lanes");
-#pragma unroll
-  for (int h = 8, m = 1; h >= 1; h >>= 1, m <<= 1) {
-    const bool up = (lane & m) != 0;   // keep the upper half of the current values
-#pragma unroll
-    for (int j = 0; j < h; ++j) {
-      const float keep = up ? v[j + h] : v[j];
-      const float send = up ? v[j] : v[j + h];
-      v[j] = keep + __shfl_xor(send, m, kWave);
-    }
-  }
-  float t = v[0];
-#pragma unroll
-  for (int m = 16; m < n; m <<= 1) t += __shfl_xor(t, m, kWave);
-  return t;
-}
-
-__device__ __forceinline__ int scatter_index(int lane) {
-  return 8 * (lane & 1) + 4 * ((lane >> 1) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 3) & 1);
 }
 
 constexpr int kEdgesPerWave = 32;
@@ -407,9 +381,9 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
       const uint32_t ee = eev[q];
-      float r[16];
+      float r[DIM];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) r[k] = 0.0f;
+      for (int k = 0; k < DIM; ++k) r[k] = 0.0f;
       float gw[LMAX + 1];
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) gw[l] = 0.0f;
@@ -440,25 +414,15 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) a.g_w[ee * (uint32_t)a.ld_gw + l * n + u] = gw[l] * cn;
       }
-      // sums over the group's channels
-      if constexpr (n >= 16) {
-        const float t = reduce_scatter16<n>(r, lane);
-        const int k = scatter_index(lane);
-        if (act[q] && u < 16 && k < 9) {
+      // sums over the group's channels (DPP; the group's last lane holds them)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) r[k] = group_sum_dpp<n>(r[k]);
+      if (act[q] && u == n - 1) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
           float* o = a.g_Y + ee * 9u + k;
-          const float val = k < DIM ? t : 0.0f;
+          const float val = k < DIM ? r[k] : 0.0f;
           *o = (keep_gy && k < DIM) ? *o + val : val;
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) r[k] = group_inner_sum(r[k], n);
-        if (act[q] && u == 0) {
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            float* o = a.g_Y + ee * 9u + k;
-            const float val = k < DIM ? r[k] : 0.0f;
-            *o = (keep_gy && k < DIM) ? *o + val : val;
-          }
         }
       }
     }

@@ -18,9 +18,12 @@ def to_dev(sysm):
     return pos, sp
 
 
-def gpu_model(mc, w, precision, scale=None, shift=None, edge_chunk=0):
+def gpu_model(mc, w, precision, scale=None, shift=None, edge_chunk=0, mlp_tile=0):
     cfg = P.config_from(mc, precision=precision, edge_chunk=edge_chunk)
-    return P.Model(cfg, W.pack_weights(mc, w), scale, shift)
+    m = P.Model(cfg, W.pack_weights(mc, w), scale, shift)
+    if mlp_tile:
+        m.set_tiles([mlp_tile] * 6 + [0, 0])
+    return m
 
 
 def gpu_eval(model, sysm, want_atom_virial=True):

@@ -147,6 +147,24 @@ def test_chunked_equals_whole(cfg2):
     assert np.array_equal(a["atom_energy"], b["atom_energy"])
 
 
+def test_bf16_tile_shapes_agree(cfg2):
+    """The 128-, 64- and 32-edge BF16 MLP kernels compute the same products in
+    the same K order: energies agree exactly; forces agree to the level of one
+    BF16 rounding of an activation (the kernels' compiled float expressions may
+    round an intermediate differently before it is rounded to BF16)."""
+    mc, s, w, sc, sh, ref = cfg2
+    outs = {t: gpu_eval(gpu_model(mc, w, BF16, sc, sh, mlp_tile=t), s) for t in (128, 64, 32)}
+    fs = float(np.sqrt((outs[64]["forces"] ** 2).mean()))
+    for t in (128, 32):
+        d = outs[t]["forces"] - outs[64]["forces"]
+        rel_rms = float(np.sqrt((d ** 2).mean())) / fs
+        _report(f"tiles_{t}_vs_64", max_dF=float(np.abs(d).max()), rel_rms=rel_rms,
+                dE=float(outs[t]["energy"][0] - outs[64]["energy"][0]))
+        assert np.array_equal(outs[t]["energy"], outs[64]["energy"])
+        assert np.array_equal(outs[t]["atom_energy"], outs[64]["atom_energy"])
+        assert rel_rms <= 2e-4
+
+
 def test_repeatable_bitwise(cfg2):
     mc, s, w, sc, sh, ref = cfg2
     m = gpu_model(mc, w, BF16, sc, sh)
@@ -166,16 +184,21 @@ SMALL = [
 ]
 
 
+# (precision, MLP edge-tile rows): every tile shape of both precisions
+PREC_TILES = [(FP32, 32), (FP32, 16), (BF16, 128), (BF16, 64), (BF16, 32)]
+
+
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: c[0])
-@pytest.mark.parametrize("prec", [FP32, BF16], ids=["fp32", "bf16"])
-def test_small_models(case, prec):
+@pytest.mark.parametrize("prec,tile", PREC_TILES,
+                         ids=[f"{'fp32' if p == FP32 else 'bf16'}_tile{t}" for p, t in PREC_TILES])
+def test_small_models(case, prec, tile):
     name, kw = case
     mc = W.ModelConfig(n_species=2, r_cut=4.0, **kw)
     w = W.make_weights(mc, np.random.default_rng(5))
     s = W.system(1)
     sc, sh = W.species_scale_shift(mc, np.random.default_rng(6))
     ref = OM.evaluate(mc, w, s, sc, sh)
-    got = gpu_eval(gpu_model(mc, w, prec, sc, sh), s)
+    got = gpu_eval(gpu_model(mc, w, prec, sc, sh, mlp_tile=tile), s)
     if prec == FP32:
         _check_fp32(name, got, ref, s.n_local)
     else:
@@ -283,6 +306,10 @@ def test_error_paths():
     with pytest.raises(P.AllegroError) as ex:
         m.neighbors(pos, sp, [8.6, 0.1, 0, 0, 8.6, 0, 0, 0, 8.6], s.pbc)
     assert ex.value.status == -1
+    for bad_tiles in ([16] * 6 + [0, 0], [0] * 6 + [64, 0]):   # 16-row MLP tiles are FP32-only
+        with pytest.raises(P.AllegroError) as ex:
+            m.set_tiles(bad_tiles)
+        assert ex.value.status == -1
     # the model stays usable after errors
     got = gpu_eval(m, s)
     assert np.isfinite(got["energy"][0])
