@@ -53,8 +53,18 @@ enum {
  *                and applied with two MFMAs, so the fixed rounding of the
  *                weights does not bias every pair energy the same way.
  *   BF16_SINGLE  BF16 MFMA with single-rounded weights (fastest; its energies
- *                carry a systematic error from the weight rounding). */
-enum { ALLEGRO_PREC_FP32 = 0, ALLEGRO_PREC_BF16 = 1, ALLEGRO_PREC_BF16_SINGLE = 2 };
+ *                carry a systematic error from the weight rounding).
+ *   BF16_MIXED   weight pairs only where a fixed rounding adds up coherently
+ *                over edges: every layer of the two-body MLP (its inputs are
+ *                species one-hots and a smooth radial basis) and the first
+ *                layer of each later latent MLP (it reads the residual stream);
+ *                the other layers and the environment embedding single-rounded. */
+enum {
+  ALLEGRO_PREC_FP32 = 0,
+  ALLEGRO_PREC_BF16 = 1,
+  ALLEGRO_PREC_BF16_SINGLE = 2,
+  ALLEGRO_PREC_BF16_MIXED = 3
+};
 
 typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
 
@@ -78,7 +88,7 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *                    1/sqrt(avg_num_neighbors)
  *   channel_mix      1 = per-irrep linear channel mixing after each tensor
  *                    product, 0 = none
- *   precision        ALLEGRO_PREC_FP32, ALLEGRO_PREC_BF16 or ALLEGRO_PREC_BF16_SINGLE
+ *   precision        one of the ALLEGRO_PREC_* modes above
  *   edge_chunk       0 = evaluate all edges at once; otherwise the largest
  *                    number of edges whose activations are held at a time
  *                    (whole centre segments; bounds workspace memory)
@@ -213,9 +223,9 @@ int allegro_autotune(AllegroModel* m, const double* pos, const int32_t* species,
 
 /*
  * allegro_set_tiles: set the edge-tile shapes directly (same order and values
- * as allegro_autotune's choices; 0 = the library's default, which for BF16
- * MLP chains is the 128-edge tile where it fits in LDS).  Host array of 8
- * int32, copied.  Returns ALLEGRO_E_INVAL for a value not available in the
+ * as allegro_autotune's choices; 0 = the library's default: the largest
+ * 64/32-edge (BF16) or 32/16-edge (FP32) MLP tile that fits in LDS, 32-edge
+ * tensor tiles).  Host array of 8 int32, copied.  Returns ALLEGRO_E_INVAL for a value not available in the
  * model's precision.
  */
 int allegro_set_tiles(AllegroModel* m, const int32_t* tiles);

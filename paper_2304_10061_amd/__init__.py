@@ -5,8 +5,8 @@ include/allegro_mi355x.h); `binding` marshals arguments to it and `autograd`
 exposes the energy as a torch.autograd.Function whose backward is the
 library's hand-written adjoint.
 """
-from .binding import (AllegroConfig, AllegroError, Model, PREC_BF16, PREC_BF16_SINGLE, PREC_FP32,
+from .binding import (AllegroConfig, AllegroError, Model, PREC_BF16, PREC_BF16_MIXED, PREC_BF16_SINGLE, PREC_FP32,
                       config_from, describe, load_library, make_config)
 
-__all__ = ["AllegroConfig", "AllegroError", "Model", "PREC_BF16", "PREC_BF16_SINGLE", "PREC_FP32",
+__all__ = ["AllegroConfig", "AllegroError", "Model", "PREC_BF16", "PREC_BF16_MIXED", "PREC_BF16_SINGLE", "PREC_FP32",
            "config_from", "describe", "load_library", "make_config"]

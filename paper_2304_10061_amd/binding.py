@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liballegro_mi355x.so")
 ALLEGRO_OK = 0
 STATUS = {0: "ALLEGRO_OK", -1: "ALLEGRO_E_INVAL", -2: "ALLEGRO_E_NOMEM", -3: "ALLEGRO_E_CAPACITY",
           -4: "ALLEGRO_E_DEVICE", -5: "ALLEGRO_E_NONFINITE", -6: "ALLEGRO_E_STATE"}
-PREC_FP32, PREC_BF16, PREC_BF16_SINGLE = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_BF16_SINGLE, PREC_BF16_MIXED = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ("allegro_describe", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",

@@ -101,6 +101,7 @@ void pack_b(const std::vector<double>& W, int K, int N, int prec, std::vector<ch
       }
     }
   g.K = K; g.N = N; g.Kp = Kp; g.Np = Np;
+  g.split = prec == 1 ? 1 : 0;
 }
 
 std::vector<double> transpose(const std::vector<double>& W, int K, int N) {
@@ -157,8 +158,8 @@ Validated validate(const AllegroConfig* c) {
   REQUIRE(c->r_cut > 0 && std::isfinite(c->r_cut), "r_cut must be positive");
   REQUIRE(c->avg_num_neighbors > 0 && std::isfinite(c->avg_num_neighbors), "avg_num_neighbors must be positive");
   REQUIRE(c->precision == ALLEGRO_PREC_FP32 || c->precision == ALLEGRO_PREC_BF16 ||
-              c->precision == ALLEGRO_PREC_BF16_SINGLE,
-          "precision must be 0, 1 or 2");
+              c->precision == ALLEGRO_PREC_BF16_SINGLE || c->precision == ALLEGRO_PREC_BF16_MIXED,
+          "precision must be 0, 1, 2 or 3");
   REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
   REQUIRE(c->neighbor_skin >= 0 && std::isfinite(c->neighbor_skin), "neighbor_skin must be >= 0");
   v.dim = (v.lmax + 1) * (v.lmax + 1);
@@ -242,7 +243,10 @@ struct AllegroModel {
   AllegroConfig cfg{};
   Validated v{};
   int prec = 1;
-  int prec_two = 1, prec_lat = 1;   // kernel precision of the two-body / later MLPs (0 FP32, 1 pairs, 2 BF16)
+  // kernel precision of the two-body / later MLPs (0 FP32, 1 BF16 with
+  // per-matrix hi + lo pairs, 2 BF16 single-rounded) and the packing of the
+  // later MLPs' first and other layers (same codes)
+  int prec_two = 1, prec_lat = 1, prec_lat_first = 1, prec_lat_rest = 1;
   std::string err;
   int device = 0;
 
@@ -313,9 +317,12 @@ std::vector<double> slice(const float* w, int64_t& off, int64_t count) {
   return out;
 }
 
-void build_mlp(Mlp& mlp, const std::vector<std::vector<double>>& Ws, const std::vector<int>& dims, int prec) {
+// prec_first applies to the first layer, prec_rest to the others.
+void build_mlp(Mlp& mlp, const std::vector<std::vector<double>>& Ws, const std::vector<int>& dims, int prec_first,
+               int prec_rest) {
   mlp.nl = (int)Ws.size();
   for (int k = 0; k < mlp.nl; ++k) {
+    const int prec = k == 0 ? prec_first : prec_rest;
     make_packed(mlp.fwd[k], Ws[k], dims[k], dims[k + 1], prec);
     make_packed(mlp.bwd[k], transpose(Ws[k], dims[k], dims[k + 1]), dims[k + 1], dims[k], prec);
   }
@@ -337,7 +344,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     Ws.push_back(slice(w, off, (int64_t)dims.back() * wd));
     dims.push_back(wd);
   }
-  build_mlp(m->twobody, Ws, dims, m->prec_two);
+  build_mlp(m->twobody, Ws, dims, m->prec_two, m->prec_two);
   const std::vector<double> embed0 = slice(w, off, (int64_t)d * LW);
   std::vector<double> env[2], alpha[2], mix[2];
   std::vector<std::vector<double>> mlpW[2];
@@ -374,7 +381,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   }
   std::vector<int> ldims{d + n};
   for (int wd : v.dimsL) ldims.push_back(wd);
-  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, m->prec_lat);
+  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, m->prec_lat_first, m->prec_lat_rest);
 
   // heads: [embed0 | env1] after the two-body MLP, env2 after the first latent MLP
   {
@@ -387,8 +394,8 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     make_packed(m->head0, H, d, 2 * LW, m->prec_two);
     make_packed(m->head0T, transpose(H, d, 2 * LW), 2 * LW, d, m->prec_two);
     if (v.nl == 2) {
-      make_packed(m->env2, env[1], d, LW, m->prec_lat);
-      make_packed(m->env2T, transpose(env[1], d, LW), LW, d, m->prec_lat);
+      make_packed(m->env2, env[1], d, LW, m->prec_lat_rest);
+      make_packed(m->env2T, transpose(env[1], d, LW), LW, d, m->prec_lat_rest);
     }
   }
   // channel mixing matrices of non-final layers (FP32): forward W[u][v] = M[v][u],
@@ -450,7 +457,8 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     MlpArgs q;
     q.d = d; q.n = n; q.w = m->latent[L].view();
     if (L + 1 < v.nl) { q.head = m->env2.g; q.head_bwd = m->env2T.g; }
-    REQUIRE(mlp_lds_bytes(q, m->prec_lat, false) != (size_t)-1 && mlp_lds_bytes(q, m->prec_lat, true) != (size_t)-1,
+    REQUIRE(mlp_lds_bytes(q, m->prec_lat, false) != (size_t)-1 &&
+                mlp_lds_bytes(q, m->prec_lat, true) != (size_t)-1,
             "latent MLP too wide for the fused kernel");
   }
 }
@@ -1102,8 +1110,14 @@ int allegro_create(const AllegroConfig* cfg, const float* weights, int64_t n_wei
     m->cfg = *cfg;
     m->v = v;
     m->prec = cfg->precision;
-    // kernel precision per MLP (the same for all MLPs in the current modes)
-    m->prec_two = m->prec_lat = m->prec;
+    switch (m->prec) {
+      case ALLEGRO_PREC_FP32: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 0; break;
+      case ALLEGRO_PREC_BF16: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 1; break;
+      case ALLEGRO_PREC_BF16_SINGLE: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 2; break;
+      default:   // BF16_MIXED: pairs in the two-body MLP and the later MLPs' first layers
+        m->prec_two = m->prec_lat = m->prec_lat_first = 1;
+        m->prec_lat_rest = 2;
+    }
     create_impl(m, weights, n_weights, species_scale, species_shift);
     *out = m;
     return ALLEGRO_OK;

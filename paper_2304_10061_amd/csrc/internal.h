@@ -33,6 +33,7 @@ constexpr int kMaxMlpLayers = 3;
 struct GemmB {
   const void* p = nullptr;
   int K = 0, N = 0, Kp = 0, Np = 0;
+  int split = 0;   // BF16 hi fragments followed by lo fragments (w = hi + lo)
 };
 
 struct MlpW {

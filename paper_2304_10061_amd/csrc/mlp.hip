@@ -39,8 +39,8 @@ bool tall_fits(const MlpArgs& a, int prec, bool bwd) {
 hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
   if (a.E <= 0) return hipSuccess;
   if (prec == 1 || prec == 2) {
-    // tall tiles by default (tm == 0) or on request, where they fit
-    if ((a.tm == kTallRows || a.tm == 0) && tall_fits(a, prec, bwd))
+    // tall tiles on request (autotuner or allegro_set_tiles), where they fit
+    if (a.tm == kTallRows && tall_fits(a, prec, bwd))
       return prec == 1 ? launch_prec<1>(a, kTallRows, bwd, s) : launch_prec<2>(a, kTallRows, bwd, s);
     const int tm = (a.tm == 64 || a.tm == 32) && fits<1>(a, bwd, a.tm) ? a.tm : pick_tm<1>(a, bwd);
     if (tm == 0) return hipErrorInvalidValue;

@@ -96,10 +96,10 @@ __device__ __forceinline__ int npasses(int Np) { return (Np / 16 + 4 * MAXCT - 1
 // PREF_A: the A fragments of the next K block are also requested ahead (two
 // register sets); without it (tall tiles, RT = 8) each row tile's A fragment
 // is read from LDS just before its MFMAs.
-template <int PREC, int RT, int MAXCT, bool PREF_A = true>
-__device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
-                                          int lda, const GemmB& B, int wave, int lane, int pass,
-                                          int kb0 = 0, int kb1 = -1, bool zero = true) {
+template <int PREC, int RT, int MAXCT, bool PREF_A, bool kSplit>
+__device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
+                                            int lda, const GemmB& B, int wave, int lane, int pass,
+                                            int kb0, int kb1, bool zero) {
   using P = PT<PREC>;
   using T = typename P::T;
   using F = typename P::F;
@@ -111,9 +111,8 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
   }
   const int nkb = B.Kp >> 5, nct = B.Np >> 4;
   if (kb1 < 0) kb1 = nkb;
-  // PREC 1 keeps each weight as a pair of BF16 values (hi + lo, lo stored
-  // after the hi fragments) and issues two MFMAs per product.
-  constexpr bool kSplit = PREC == 1;
+  // kSplit: each weight is a pair of BF16 values (hi + lo, lo stored after
+  // the hi fragments), two MFMAs per product.
   constexpr int NA = PREF_A ? RT : 1;
   const size_t lo_off = (size_t)B.Kp * B.Np;
   const T* Bl = (const T*)B.p + (size_t)lane * 8;
@@ -184,6 +183,22 @@ __device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typenam
     if (tile_of<MAXCT>(pass, q, wave) >= nct)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) acc[rt][q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+// PREC 1 kernels take BF16 matrices with or without lo fragments (B.split,
+// wave-uniform), so that a chain can mix paired and single-rounded layers.
+template <int PREC, int RT, int MAXCT, bool PREF_A = true>
+__device__ __forceinline__ void gemm_tile(f32x4 (&acc)[RT][MAXCT], const typename PT<PREC>::T* A,
+                                          int lda, const GemmB& B, int wave, int lane, int pass,
+                                          int kb0 = 0, int kb1 = -1, bool zero = true) {
+  if constexpr (PREC == 1) {
+    if (B.split)
+      gemm_tile_k<PREC, RT, MAXCT, PREF_A, true>(acc, A, lda, B, wave, lane, pass, kb0, kb1, zero);
+    else
+      gemm_tile_k<PREC, RT, MAXCT, PREF_A, false>(acc, A, lda, B, wave, lane, pass, kb0, kb1, zero);
+  } else {
+    gemm_tile_k<PREC, RT, MAXCT, PREF_A, false>(acc, A, lda, B, wave, lane, pass, kb0, kb1, zero);
+  }
 }
 
 template <class T> __device__ __forceinline__ T to_t(float v) { return (T)v; }

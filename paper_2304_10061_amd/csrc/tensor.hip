@@ -261,37 +261,44 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
 // k_tp_adjoint_gamma (one wavefront per centre; lane = channel u, and with
 // n < 64 the G = 64/n lane groups take interleaved edges) accumulates
 //   dE/dGamma_i[b][u] = sum_{e in N(i)} sum_{a,c} W[a][b][c] V_e[a][u] dE/dT_e[c][u]
-// in registers and writes it once per centre (without the factor c).
-//
-// k_tp_adjoint_edges (edge-parallel; G edges per wavefront step, each wave a
-// contiguous run of edges) then produces the per-edge gradients:
-//   dE/dw_e[l][u] = c sum_{b: l(b)=l} dE/dGamma_i[b][u] Y_e[b]
-//   dE/dY_e[b]   += c sum_u dE/dGamma_i[b][u] w_e[l(b)][u]
-// and, when V_e = a0_e[l(a)][u] Y_e[a] (first layer),
+// in registers and writes it once per centre (without the factor c).  When
+// V_e = a0_e[l(a)][u] Y_e[a] (first layer, A0) the same pass, which already
+// holds dE/dT_e and a0_e, also emits
 //   dE/dV_e[a][u] = sum_{b,c} W[a][b][c] Gamma_i[b][u] dE/dT_e[c][u]
 //   dE/da0_e[l][u] = sum_{a: l(a)=l} dE/dV_e[a][u] Y_e[a]
-//   dE/dY_e[a]   += sum_u dE/dV_e[a][u] a0_e[l(a)][u].
+//   dE/dY_e[a]   (+)= sum_u dE/dV_e[a][u] a0_e[l(a)][u].
+//
+// k_tp_adjoint_edges (edge-parallel; G edges per wavefront step, each wave a
+// contiguous run of edges) then produces the environment part:
+//   dE/dw_e[l][u] = c sum_{b: l(b)=l} dE/dGamma_i[b][u] Y_e[b]
+//   dE/dY_e[b]   += c sum_u dE/dGamma_i[b][u] w_e[l(b)][u].
 // The sums over channels use DPP lane moves within each group of n lanes, in
 // a fixed order: deterministic.
-constexpr int kBatch = 4;
-
-template <int LMAX, bool FINAL, int G>
+template <int LMAX, bool FINAL, int G, bool A0>
 __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
   using Pat = TpPattern<LMAX, FINAL>;
   constexpr int DIM = Pat::DIM, DOUT = Pat::DOUT;
   constexpr int n = kWave / G;
+  // edges per lane group whose loads are issued together (fewer when both
+  // 83-term contractions run per edge, to stay within 128 registers)
+  constexpr int kBatch = (A0 && !FINAL) ? 2 : 4;
   const int lane = lane_id();
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.n_centres) return;
   const int u = lane & (n - 1), g = lane / n;
   const float* w = a.tpw_v;
-  float gG[DIM];
+  float gG[DIM], Gm[A0 ? DIM : 1];
 #pragma unroll
   for (int b = 0; b < DIM; ++b) gG[b] = 0.0f;
+  if constexpr (A0) {
+    const float* gmp = a.gam + (size_t)c * DIM * n + u;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) Gm[b] = gmp[b * n];
+  }
+  const bool keep_gy = a.gy_accum != 0;
   const int eb0 = a.row_ptr[c], eb1 = a.row_ptr[c + 1];
-  const bool from_a0 = a.v.from_a0 != 0;
   for (int e0 = eb0; e0 < eb1; e0 += G * kBatch) {
-    float V[kBatch][DIM], gT[kBatch][DOUT];
+    float V[kBatch][DIM], gT[kBatch][DOUT], a0v[A0 ? kBatch : 1][LMAX + 1], Yv[A0 ? kBatch : 1][DIM];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const int e = e0 + g + G * j;
@@ -299,13 +306,15 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
       const uint32_t ee = act ? e : eb0;
       const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
       const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
-      if (from_a0) {
+      if constexpr (A0) {
         const float* Y = a.eb + ee * kEB;
-        float a0v[LMAX + 1];
 #pragma unroll
-        for (int l = 0; l <= LMAX; ++l) a0v[l] = vp[l * n];
+        for (int l = 0; l <= LMAX; ++l) a0v[j][l] = vp[l * n];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) V[j][k] = a0v[lof(k)] * Y[k];
+        for (int k = 0; k < DIM; ++k) {
+          Yv[j][k] = Y[k];
+          V[j][k] = a0v[j][lof(k)] * Yv[j][k];
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < DIM; ++k) V[j][k] = vp[k * n];
@@ -314,7 +323,36 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
       for (int k = 0; k < DOUT; ++k) gT[j][k] = act ? gtp[k * n] : 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) tp_adjoint_g<Pat>(V[j], gT[j], gG, w, std::make_index_sequence<Pat::NNZ>{});
+    for (int j = 0; j < kBatch; ++j) {
+      tp_adjoint_g<Pat>(V[j], gT[j], gG, w, std::make_index_sequence<Pat::NNZ>{});
+      if constexpr (A0) {
+        const int e = e0 + g + G * j;
+        float gV[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) gV[k] = 0.0f;
+        tp_adjoint_v<Pat>(Gm, gT[j], gV, w, std::make_index_sequence<Pat::NNZ>{});
+        float ga[LMAX + 1];
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
+        float r[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          ga[lof(k)] = fmaf(gV[k], Yv[j][k], ga[lof(k)]);
+          r[k] = group_sum_dpp<n>(gV[k] * a0v[j][lof(k)]);
+        }
+        if (e < eb1) {
+#pragma unroll
+          for (int l = 0; l <= LMAX; ++l) a.g_a0[(uint32_t)e * a.ld_gw + l * n + u] = ga[l];
+          if (u == n - 1) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+              float* o = a.g_Y + (uint32_t)e * 9u + k;
+              *o = keep_gy ? *o + r[k] : r[k];
+            }
+          }
+        }
+      }
+    }
   }
   if constexpr (G > 1) {
 #pragma unroll
@@ -329,26 +367,24 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
 
 constexpr int kEdgesPerWave = 32;
 
-// A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a].
-template <int LMAX, bool FINAL, int G, bool A0>
-__global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
+// keep_gy: add to dE/dY (set when an earlier kernel of this or a later
+// layer already wrote it).
+template <int LMAX, bool FINAL, int G>
+__global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a, int keep_gy) {
   using Pat = TpPattern<LMAX, FINAL>;
-  constexpr int DIM = Pat::DIM, DOUT = Pat::DOUT;
+  constexpr int DIM = Pat::DIM;
   constexpr int n = kWave / G;
-  constexpr int KB = A0 ? 2 : 4;   // edges per lane group whose loads are issued together
+  constexpr int KB = 4;   // edges per lane group whose loads are issued together
   const int lane = lane_id();
   const int u = lane & (n - 1), g = lane / n;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t w0 = (int64_t)wave * kEdgesPerWave;
-  const float* w = a.tpw_v;
-  const bool keep_gy = a.gy_accum != 0;
   const float cn = a.c_norm;
   // centres of the wave's edges: one load per lane, read out per edge
   const int64_t el = w0 + (lane & (kEdgesPerWave - 1));
   const int ci_lane = el < a.E ? a.ei[el] - a.centre_base : 0;
   for (int j0 = 0; j0 < kEdgesPerWave; j0 += G * KB) {
     float gG[KB][DIM], Yv[KB][DIM], wv[KB][LMAX + 1];
-    float Gm[A0 ? KB : 1][DIM], gT[A0 ? KB : 1][DOUT], a0v[A0 ? KB : 1][LMAX + 1];
     bool act[KB];
     uint32_t eev[KB];
 #pragma unroll
@@ -366,63 +402,28 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       for (int b = 0; b < DIM; ++b) { gG[q][b] = ggp[b * n]; Yv[q][b] = Y[b]; }
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) wv[q][l] = wp[l * n];
-      if constexpr (A0) {
-        const float* gmp = a.gam + ci * (uint32_t)(DIM * n) + u;
-        const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
-        const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) Gm[q][b] = gmp[b * n];
-#pragma unroll
-        for (int k = 0; k < DOUT; ++k) gT[q][k] = gtp[k * n];
-#pragma unroll
-        for (int l = 0; l <= LMAX; ++l) a0v[q][l] = vp[l * n];
-      }
     }
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
       const uint32_t ee = eev[q];
-      float r[DIM];
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) r[k] = 0.0f;
-      float gw[LMAX + 1];
+      float gw[LMAX + 1], r[DIM];
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) gw[l] = 0.0f;
 #pragma unroll
       for (int b = 0; b < DIM; ++b) {
         gw[lof(b)] = fmaf(gG[q][b], Yv[q][b], gw[lof(b)]);
-        r[b] = cn * gG[q][b] * wv[q][lof(b)];
-      }
-      if constexpr (A0) {
-        float gV[DIM];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) gV[k] = 0.0f;
-        tp_adjoint_v<Pat>(Gm[q], gT[q], gV, w, std::make_index_sequence<Pat::NNZ>{});
-        float ga[LMAX + 1];
-#pragma unroll
-        for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          ga[lof(k)] = fmaf(gV[k], Yv[q][k], ga[lof(k)]);
-          r[k] = fmaf(gV[k], a0v[q][lof(k)], r[k]);
-        }
-        if (act[q]) {
-#pragma unroll
-          for (int l = 0; l <= LMAX; ++l) a.g_a0[ee * (uint32_t)a.ld_gw + l * n + u] = ga[l];
-        }
+        r[b] = group_sum_dpp<n>(cn * gG[q][b] * wv[q][lof(b)]);
       }
       if (act[q]) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) a.g_w[ee * (uint32_t)a.ld_gw + l * n + u] = gw[l] * cn;
-      }
-      // sums over the group's channels (DPP; the group's last lane holds them)
+        if (u == n - 1) {
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) r[k] = group_sum_dpp<n>(r[k]);
-      if (act[q] && u == n - 1) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          float* o = a.g_Y + ee * 9u + k;
-          const float val = k < DIM ? r[k] : 0.0f;
-          *o = (keep_gy && k < DIM) ? *o + val : val;
+          for (int k = 0; k < 9; ++k) {
+            float* o = a.g_Y + ee * 9u + k;
+            const float val = k < DIM ? r[k < DIM ? k : 0] : 0.0f;
+            *o = (keep_gy && k < DIM) ? *o + val : val;
+          }
         }
       }
     }
@@ -489,12 +490,17 @@ hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s) {
 
 template <int LMAX, bool FINAL, int G>
 hipError_t launch_adjoint_g(const TensorArgs& a, hipStream_t s) {
-  if (a.n_centres > 0)
-    hipLaunchKernelGGL((k_tp_adjoint_gamma<LMAX, FINAL, G>), dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
+  const bool a0 = a.v.from_a0 != 0;
+  if (a.n_centres > 0) {
+    const dim3 grid(blocks(a.n_centres, 4));
+    if (a0) hipLaunchKernelGGL((k_tp_adjoint_gamma<LMAX, FINAL, G, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_tp_adjoint_gamma<LMAX, FINAL, G, false>), grid, dim3(256), 0, s, a);
+  }
   if (a.E > 0) {
-    const dim3 grid(blocks(a.E, 4 * kEdgesPerWave));
-    if (a.v.from_a0) hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G, false>), grid, dim3(256), 0, s, a);
+    // the first-layer pass above has already written its part of dE/dY
+    const int keep = (a.gy_accum || a0) ? 1 : 0;
+    hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G>), dim3(blocks(a.E, 4 * kEdgesPerWave)), dim3(256), 0,
+                       s, a, keep);
   }
   return hipGetLastError();
 }

@@ -22,7 +22,7 @@ from gpu_helpers import gpu_edges, gpu_eval, gpu_model, to_dev
 
 pytestmark = pytest.mark.gpu
 
-FP32, BF16, BF16S = P.PREC_FP32, P.PREC_BF16, P.PREC_BF16_SINGLE
+FP32, BF16, BF16S, BF16M = P.PREC_FP32, P.PREC_BF16, P.PREC_BF16_SINGLE, P.PREC_BF16_MIXED
 
 
 def _report(tag, **kw):
@@ -121,11 +121,12 @@ def test_fp32_water_box(cfg2):
     assert np.abs(got["atom_energy"] - ref.atom_energy).max() < 1e-5
 
 
-def test_bf16_water_box(cfg2):
+@pytest.mark.parametrize("prec", [BF16, BF16M], ids=["bf16", "bf16_mixed"])
+def test_bf16_water_box(cfg2, prec):
     mc, s, w, sc, sh, ref = cfg2
-    m = gpu_model(mc, w, BF16, sc, sh)
+    m = gpu_model(mc, w, prec, sc, sh)
     got = gpu_eval(m, s)
-    _check_bf16("cfg2_bf16", got, ref, s.n_local)
+    _check_bf16(f"cfg2_{'bf16' if prec == BF16 else 'bf16_mixed'}", got, ref, s.n_local)
 
 
 def test_bf16_single_rounded_weights_forces(cfg2):
@@ -185,12 +186,12 @@ SMALL = [
 
 
 # (precision, MLP edge-tile rows): every tile shape of both precisions
-PREC_TILES = [(FP32, 32), (FP32, 16), (BF16, 128), (BF16, 64), (BF16, 32)]
+PREC_TILES = [(FP32, 32), (FP32, 16), (BF16, 128), (BF16, 64), (BF16, 32), (BF16M, 128), (BF16M, 64)]
+_PNAME = {FP32: "fp32", BF16: "bf16", BF16M: "bf16mixed"}
 
 
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: c[0])
-@pytest.mark.parametrize("prec,tile", PREC_TILES,
-                         ids=[f"{'fp32' if p == FP32 else 'bf16'}_tile{t}" for p, t in PREC_TILES])
+@pytest.mark.parametrize("prec,tile", PREC_TILES, ids=[f"{_PNAME[p]}_tile{t}" for p, t in PREC_TILES])
 def test_small_models(case, prec, tile):
     name, kw = case
     mc = W.ModelConfig(n_species=2, r_cut=4.0, **kw)
@@ -265,7 +266,7 @@ def _sampled_reference(mc, s, w, nbr, rng):
     return cents, e_raw, atoms, F
 
 
-@pytest.mark.parametrize("prec", [FP32, BF16], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("prec", [FP32, BF16, BF16M], ids=["fp32", "bf16", "bf16_mixed"])
 def test_protein_box_sampled(cfg3, prec):
     mc, s, w, nbr = cfg3
     got = gpu_eval(gpu_model(mc, w, prec), s, want_atom_virial=False)
@@ -273,7 +274,7 @@ def test_protein_box_sampled(cfg3, prec):
     dEi = got["atom_energy"][cents] - e_ref
     dF = got["forces"][atoms] - F_ref
     frms = float(np.sqrt((F_ref ** 2).mean()))
-    _report(f"cfg3_{'fp32' if prec == FP32 else 'bf16'}", mean_dEi=float(abs(dEi.mean())),
+    _report(f"cfg3_{_PNAME.get(prec, prec)}", mean_dEi=float(abs(dEi.mean())),
             max_dEi=float(np.abs(dEi).max()), max_dF=float(np.abs(dF).max()), Frms=frms,
             net_force=float(np.abs(got["forces"].sum(0)).max()))
     if prec == FP32:
