@@ -40,10 +40,22 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct PT;
 
+// Buffer resource of a read-only array of `bytes` bytes (raw buffer, gfx9
+// descriptor word 3); out-of-range reads return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ro_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 template <> struct PT<1> {
   using T = __bf16;
   struct F { bf16x8 v; };
   static __device__ __forceinline__ F load(const T* p) { F f; f.v = *(const bf16x8*)p; return f; }
+  // 16 bytes at voff + soff (soff wave-uniform)
+  static __device__ __forceinline__ F load_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    F f;
+    f.v = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return f;
+  }
   static __device__ __forceinline__ f32x4 mma(const F& a, const F& b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
   }
@@ -59,6 +71,12 @@ template <> struct PT<0> {
     F f;
     f.lo = *(const f32x4*)p;
     f.hi = *(const f32x4*)(p + 4);
+    return f;
+  }
+  static __device__ __forceinline__ F load_buf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    F f;
+    f.lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    f.hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0));
     return f;
   }
   // Eight K=4 steps; step s takes k = 8 (lane/16) + s from each lane group, so
@@ -114,15 +132,19 @@ __device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typen
   // kSplit: each weight is a pair of BF16 values (hi + lo, lo stored after
   // the hi fragments), two MFMAs per product.
   constexpr int NA = PREF_A ? RT : 1;
-  const size_t lo_off = (size_t)B.Kp * B.Np;
-  const T* Bl = (const T*)B.p + (size_t)lane * 8;
   const T* Arow = A + (lane & 15) * lda + 8 * (lane >> 4) - kb0 * 32;
-  size_t boff[MAXCT];
+  // B fragments through a buffer resource: the lane's slot is a fixed vector
+  // offset, the column tile and K block a wave-uniform scalar offset, so the
+  // loads need no per-lane address arithmetic
+  const uint32_t lo_bytes = (uint32_t)(B.Kp * B.Np * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rb = ro_rsrc(B.p, lo_bytes * (kSplit ? 2 : 1));
+  const uint32_t loff = (uint32_t)lane * 8 * sizeof(T);
+  uint32_t bq[MAXCT];
 #pragma unroll
   for (int q = 0; q < MAXCT; ++q) {
     int nt = tile_of<MAXCT>(pass, q, wave);
     nt = nt < nct ? nt : nct - 1;
-    boff[q] = (size_t)(nt * nkb) * 512;
+    bq[q] = (uint32_t)(nt * nkb) * 512 * sizeof(T);
   }
   // Register buffers of B (and A) fragments, used in rotation: the fragments
   // of K block kb + 1 are requested before the MFMAs of block kb.
@@ -132,8 +154,9 @@ __device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typen
   auto load = [&](F (&aa)[NA], F (&bb)[MAXCT], F (&ll)[kSplit ? MAXCT : 1], int kb) {
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
-      bb[q] = P::load(Bl + boff[q] + (size_t)kb * 512);
-      if constexpr (kSplit) ll[q] = P::load(Bl + lo_off + boff[q] + (size_t)kb * 512);
+      const uint32_t so = bq[q] + (uint32_t)kb * 512 * sizeof(T);
+      bb[q] = P::load_buf(rb, loff, so);
+      if constexpr (kSplit) ll[q] = P::load_buf(rb, loff, so + lo_bytes);
     }
     if constexpr (PREF_A) {
 #pragma unroll
