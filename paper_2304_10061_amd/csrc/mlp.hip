@@ -59,7 +59,7 @@ size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd) {
   int ldx, ldh;
   size_t bytes;
   const int tm = prec ? pick_tm<1>(a, bwd) : pick_tm<0>(a, bwd);
-  if (tm == 0 || max_ct(a) > 4) return (size_t)-1;
+  if (tm == 0 || max_ct(a) > 2) return (size_t)-1;
   if (prec) lds_dims<1>(a, tm, bwd, &ldx, &ldh, &bytes);
   else lds_dims<0>(a, tm, bwd, &ldx, &ldh, &bytes);
   return bytes;

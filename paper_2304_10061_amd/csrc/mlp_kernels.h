@@ -95,14 +95,28 @@ template <> struct PT<0> {
   }
 };
 
-// Column tiles of a GEMM output are dealt to the four waves round-robin; pass
-// p covers nt = wave + 4 (p MAXCT + q), q < MAXCT, so wide outputs run in
+// Waves per block.  Eight waves (two per SIMD) give each SIMD a second
+// instruction stream to issue from while one waits on memory or a barrier.
+constexpr int kNW = 8;
+constexpr int kThreads = 64 * kNW;
+
+// Column tiles of a GEMM output are dealt to the waves round-robin; pass p
+// covers nt = wave + kNW (p MAXCT + q), q < MAXCT, so wide outputs run in
 // several passes with a bounded accumulator set.
 template <int MAXCT>
-__device__ __forceinline__ int tile_of(int pass, int q, int wave) { return wave + 4 * (pass * MAXCT + q); }
+__device__ __forceinline__ int tile_of(int pass, int q, int wave) { return wave + kNW * (pass * MAXCT + q); }
 
 template <int MAXCT>
-__device__ __forceinline__ int npasses(int Np) { return (Np / 16 + 4 * MAXCT - 1) / (4 * MAXCT); }
+__host__ __device__ __forceinline__ int npasses(int Np) { return (Np / 16 + kNW * MAXCT - 1) / (kNW * MAXCT); }
+
+// Sum of the per-wave partials of row r, in wave order.
+template <int TM>
+__device__ __forceinline__ float wave_partials_sum(const float (&red)[kNW][TM], int r) {
+  float s = red[0][r];
+#pragma unroll
+  for (int w = 1; w < kNW; ++w) s += red[w][r];
+  return s;
+}
 
 // acc[rt][q] = A[TM x K-range] (LDS) @ B[K-range x tiles of this pass].
 // A holds the columns of K blocks [kb0, kb1) starting at its column 0.  The
@@ -147,7 +161,8 @@ __device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typen
     bq[q] = (uint32_t)(nt * nkb) * 512 * sizeof(T);
   }
   // Register buffers of B (and A) fragments, used in rotation: the fragments
-  // of K block kb + 1 are requested before the MFMAs of block kb.
+  // of K block kb + 1 (kb + 2 for short tiles) are requested before the MFMAs
+  // of block kb.
   // Scheduling barriers keep the compiler from sinking those loads next to
   // their first use.
   F a0[NA], a1[NA], b0[MAXCT], b1[MAXCT], l0[kSplit ? MAXCT : 1], l1[kSplit ? MAXCT : 1];
@@ -190,15 +205,33 @@ __device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typen
     }
     __builtin_amdgcn_sched_barrier(0);
   };
-  load(a0, b0, l0, kb0);
-  int kb = kb0;
-  for (; kb + 1 < kb1; kb += 2) {
-    load(a1, b1, l1, kb + 1);
-    compute(a0, b0, l0, kb);
-    load(a0, b0, l0, clampk(kb + 2));
-    compute(a1, b1, l1, kb + 1);
+  if constexpr (PREF_A && RT <= 2) {
+    // short tiles have few MFMAs per K block: request two blocks ahead
+    F a2[NA], b2[MAXCT], l2[kSplit ? MAXCT : 1];
+    load(a0, b0, l0, kb0);
+    load(a1, b1, l1, clampk(kb0 + 1));
+    int kb = kb0;
+    for (; kb + 2 < kb1; kb += 3) {
+      load(a2, b2, l2, kb + 2);
+      compute(a0, b0, l0, kb);
+      load(a0, b0, l0, clampk(kb + 3));
+      compute(a1, b1, l1, kb + 1);
+      load(a1, b1, l1, clampk(kb + 4));
+      compute(a2, b2, l2, kb + 2);
+    }
+    if (kb < kb1) compute(a0, b0, l0, kb);
+    if (kb + 1 < kb1) compute(a1, b1, l1, kb + 1);
+  } else {
+    load(a0, b0, l0, kb0);
+    int kb = kb0;
+    for (; kb + 1 < kb1; kb += 2) {
+      load(a1, b1, l1, kb + 1);
+      compute(a0, b0, l0, kb);
+      load(a0, b0, l0, clampk(kb + 2));
+      compute(a1, b1, l1, kb + 1);
+    }
+    if (kb < kb1) compute(a0, b0, l0, kb);
   }
-  if (kb < kb1) compute(a0, b0, l0, kb);
   // tiles clamped onto the last one hold copies: zero them so that register
   // uses of acc (gradients, dot products) see exact zeros there
 #pragma unroll
@@ -247,7 +280,7 @@ template <int PREC, int TM, class Src>
 __device__ __forceinline__ void gather_rows(typename PT<PREC>::T* X, int ldx, int e0, int E, int c0, int w4,
                                             Src src) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  constexpr int RPW = TM / 4;
+  constexpr int RPW = TM / kNW;
   const int total = RPW * w4;
   for (int t0 = 0; t0 < total; t0 += 64 * 8) {
     float4 v[8];
@@ -273,7 +306,7 @@ __device__ __forceinline__ void gather_rows(typename PT<PREC>::T* X, int ldx, in
 template <int PREC, int TM>
 __device__ __forceinline__ void zero_cols(typename PT<PREC>::T* X, int ldx, int c0, int w4) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  constexpr int RPW = TM / 4;
+  constexpr int RPW = TM / kNW;
   for (int t = lane; t < RPW * w4; t += 64) {
     const int r = t / w4, q = t - r * w4;
     store4(X + (wave * RPW + r) * ldx + c0 + 4 * q, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
@@ -317,7 +350,7 @@ template <int PREC, int KIND, int TM>
 __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp) {
   using T = typename PT<PREC>::T;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  constexpr int RPW = TM / 4;
+  constexpr int RPW = TM / kNW;
   if constexpr (KIND == kTwoBody) {
     // one row per lane pass: the row's species pair, then its columns
     const int S = a.n_species, nb = a.n_bessel;
@@ -424,15 +457,18 @@ __device__ __forceinline__ const typename PT<PREC>::T* hidden_layers(
   return in;
 }
 
+#ifndef ALLEGRO_MLP_MINB
+#define ALLEGRO_MLP_MINB 1
+#endif
 template <int PREC, int KIND, int TM, int MAXCT>
-__global__ __launch_bounds__(256, 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
+__global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
   extern __shared__ __align__(16) char smem[];
   T* X = (T*)smem;
   T* H = X + TM * ldx;
-  __shared__ float red[4][TM];
+  __shared__ float red[kNW][TM];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
 
@@ -516,7 +552,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh)
     if ((int)threadIdx.x < TM) {
       const int e = e0 + threadIdx.x;
       if (e < a.E)
-        a.eij[e] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+        a.eij[e] = wave_partials_sum(red, threadIdx.x);
     }
     return;
   }
@@ -545,7 +581,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh)
 }
 
 template <int PREC, int KIND, int TM, int MAXCT>
-__global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
+__global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -553,7 +589,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh)
   T* X = (T*)smem;
   T* H = X + TM * ldx;
   T* Pb = H + TM * ldh;                 // nl-1 pre-activation buffers [TM][ldh]
-  __shared__ float red[4][TM];
+  __shared__ float red[kNW][TM];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
   const int d = a.d;
@@ -643,8 +679,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh)
   if ((int)threadIdx.x < TM) {
     const int e = e0 + threadIdx.x;
     if (e < a.E) {
-      const float gu = rs * (((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                             red[3][threadIdx.x]);
+      const float gu = rs * wave_partials_sum(red, threadIdx.x);
       a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
     }
   }
@@ -709,7 +744,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh)
 // tiles (half the L2 traffic per MFMA of a 64-row tile).  Activations live in
 // one LDS buffer and are updated in place: a layer's output overwrites its
 // input after a barrier.  Requires every hidden width to fit one pass
-// (<= 64 MAXCT columns).  The backward kernel writes the hidden
+// (<= 16 kNW MAXCT columns).  The backward kernel writes the hidden
 // pre-activations of its recomputation to a global scratch array in register
 // (fragment) order, and dE/dx_out to the output row it is added to at the
 // end.  Per element the arithmetic is the same as in the 64- and 32-row
@@ -719,16 +754,16 @@ constexpr int kTallRows = 128;
 // Scratch slot of fragment (rt, q) of this wave for hidden layer l.
 template <int MAXCT>
 __device__ __forceinline__ size_t zslot(int l, int wave, int q, int rt, int lane) {
-  return (((((size_t)blockIdx.x * 2 + l) * 4 + wave) * MAXCT + q) * 8 + rt) * 64 + lane;
+  return (((((size_t)blockIdx.x * 2 + l) * kNW + wave) * MAXCT + q) * 8 + rt) * 64 + lane;
 }
 
 template <int PREC, int KIND, int MAXCT>
-__global__ __launch_bounds__(256, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
+__global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
   using T = typename PT<PREC>::T;
   constexpr int TM = kTallRows, RT = 8;
   extern __shared__ __align__(16) char smem[];
   T* X = (T*)smem;
-  __shared__ float red[4][TM];
+  __shared__ float red[kNW][TM];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
   const int d = a.d, nl = a.w.nl;
@@ -800,7 +835,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
     if ((int)threadIdx.x < TM) {
       const int e = e0 + threadIdx.x;
       if (e < a.E)
-        a.eij[e] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+        a.eij[e] = wave_partials_sum(red, threadIdx.x);
     }
     return;
   } else {
@@ -828,13 +863,13 @@ __global__ __launch_bounds__(256, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
 }
 
 template <int PREC, int KIND, int MAXCT>
-__global__ __launch_bounds__(256, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, int) {
+__global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, int) {
   using T = typename PT<PREC>::T;
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   constexpr int TM = kTallRows, RT = 8;
   extern __shared__ __align__(16) char smem[];
   T* X = (T*)smem;
-  __shared__ float red[4][TM];
+  __shared__ float red[kNW][TM];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
   const int d = a.d, nl = a.w.nl;
@@ -951,8 +986,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, int) {
   if ((int)threadIdx.x < TM) {
     const int e = e0 + threadIdx.x;
     if (e < a.E) {
-      const float gu = rs * (((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                             red[3][threadIdx.x]);
+      const float gu = rs * wave_partials_sum(red, threadIdx.x);
       a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
     }
   }
@@ -1020,7 +1054,7 @@ void lds_dims(const MlpArgs& a, int TM, bool bwd, int* ldx, int* ldh, size_t* by
 // Accumulator tiles per wave: the latent width d must fit one pass.
 inline int max_ct(const MlpArgs& a) {
   const int dt = (a.d + 15) / 16;
-  return (dt + 3) / 4;
+  return (dt + kNW - 1) / kNW;
 }
 
 // Tall tiles (BF16 only): one LDS buffer [128][ldx]; every hidden width and
@@ -1028,7 +1062,7 @@ inline int max_ct(const MlpArgs& a) {
 // scratch arrays.
 inline bool tall_ok(const MlpArgs& a, int prec, bool bwd) {
   if (prec == 0) return false;
-  const int cols = 64 * max_ct(a);
+  const int cols = 16 * kNW * max_ct(a);
   for (int l = 0; l < a.w.nl; ++l)
     if (a.w.fwd[l].Np > cols) return false;
   if (bwd && (a.g_store == nullptr || (a.w.nl > 1 && a.act_scratch == nullptr))) return false;
@@ -1045,8 +1079,8 @@ inline void tall_dims(const MlpArgs& a, int* ldx, size_t* bytes) {
 // Bytes of the pre-activation scratch array for E rows (two hidden layers of
 // 64 MAXCT columns per 128-row tile, BF16).
 inline size_t tall_scratch_bytes(int64_t E, int d) {
-  const int ct = ((d + 15) / 16 + 3) / 4;
-  return (size_t)((E + kTallRows - 1) / kTallRows) * 2 * kTallRows * 64 * ct * 2;
+  const int ct = ((d + 15) / 16 + kNW - 1) / kNW;
+  return (size_t)((E + kTallRows - 1) / kTallRows) * 2 * kTallRows * 16 * kNW * ct * 2;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024 - 4096;
@@ -1056,7 +1090,7 @@ hipError_t launch_one(const MlpArgs& a, bool bwd, hipStream_t s) {
   int ldx, ldh;
   size_t bytes;
   lds_dims<PREC>(a, TM, bwd, &ldx, &ldh, &bytes);
-  const dim3 grid((a.E + TM - 1) / TM), block(256);
+  const dim3 grid((a.E + TM - 1) / TM), block(kThreads);
   auto k = bwd ? k_mlp_bwd<PREC, KIND, TM, MAXCT> : k_mlp_fwd<PREC, KIND, TM, MAXCT>;
   hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (st != hipSuccess) return st;
@@ -1069,7 +1103,7 @@ hipError_t launch_tall(const MlpArgs& a, bool bwd, hipStream_t s) {
   int ldx;
   size_t bytes;
   tall_dims(a, &ldx, &bytes);
-  const dim3 grid((a.E + kTallRows - 1) / kTallRows), block(256);
+  const dim3 grid((a.E + kTallRows - 1) / kTallRows), block(kThreads);
   auto k = bwd ? k_mlp_bwd_t<PREC, KIND, MAXCT> : k_mlp_fwd_t<PREC, KIND, MAXCT>;
   hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (st != hipSuccess) return st;
@@ -1082,16 +1116,15 @@ hipError_t dispatch_tall(const MlpArgs& a, bool bwd, hipStream_t s) {
   const int ct = max_ct(a);
   if (ct <= 1) return launch_tall<PREC, KIND, 1>(a, bwd, s);
   if (ct <= 2) return launch_tall<PREC, KIND, 2>(a, bwd, s);
-  if (ct <= 4) return launch_tall<PREC, KIND, 4>(a, bwd, s);
   return hipErrorInvalidValue;
 }
 
+// d <= 256 (the interface's limit): at most two column tiles per wave
 template <int PREC, int KIND, int TM>
 hipError_t dispatch_ct(const MlpArgs& a, bool bwd, hipStream_t s) {
   const int ct = max_ct(a);
   if (ct <= 1) return launch_one<PREC, KIND, TM, 1>(a, bwd, s);
   if (ct <= 2) return launch_one<PREC, KIND, TM, 2>(a, bwd, s);
-  if (ct <= 4) return launch_one<PREC, KIND, TM, 4>(a, bwd, s);
   return hipErrorInvalidValue;
 }
 
