@@ -783,6 +783,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
       mf.w = m->latent[0].view(); mf.x_prev = ptr<float>(m->x[0]); mf.tp_v = v_a0; mf.tp_gam = ptr<float>(m->gam[0]);
     }
     mf.tm = m->tm_choice[2];
+    mf.tp_out = ptr<float>(m->gTf);   // the final scalars, read back by the backward pass
     timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, m->prec_lat, s); });
 
     ReduceArgs ra;
@@ -791,6 +792,8 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     timed(m, "atom_energy", s, [&] { return launch_atom_energy(ra, s); });
 
     // ---- adjoint ----
+    // the backward reads each row's stored scalars before overwriting them with dE/ds
+    mf.tp_out = nullptr; mf.s_in = ptr<float>(m->gTf); mf.s_ld = n;
     mf.g_xprev = ptr<float>(m->gxa); mf.g_s = ptr<float>(m->gTf); mf.g_u = ptr<float>(m->gu); mf.gu_accum = 0;
     mf.g_store = mf.g_xprev; mf.act_scratch = m->zscr.p;
     mf.tm = m->tm_choice[3];

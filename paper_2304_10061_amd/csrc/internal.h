@@ -66,11 +66,14 @@ struct MlpArgs {
   const int32_t* species = nullptr;  // [n_total]
   // latent inputs
   const float* x_prev = nullptr;  // [E][d]
-  const float* s_in = nullptr;    // non-final: V^L (component 0 = first n floats), row stride s_ld
+  const float* s_in = nullptr;    // non-final: V^L (component 0 = first n floats), row stride s_ld;
+                                  // final: the stored tensor-product scalars, or null to recompute them
   int s_ld = 0;
   // final layer: scalar tensor-product outputs computed in the prologue
   VSrc tp_v;
   const float* tp_gam = nullptr;  // Gamma [centres][dim][n]
+  float* tp_out = nullptr;        // forward: receives those scalars [E][n] (optional); the
+                                  // backward reads them back through s_in (s_ld = n)
   float tp_w[9] = {0};            // diagonal coupling weight of each component
   float res_scale = 0.70710678118654752f;
   // forward outputs

@@ -32,7 +32,7 @@ bool tall_fits(const MlpArgs& a, int prec, bool bwd) {
   if (!tall_ok(a, prec, bwd)) return false;
   int ldx;
   size_t bytes;
-  tall_dims(a, &ldx, &bytes);
+  tall_dims(a, bwd, &ldx, &bytes);
   return bytes <= kLdsLimit;
 }
 

@@ -160,9 +160,8 @@ __device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typen
     nt = nt < nct ? nt : nct - 1;
     bq[q] = (uint32_t)(nt * nkb) * 512 * sizeof(T);
   }
-  // Register buffers of B (and A) fragments, used in rotation: the fragments
-  // of K block kb + 1 (kb + 2 for short tiles) are requested before the MFMAs
-  // of block kb.
+  // Two register sets of B (and A) fragments, used in turn: the fragments of
+  // K block kb + 1 are requested before the MFMAs of block kb.
   // Scheduling barriers keep the compiler from sinking those loads next to
   // their first use.
   F a0[NA], a1[NA], b0[MAXCT], b1[MAXCT], l0[kSplit ? MAXCT : 1], l1[kSplit ? MAXCT : 1];
@@ -205,33 +204,15 @@ __device__ __forceinline__ void gemm_tile_k(f32x4 (&acc)[RT][MAXCT], const typen
     }
     __builtin_amdgcn_sched_barrier(0);
   };
-  if constexpr (PREF_A && RT <= 2) {
-    // short tiles have few MFMAs per K block: request two blocks ahead
-    F a2[NA], b2[MAXCT], l2[kSplit ? MAXCT : 1];
-    load(a0, b0, l0, kb0);
-    load(a1, b1, l1, clampk(kb0 + 1));
-    int kb = kb0;
-    for (; kb + 2 < kb1; kb += 3) {
-      load(a2, b2, l2, kb + 2);
-      compute(a0, b0, l0, kb);
-      load(a0, b0, l0, clampk(kb + 3));
-      compute(a1, b1, l1, kb + 1);
-      load(a1, b1, l1, clampk(kb + 4));
-      compute(a2, b2, l2, kb + 2);
-    }
-    if (kb < kb1) compute(a0, b0, l0, kb);
-    if (kb + 1 < kb1) compute(a1, b1, l1, kb + 1);
-  } else {
-    load(a0, b0, l0, kb0);
-    int kb = kb0;
-    for (; kb + 1 < kb1; kb += 2) {
-      load(a1, b1, l1, kb + 1);
-      compute(a0, b0, l0, kb);
-      load(a0, b0, l0, clampk(kb + 2));
-      compute(a1, b1, l1, kb + 1);
-    }
-    if (kb < kb1) compute(a0, b0, l0, kb);
+  load(a0, b0, l0, kb0);
+  int kb = kb0;
+  for (; kb + 1 < kb1; kb += 2) {
+    load(a1, b1, l1, kb + 1);
+    compute(a0, b0, l0, kb);
+    load(a0, b0, l0, clampk(kb + 2));
+    compute(a1, b1, l1, kb + 1);
   }
+  if (kb < kb1) compute(a0, b0, l0, kb);
   // tiles clamped onto the last one hold copies: zero them so that register
   // uses of acc (gradients, dot products) see exact zeros there
 #pragma unroll
@@ -376,7 +357,9 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
   const int d = a.d, n = a.n;
   gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, d >> 2,
                         [&](int e, int c) { return ld4(a.x_prev, (uint32_t)e * d + c); });
-  if constexpr (KIND == kLatent) {
+  if (KIND == kLatent || a.s_in != nullptr) {
+    // latent: V^L[0]; final layer with s_in set: the tensor-product scalars
+    // its forward pass stored
     gather_rows<PREC, TM>(X, ldx, e0, a.E, d, n >> 2,
                           [&](int e, int c) { return ld4(a.s_in, (uint32_t)e * a.s_ld + (c - d)); });
   } else {
@@ -388,6 +371,7 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
       const int row = wave * RPW + r, e = e0 + row;
       float4 v = final_tp4(a, e < a.E ? e : a.E - 1, 4 * q);
       if (e >= a.E) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      else if (a.tp_out) *(float4*)(a.tp_out + (uint32_t)e * n + 4 * q) = v;
       store4(X + row * ldx + d + 4 * q, v);
     }
   }
@@ -457,11 +441,15 @@ __device__ __forceinline__ const typename PT<PREC>::T* hidden_layers(
   return in;
 }
 
-#ifndef ALLEGRO_MLP_MINB
-#define ALLEGRO_MLP_MINB 1
-#endif
+// Short tiles (32 BF16 / 16 FP32 rows) are compiled for four waves per SIMD
+// (<= 128 VGPRs) so that two blocks share a CU: one block's gathers and
+// barriers then overlap the other's MFMAs.
+template <int PREC, int TM>
+constexpr int kWavesPerEu = TM * (PREC ? 1 : 2) <= 32 ? 4 : 1;
+
 template <int PREC, int KIND, int TM, int MAXCT>
-__global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PREC, TM>, 8)))
+void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -581,7 +569,8 @@ __global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_m
 }
 
 template <int PREC, int KIND, int TM, int MAXCT>
-__global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PREC, TM>, 8)))
+void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -617,6 +606,10 @@ __global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_m
 #pragma unroll
         for (int i = 0; i < 4; ++i) G[rt][q][i] = gsrc ? gsrc[rowoff[rt][i] + cc] : 0.0f;
     }
+  }
+  // G is masked (rows beyond E, columns beyond d) only after the head part,
+  // so that its loads and the head staging loads are in flight together
+  auto mask_g = [&] {
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
       const int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
@@ -628,19 +621,17 @@ __global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_m
           if (!(e < a.E && col < d)) G[rt][q][i] = 0.0f;
         }
     }
+  };
+  // u of the tile's rows (zero beyond E), kept in LDS until the chain is recomputed
+  __shared__ float us[TM];
+  if ((int)threadIdx.x < TM) {
+    const int e = e0 + threadIdx.x;
+    us[threadIdx.x] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
   }
-  // u of this lane's rows (zero beyond E)
-  float ur[RT][4];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-      ur[rt][i] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
-    }
   f32x4 acc[RT][MAXCT];
   if (KIND != kLatentFinal && a.head_bwd.p != nullptr) {
-    // G += g_head @ W_head^T, K staged through X in chunks of its width
+    // G += g_head @ W_head^T, K staged through X (in chunks of its width
+    // where X is narrower than the head)
     const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5, chunk = ldx >> 5;
     for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
       const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
@@ -656,6 +647,7 @@ __global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_m
 #pragma unroll
       for (int q = 0; q < MAXCT; ++q) G[rt][q] += acc[rt][q];
   }
+  mask_g();
 
   // 2. recompute the chain, keeping hidden pre-activations
   build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
@@ -691,7 +683,7 @@ __global__ __launch_bounds__(kThreads, TM <= 32 ? ALLEGRO_MLP_MINB : 1) void k_m
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[rt][q][i] = rs * ur[rt][i] * G[rt][q][i];
+      for (int i = 0; i < 4; ++i) acc[rt][q][i] = rs * us[rt * 16 + 4 * (lane >> 4) + i] * G[rt][q][i];
   store_tile<PREC, RT, MAXCT>(acc, cur, ldc, a.w.fwd[nl - 1].Np, wave, lane, 0,
                               [](float v, int, int) { return v; });
   __syncthreads();
@@ -1044,6 +1036,7 @@ void lds_dims(const MlpArgs& a, int TM, bool bwd, int* ldx, int* ldh, size_t* by
   int kh = 32;                       // widths of hidden layers and of the output d
   for (int l = 0; l < a.w.nl; ++l) kh = kh > a.w.fwd[l].Np ? kh : a.w.fwd[l].Np;
   int kx = kh > a.w.fwd[0].Kp ? kh : a.w.fwd[0].Kp;
+  if (bwd && a.head_bwd.p != nullptr && a.head_bwd.Kp > kx) kx = a.head_bwd.Kp;   // head staged in one piece
   const int pad = PREC ? 8 : 4;
   *ldx = kx + pad;
   *ldh = kh + pad;
@@ -1069,9 +1062,10 @@ inline bool tall_ok(const MlpArgs& a, int prec, bool bwd) {
   return a.w.nl <= 3;
 }
 
-inline void tall_dims(const MlpArgs& a, int* ldx, size_t* bytes) {
+inline void tall_dims(const MlpArgs& a, bool bwd, int* ldx, size_t* bytes) {
   int k = a.w.fwd[0].Kp;
   for (int l = 0; l < a.w.nl; ++l) k = k > a.w.fwd[l].Np ? k : a.w.fwd[l].Np;
+  if (bwd && a.head_bwd.p != nullptr && a.head_bwd.Kp > k) k = a.head_bwd.Kp;
   *ldx = k + 8;
   *bytes = (size_t)kTallRows * *ldx * 2;
 }
@@ -1102,7 +1096,7 @@ template <int PREC, int KIND, int MAXCT>
 hipError_t launch_tall(const MlpArgs& a, bool bwd, hipStream_t s) {
   int ldx;
   size_t bytes;
-  tall_dims(a, &ldx, &bytes);
+  tall_dims(a, bwd, &ldx, &bytes);
   const dim3 grid((a.E + kTallRows - 1) / kTallRows), block(kThreads);
   auto k = bwd ? k_mlp_bwd_t<PREC, KIND, MAXCT> : k_mlp_fwd_t<PREC, KIND, MAXCT>;
   hipError_t st = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
