@@ -732,7 +732,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     const int32_t* drp = ptr<int32_t>(m->chunk_rp) + m->chunk_rp_off[k];
 
     EdgeArgs ea;
-    ea.E = E; ea.pos = pos; ea.ei = ei + eA; ea.ej = ej + eA; ea.es = es + 3 * eA;
+    ea.E = E; ea.pos = pos; ea.ei = ei + eA; ea.ej = ej + eA; ea.es = es + 3 * eA; ea.species = species;
     for (int ax = 0; ax < 3; ++ax) ea.L[ax] = m->L[ax];
     ea.r_cut = m->cfg.r_cut; ea.p = v.p; ea.n_bessel = v.nb; ea.l_max = v.lmax;
     ea.eb = ptr<float>(m->eb);

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
   o[kEB_U] = u;
   o[kEB_D] = d;
   o[kEB_RHAT] = x; o[kEB_RHAT + 1] = y; o[kEB_RHAT + 2] = z;
-  o[14] = 0.0f; o[15] = 0.0f;
+  o[kEB_ZI] = (float)a.species[a.ei[e]];
+  o[kEB_ZJ] = (float)a.species[a.ej[e]];
   const float pref = sqrtf(2.0f / rc);
   for (int k = 0; k < 16; ++k) {
     float v = 0.0f;

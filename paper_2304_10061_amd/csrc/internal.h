@@ -3,7 +3,7 @@
 //
 // Edge-major layouts in HBM (E = edges of the current chunk, rows ordered by
 // centre, each centre's neighbours sorted by (j, shift)):
-//   eb      [E][kEB]     float  edge record: Y[0..8], u, d, rhat[3], R[16..31]
+//   eb      [E][kEB]     float  edge record: Y[0..8], u, d, rhat[3], Z_i, Z_j, R[16..31]
 //   x^L     [E][d]       float  latent (scalar-track) features, the residual stream
 //   head    [E][H]       float  outputs of the linear map that follows an MLP
 //                               (after the two-body MLP: [a0 | w^1], each
@@ -23,6 +23,8 @@ constexpr int kEB = 32;     // floats per edge record
 constexpr int kEB_U = 9;
 constexpr int kEB_D = 10;
 constexpr int kEB_RHAT = 11;
+constexpr int kEB_ZI = 14;  // species of the centre and of the neighbour (small integers held
+constexpr int kEB_ZJ = 15;  // exactly as floats), so that edge-row readers need no index chase
 constexpr int kEB_R = 16;   // radial basis R_n = B_n u, n < 16
 
 constexpr int kMaxMlpLayers = 3;
@@ -101,6 +103,7 @@ struct EdgeArgs {
   const int32_t* ei = nullptr;    // global centre index
   const int32_t* ej = nullptr;
   const int32_t* es = nullptr;    // [E][3]
+  const int32_t* species = nullptr;  // [n_total]
   double L[3] = {0, 0, 0};        // periodic lengths (0 = open axis)
   double r_cut = 0;
   int p = 6, n_bessel = 8, l_max = 2;

@@ -38,6 +38,8 @@ bool tall_fits(const MlpArgs& a, int prec, bool bwd) {
 
 hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
   if (a.E <= 0) return hipSuccess;
+  // the final layer's backward reads the scalars its forward pass stored
+  if (bwd && a.kind == kLatentFinal && a.s_in == nullptr) return hipErrorInvalidValue;
   if (prec == 1 || prec == 2) {
     // tall tiles on request (autotuner or allegro_set_tiles), where they fit
     if (a.tm == kTallRows && tall_fits(a, prec, bwd))

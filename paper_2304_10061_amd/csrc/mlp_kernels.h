@@ -252,22 +252,25 @@ __device__ __forceinline__ void store4(float* p, float4 v) { *(float4*)p = v; }
 __device__ __forceinline__ float4 ld4(const float* base, uint32_t off) { return *(const float4*)(base + off); }
 
 // Copies float4 chunks of edge rows into X: for each row r of this wave's
-// TM/4 rows and chunk q < w4, X[r][c0 + 4q ..] = *src(e, c0 + 4q) for edges
-// e0 + r < E (zero otherwise).  The (row, chunk) items are spread over the
-// lanes and processed eight at a time with every load issued before the
-// first store, so eight loads per lane are in flight.  `src` must return an
-// in-range address for any e < E and column of the range.
+// TM/kNW rows and chunk q < w4, X[r][c0 + 4q ..] = *src(e, c0 + 4q) for
+// edges e0 + r < E (zero otherwise).  The (row, chunk) items are spread over
+// the lanes and processed NB at a time with every load issued before the
+// first store: a bulk gather costs one memory round trip per NB items per
+// lane (one in all, for rows of up to 320 floats), the round trips being
+// what these latency-bound kernels wait on.  `src` must return an in-range
+// value for any e < E and column of the range.
 template <int PREC, int TM, class Src>
 __device__ __forceinline__ void gather_rows(typename PT<PREC>::T* X, int ldx, int e0, int E, int c0, int w4,
                                             Src src) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int RPW = TM / kNW;
+  constexpr int NB = TM >= 64 ? 12 : 8;
   const int total = RPW * w4;
-  for (int t0 = 0; t0 < total; t0 += 64 * 8) {
-    float4 v[8];
-    int off[8];
+  for (int t0 = 0; t0 < total; t0 += 64 * NB) {
+    float4 v[NB];
+    int off[NB];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NB; ++j) {
       const int t = t0 + lane + 64 * j;
       const int r = t / w4, q = t - r * w4;
       const int row = wave * RPW + (r < RPW ? r : RPW - 1);
@@ -278,7 +281,7 @@ __device__ __forceinline__ void gather_rows(typename PT<PREC>::T* X, int ldx, in
       off[j] = t < total ? row * ldx + c0 + 4 * q : -1;
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < NB; ++j)
       if (off[j] >= 0) store4(X + off[j], v[j]);
   }
 }
@@ -297,9 +300,9 @@ __device__ __forceinline__ void zero_cols(typename PT<PREC>::T* X, int ldx, int 
 // Final-layer scalar tensor product for channels u..u+3 of edge e:
 // T[u] = sum_c w_c V[c][u] Gamma[c][u] (V either stored or the rank-1
 // first-layer form a0[l(c)][u] Y_c).
-__device__ __forceinline__ float4 final_tp4(const MlpArgs& a, int e, int u) {
+__device__ __forceinline__ float4 final_tp4(const MlpArgs& a, int e, int centre, int u) {
   const int dim = (a.l_max + 1) * (a.l_max + 1);
-  const uint32_t gbase = (uint32_t)(a.ei[e] - a.centre_base) * dim * a.n + u;
+  const uint32_t gbase = (uint32_t)(centre - a.centre_base) * dim * a.n + u;
   const uint32_t vbase = (uint32_t)e * a.tp_v.ld + u;
   float4 g[9], vv[9];
   float wy[9];
@@ -327,7 +330,9 @@ __device__ __forceinline__ float4 final_tp4(const MlpArgs& a, int e, int u) {
 // Input rows of the chain for edges e0 .. e0+TM-1, zero padded to Kp.
 //   two-body: [onehot(Z_i), onehot(Z_j), R_0..R_{nb-1}]
 //   latent:   [x^{L-1}, V^L[0] (or the final scalar tensor product)]
-template <int PREC, int KIND, int TM>
+// STORED: the final layer's scalars are read from s_in (backward kernels;
+// the host guarantees s_in), never recomputed.
+template <int PREC, int KIND, int TM, bool STORED = false>
 __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp) {
   using T = typename PT<PREC>::T;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -340,7 +345,8 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
       const int row = wave * RPW + r, e = e0 + row;
       const bool ok = e < a.E;
       const int ec = ok ? e : a.E - 1;
-      const int zi = a.species[a.ei[ec]], zj = a.species[a.ej[ec]];
+      const float* rec = a.eb + (uint32_t)ec * kEB;
+      const int zi = (int)rec[kEB_ZI], zj = (int)rec[kEB_ZJ];
       float x[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -355,24 +361,62 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
     }
   } else {
   const int d = a.d, n = a.n;
-  gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, d >> 2,
-                        [&](int e, int c) { return ld4(a.x_prev, (uint32_t)e * d + c); });
-  if (KIND == kLatent || a.s_in != nullptr) {
-    // latent: V^L[0]; final layer with s_in set: the tensor-product scalars
-    // its forward pass stored
-    gather_rows<PREC, TM>(X, ldx, e0, a.E, d, n >> 2,
-                          [&](int e, int c) { return ld4(a.s_in, (uint32_t)e * a.s_ld + (c - d)); });
-  } else {
-    // final layer: one (row, 4 channels) item per lane at a time; each
-    // gathers 2 dim float4s before combining them
-    const int w4 = n >> 2;
-    for (int t = lane; t < RPW * w4; t += 64) {
-      const int r = t / w4, q = t - r * w4;
-      const int row = wave * RPW + r, e = e0 + row;
-      float4 v = final_tp4(a, e < a.E ? e : a.E - 1, 4 * q);
-      if (e >= a.E) v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      else if (a.tp_out) *(float4*)(a.tp_out + (uint32_t)e * n + 4 * q) = v;
-      store4(X + row * ldx + d + 4 * q, v);
+  if (KIND == kLatent || STORED || a.s_in != nullptr) {
+    // [x_prev | s] in one gather: s is V^L[0] (latent) or, for the final
+    // layer, the tensor-product scalars its forward pass stored
+    gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, (d + n) >> 2, [&](int e, int c) {
+      const float* p = c < d ? a.x_prev + (uint32_t)e * d + c : a.s_in + (uint32_t)e * a.s_ld + (c - d);
+      return *(const float4*)p;
+    });
+  } else if constexpr (!STORED) {
+    // final layer: the scalar tensor product of each (row, 4 channels) item,
+    // NI items per lane at a time (a tile has at most TM/32 per lane).  The
+    // centres of the first NI are requested before the x_prev gather so that
+    // their latency overlaps it.
+    constexpr int NI = TM >= 64 ? 2 : 1;
+    const int w4 = n >> 2, total = RPW * w4;
+    auto item_edge = [&](int t, int* row, int* q) {
+      const int r = t / w4;
+      *q = t - r * w4;
+      *row = wave * RPW + r;
+      return e0 + *row;
+    };
+    int cen[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      int row, q;
+      const int e = item_edge(lane + 64 * j, &row, &q);
+      cen[j] = a.ei[e < a.E ? e : a.E - 1];
+    }
+    gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, d >> 2,
+                          [&](int e, int c) { return ld4(a.x_prev, (uint32_t)e * d + c); });
+    for (int t0 = 0; t0 < total; t0 += 64 * NI) {
+      if (t0 > 0) {
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          int row, q;
+          const int e = item_edge(t0 + lane + 64 * j, &row, &q);
+          cen[j] = a.ei[e < a.E ? e : a.E - 1];
+        }
+      }
+      float4 v[NI];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        int row, q;
+        const int e = item_edge(t0 + lane + 64 * j, &row, &q);
+        v[j] = final_tp4(a, e < a.E ? e : a.E - 1, cen[j], 4 * q);
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int t = t0 + lane + 64 * j;
+        int row, q;
+        const int e = item_edge(t, &row, &q);
+        if (t >= total) continue;
+        float4 vv = v[j];
+        if (e >= a.E) vv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        else if (a.tp_out) *(float4*)(a.tp_out + (uint32_t)e * n + 4 * q) = vv;
+        store4(X + row * ldx + d + 4 * q, vv);
+      }
     }
   }
   if (Kp > d + n) zero_cols<PREC, TM>(X, ldx, d + n, (Kp - d - n) >> 2);
@@ -595,7 +639,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
       for (int i = 0; i < 4; ++i) {
         int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
         e = e < a.E ? e : a.E - 1;
-        rowoff[rt][i] = (uint32_t)(KIND == kLatentFinal ? a.species[a.ei[e]] : e) * d;
+        rowoff[rt][i] = (uint32_t)(KIND == kLatentFinal ? (int)a.eb[(uint32_t)e * kEB + kEB_ZI] : e) * d;
       }
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
@@ -650,7 +694,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   mask_g();
 
   // 2. recompute the chain, keeping hidden pre-activations
-  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
   __syncthreads();
   int ldin;
   const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, Pb, ldh, &ldin, wave, lane);
@@ -898,7 +942,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
         for (int i = 0; i < 4; ++i) {
           int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
           e = e < a.E ? e : a.E - 1;
-          const uint32_t ro = (uint32_t)(KIND == kLatentFinal ? a.species[a.ei[e]] : e) * d;
+          const uint32_t ro = (uint32_t)(KIND == kLatentFinal ? (int)a.eb[(uint32_t)e * kEB + kEB_ZI] : e) * d;
 #pragma unroll
           for (int q = 0; q < MAXCT; ++q) {
             int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
@@ -921,7 +965,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
   }
 
   // 2. recompute the chain; hidden pre-activations to the scratch array
-  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
   __syncthreads();
   for (int l = 0; l + 1 < nl; ++l) {
     gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.fwd[l], wave, lane, 0);
