@@ -366,15 +366,18 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
   const bool keep_gy = a.gy_accum != 0;
   const float cn = a.c_norm;
   // centres of the wave's edges: one load per lane, read out per edge.  With
-  // one edge per wave step (G = 1) the centre is wave-uniform and its
-  // dE/dGamma (and Gamma) rows stay in registers until it changes.
+  // one edge per wave step (G = 1) the centre is wave-uniform; without the
+  // first-layer rank-1 form its dE/dGamma rows then stay in registers until
+  // it changes (CACHE).  The rank-1 form keeps every row load in the batched
+  // load phase, where its latency overlaps the batch's other loads.
+  constexpr bool CACHE = G == 1 && !A0;
   const int64_t el = w0 + (lane & (kEdgesPerWave - 1));
   const int ci_lane = el < a.E ? a.ei[el] - a.centre_base : 0;
   int cur = -1;
-  float cG[DIM], cM[A0 ? DIM : 1];
+  float cG[CACHE ? DIM : 1];
   for (int j0 = 0; j0 < kEdgesPerWave; j0 += G * KB) {
-    float gG[G == 1 ? 1 : KB][DIM], Yv[KB][DIM], wv[KB][LMAX + 1];
-    float Gm[A0 && G != 1 ? KB : 1][DIM], gT[A0 ? KB : 1][DOUT], a0v[A0 ? KB : 1][LMAX + 1];
+    float gG[CACHE ? 1 : KB][DIM], Yv[KB][DIM], wv[KB][LMAX + 1];
+    float Gm[A0 ? KB : 1][DIM], gT[A0 ? KB : 1][DOUT], a0v[A0 ? KB : 1][LMAX + 1];
     bool act[KB];
     uint32_t eev[KB], civ[KB];
 #pragma unroll
@@ -393,7 +396,7 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       for (int b = 0; b < DIM; ++b) Yv[q][b] = Y[b];
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) wv[q][l] = wp[l * n];
-      if constexpr (G != 1) {
+      if constexpr (!CACHE) {
         const float* ggp = a.g_gam + ci * (uint32_t)(DIM * n) + u;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) gG[q][b] = ggp[b * n];
@@ -401,11 +404,9 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       if constexpr (A0) {
         const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
         const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
-        if constexpr (G != 1) {
-          const float* gmp = a.gam + ci * (uint32_t)(DIM * n) + u;
+        const float* gmp = a.gam + ci * (uint32_t)(DIM * n) + u;
 #pragma unroll
-          for (int b = 0; b < DIM; ++b) Gm[q][b] = gmp[b * n];
-        }
+        for (int b = 0; b < DIM; ++b) Gm[q][b] = gmp[b * n];
 #pragma unroll
         for (int k = 0; k < DOUT; ++k) gT[q][k] = gtp[k * n];
 #pragma unroll
@@ -415,20 +416,15 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
       const uint32_t ee = eev[q];
-      if constexpr (G == 1) {
+      if constexpr (CACHE) {
         if ((int)civ[q] != cur) {   // wave-uniform
           const float* ggp = a.g_gam + civ[q] * (uint32_t)(DIM * n) + u;
 #pragma unroll
           for (int b = 0; b < DIM; ++b) cG[b] = ggp[b * n];
-          if constexpr (A0) {
-            const float* gmp = a.gam + civ[q] * (uint32_t)(DIM * n) + u;
-#pragma unroll
-            for (int b = 0; b < DIM; ++b) cM[b] = gmp[b * n];
-          }
           cur = (int)civ[q];
         }
       }
-      const float* gGq = G == 1 ? cG : gG[G == 1 ? 0 : q];
+      const float* gGq = CACHE ? cG : gG[CACHE ? 0 : q];
       float r[DIM];
 #pragma unroll
       for (int k = 0; k < DIM; ++k) r[k] = 0.0f;
@@ -444,7 +440,7 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
         float gV[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) gV[k] = 0.0f;
-        tp_adjoint_v<Pat>(G == 1 ? cM : Gm[G == 1 ? 0 : q], gT[q], gV, w, std::make_index_sequence<Pat::NNZ>{});
+        tp_adjoint_v<Pat>(Gm[q], gT[q], gV, w, std::make_index_sequence<Pat::NNZ>{});
         float ga[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
