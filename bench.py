@@ -38,11 +38,18 @@ MLP_KIND = {"twobody": 0, "latent": 1, "final": 2}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_protein_box.md")
 
 
+MLP_WAVES = 8                 # waves per MLP block
+TALL_ROWS = 128               # tile rows of the in-place (tall) MLP kernels
+
+
 def mlp_symbol(launch, precision, tile_rows, latent):
-    """'mlp_bwd_final', 1, 32, 256 -> 'k_mlp_bwd<1, 2, 32, 4>' (the kernel's name
-    without namespace and arguments; the last argument is ceil(d / 64))."""
+    """'mlp_bwd_final', 1, 32, 256 -> 'k_mlp_bwd<1, 2, 32, 2>' (the kernel's name
+    without namespace and arguments; the last argument is the column tiles per
+    wave, ceil(d / (16 * MLP_WAVES))); 128-row tiles -> 'k_mlp_bwd_t<1, 2, 2>'."""
     _, fb, kind = launch.split("_", 2)
-    ct = -(-(-(-latent // 16)) // 4)
+    ct = -(-(-(-latent // 16)) // MLP_WAVES)
+    if tile_rows == TALL_ROWS:
+        return f"k_mlp_{fb}_t<{precision}, {MLP_KIND[kind]}, {ct}>"
     return f"k_mlp_{fb}<{precision}, {MLP_KIND[kind]}, {tile_rows}, {ct}>"
 
 
@@ -232,8 +239,10 @@ def cpu_baseline(mc, s, w, n_centres):
     rng = np.random.default_rng(0)
     cents = np.sort(rng.choice(s.n_local, size=n_centres, replace=False))
     p = OM.Params(mc, w)
+    # in pieces of 512 centres, so that host memory stays at a few GB
     t0 = time.perf_counter()
-    OM.evaluate_centres(mc, w, s, cents, nbr, params=p)
+    for k in range(0, n_centres, 512):
+        OM.evaluate_centres(mc, w, s, cents[k:k + 512], nbr, params=p)
     t = time.perf_counter() - t0
     return {"value": n_centres / t, "unit": "atom-steps/s", "cores": int(torch.get_num_threads()),
             "kind": "oracle",
@@ -357,7 +366,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=384)
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="centres of the box in the oracle timing sample (about 10 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 and single-rounded BF16 comparisons")
     ap.add_argument("--workload", default="protein-box", choices=["protein-box", "subdomain", "clusters"],
