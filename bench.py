@@ -300,13 +300,11 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
             return m.neighbors(pos, sp, sysm.cell, sysm.pbc, nl)
         return m.neighbors_batched(sysm.atom_offsets, pos, sp)
 
-    tiles = None
     if kind == "subdomain":
         own = sysm.ghost_owner
         m.set_ghosts(nl, own, sysm.pos[nl:] - base.pos[own])
     build()
-    if kind == "clusters":
-        tiles = m.autotune(pos, sp)
+    tiles = m.autotune(pos, sp)   # edge-tile shapes for this system (a few evaluations)
     disp_max, edges = 0.0, []
     done = 0
     first = True
