@@ -504,15 +504,12 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int e0 = blockIdx.x * TM;
 
-  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
-  __syncthreads();
-  int ldin;
-  const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, nullptr, 0, &ldin, wave, lane);
-  const int nl = a.w.nl;
-  f32x4 acc[RT][MAXCT];
-  gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // N = d: one pass
-  // epilogue: x = u h (two-body) or rs (x_prev + u h) (latent), kept in acc.
-  // All loads are issued before the first store.
+  // The epilogue's per-row inputs (u, and the residual x_prev in this lane's
+  // fragment layout) are requested together with the input gather, so that
+  // their latency overlaps it instead of following the last GEMM -- except in
+  // the final layer's 32-row kernel, whose input build (the tensor-product
+  // scalars) leaves no registers for them under the two-blocks-per-CU limit.
+  constexpr bool kEarly = KIND == kLatent || TM >= 64;
   const int d = a.d;
   float ur[RT][4];
 #pragma unroll
@@ -522,8 +519,8 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
       const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
       ur[rt][i] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
     }
-  if constexpr (KIND != kTwoBody) {
-    float xp[RT][MAXCT][4];
+  float xp[RT][MAXCT][4];
+  auto load_xp = [&] {
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q) {
       int col = tile_of<MAXCT>(0, q, wave) * 16 + (lane & 15);
@@ -537,6 +534,18 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
           xp[rt][q][i] = a.x_prev[(uint32_t)e * d + col];
         }
     }
+  };
+  if constexpr (KIND != kTwoBody && kEarly) load_xp();
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  __syncthreads();
+  int ldin;
+  const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, nullptr, 0, &ldin, wave, lane);
+  const int nl = a.w.nl;
+  f32x4 acc[RT][MAXCT];
+  gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // N = d: one pass
+  // epilogue: x = u h (two-body) or rs (x_prev + u h) (latent), kept in acc
+  if constexpr (KIND != kTwoBody) {
+    if constexpr (!kEarly) load_xp();
 #pragma unroll
     for (int q = 0; q < MAXCT; ++q)
 #pragma unroll
@@ -673,19 +682,34 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
     us[threadIdx.x] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
   }
   f32x4 acc[RT][MAXCT];
+  bool input_ready = false;
   if (KIND != kLatentFinal && a.head_bwd.p != nullptr) {
-    // G += g_head @ W_head^T, K staged through X (in chunks of its width
-    // where X is narrower than the head)
-    const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5, chunk = ldx >> 5;
-    for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
-      const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
-      const int w = (kb1 - kb0) * 32;
-      stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, w);
+    // G += g_head @ W_head^T
+    const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5;
+    const int ldg = a.head_bwd.Kp + (PREC ? 8 : 4);
+    if (ldg <= nl * ldh) {
+      // the whole head gradient fits the H / pre-activation region (a
+      // [TM][ldg] view of it): stage it there while the chain's input rows
+      // gather into X, both in one memory round trip
+      stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, H, ldg, e0, 0, nkb * 32);
+      build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
       __syncthreads();
-      gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, kb0 == 0);
-      __syncthreads();
+      gemm_tile<PREC, RT, MAXCT>(acc, H, ldg, a.head_bwd, wave, lane, 0);
+      __syncthreads();   // H is rewritten by the recomputation
+      input_ready = true;
+    } else {
+      // K staged through X in chunks of its width
+      const int chunk = ldx >> 5;
+      for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
+        const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
+        const int w = (kb1 - kb0) * 32;
+        stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, w);
+        __syncthreads();
+        gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, kb0 == 0);
+        __syncthreads();
+      }
     }
-    // the K sum continues across chunks in the accumulators; G = g_x + sum
+    // (the K sum continues across chunks in the accumulators); G = g_x + sum
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -694,8 +718,10 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   mask_g();
 
   // 2. recompute the chain, keeping hidden pre-activations
-  build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
-  __syncthreads();
+  if (!input_ready) {
+    build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
+    __syncthreads();
+  }
   int ldin;
   const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, Pb, ldh, &ldin, wave, lane);
   gemm_tile<PREC, RT, MAXCT>(acc, in, ldin, a.w.fwd[nl - 1], wave, lane, 0);   // acc = h
@@ -1079,8 +1105,7 @@ template <int PREC>
 void lds_dims(const MlpArgs& a, int TM, bool bwd, int* ldx, int* ldh, size_t* bytes) {
   int kh = 32;                       // widths of hidden layers and of the output d
   for (int l = 0; l < a.w.nl; ++l) kh = kh > a.w.fwd[l].Np ? kh : a.w.fwd[l].Np;
-  int kx = kh > a.w.fwd[0].Kp ? kh : a.w.fwd[0].Kp;
-  if (bwd && a.head_bwd.p != nullptr && a.head_bwd.Kp > kx) kx = a.head_bwd.Kp;   // head staged in one piece
+  const int kx = kh > a.w.fwd[0].Kp ? kh : a.w.fwd[0].Kp;
   const int pad = PREC ? 8 : 4;
   *ldx = kx + pad;
   *ldh = kh + pad;
