@@ -33,9 +33,14 @@ def envelope(t: torch.Tensor, p: int = 6) -> torch.Tensor:
             - p * (p + 1) / 2.0 * t ** (p + 2))
 
 
-def bessel(d: torch.Tensor, r_cut: float, n_bessel: int) -> torch.Tensor:
-    """[E, n_bessel] Bessel basis B_n(d)."""
+def bessel(d: torch.Tensor, r_cut, n_bessel: int) -> torch.Tensor:
+    """[E, n_bessel] Bessel basis B_n(d); `r_cut` is one radius or one per
+    edge (per-ordered-species-pair cutoffs: each pair's basis is scaled to
+    its own cutoff)."""
     n = torch.arange(1, n_bessel + 1, dtype=d.dtype)
+    if isinstance(r_cut, torch.Tensor):
+        rc = r_cut[:, None]
+        return torch.sqrt(2.0 / rc) * torch.sin(n[None, :] * math.pi * d[:, None] / rc) / d[:, None]
     return math.sqrt(2.0 / r_cut) * torch.sin(n[None, :] * math.pi * d[:, None] / r_cut) / d[:, None]
 
 

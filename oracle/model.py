@@ -96,8 +96,14 @@ def edge_energies(p: Params, r: torch.Tensor, ci: torch.Tensor, zi: torch.Tensor
 
     d = torch.sqrt((r * r).sum(1))
     rhat = r / d[:, None]
-    u = basis.envelope(d / mc.r_cut, mc.envelope_p)
-    R = basis.bessel(d, mc.r_cut, mc.n_bessel) * u[:, None]
+    # cutoff of each edge: the global r_c, or its ordered species pair's own
+    # (section "Species-dependent cutoffs"); envelope and basis scale with it
+    if mc.pair_cutoffs is None:
+        rc = mc.r_cut
+    else:
+        rc = torch.as_tensor(np.asarray(mc.pair_cutoffs, dtype=np.float64))[zi, zj]
+    u = basis.envelope(d / rc, mc.envelope_p)
+    R = basis.bessel(d, rc, mc.n_bessel) * u[:, None]
     Y = basis.spherical_harmonics(rhat, lm)
 
     onehot = torch.zeros(E, 2 * S, dtype=torch.float64)
@@ -138,7 +144,8 @@ def evaluate(mc, weights, sysm, scale=None, shift=None, nbr=None, params=None,
     nl, nt = sysm.n_local, pos.shape[0]
     L = np.where(np.asarray(sysm.pbc) != 0, np.asarray(sysm.cell, dtype=np.float64), 0.0)
     if nbr is None:
-        nbr = neighbor_list(pos, sysm.cell, sysm.pbc, mc.r_cut, n_local=nl)
+        nbr = neighbor_list(pos, sysm.cell, sysm.pbc, mc.r_cut, n_local=nl, species=sysm.species,
+                            pair_cutoffs=mc.pair_cutoffs)
     i, j, s = nbr
     rp = row_ptr(i, nl)
     sig = np.ones(mc.n_species) if scale is None else np.asarray(scale, dtype=np.float64)

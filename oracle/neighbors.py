@@ -12,6 +12,10 @@ Distance test, fixed so that any implementation can reproduce it bit for bit:
   dx = (x_j - x_i) + s_x * L_x   (same for y, z; IEEE double, no fused ops)
   d2 = (dx*dx + dy*dy) + dz*dz
   keep iff d2 < r_c*r_c and not (i == j and s == 0).
+With per-ordered-species-pair cutoffs (section "Species-dependent cutoffs":
+an independent cutoff for each ordered pair, so that (Z_i, Z_j) and
+(Z_j, Z_i) may differ) r_c is rc[Z_i][Z_j] of the centre's and the
+neighbour's species; the global r_c then only bounds the search.
 The result is sorted by (i, j, s_x, s_y, s_z).
 """
 from __future__ import annotations
@@ -33,13 +37,16 @@ def _shift_ranges(dx0: np.ndarray, L: float, r_cut: float, periodic: bool):
     return lo, hi
 
 
-def _exact_test(pos, cell, i, j, s, r_cut):
+def _d2(pos, cell, i, j, s):
     L = np.where(np.asarray(cell) > 0, np.asarray(cell, dtype=np.float64), 0.0)
     dx = (pos[j, 0] - pos[i, 0]) + s[:, 0].astype(np.float64) * L[0]
     dy = (pos[j, 1] - pos[i, 1]) + s[:, 1].astype(np.float64) * L[1]
     dz = (pos[j, 2] - pos[i, 2]) + s[:, 2].astype(np.float64) * L[2]
-    d2 = (dx * dx + dy * dy) + dz * dz
-    keep = d2 < r_cut * r_cut
+    return (dx * dx + dy * dy) + dz * dz
+
+
+def _exact_test(pos, cell, i, j, s, r_cut):
+    keep = _d2(pos, cell, i, j, s) < r_cut * r_cut
     keep &= ~((i == j) & np.all(s == 0, axis=1))
     return keep
 
@@ -71,8 +78,11 @@ def _expand_candidates(pos, cell, pbc, r_cut, ci, cj):
     return rep_i[keep], rep_j[keep], s[keep]
 
 
-def neighbor_list(pos, cell, pbc, r_cut, n_local=None, method="auto"):
+def neighbor_list(pos, cell, pbc, r_cut, n_local=None, method="auto", species=None, pair_cutoffs=None):
     """Return (i, j, shift) int64 arrays, sorted by (i, j, sx, sy, sz).
+
+    `pair_cutoffs` (with `species`): [S][S] ordered cutoffs rc[Z_centre][Z_neighbour],
+    each at most r_cut; a pair is kept iff d2 < rc*rc for its own species pair.
 
     `method="brute"` tests every (i, j) atom pair with every image shift that
     can possibly be in range (the definition).  `method="kdtree"` only changes
@@ -124,6 +134,14 @@ def neighbor_list(pos, cell, pbc, r_cut, n_local=None, method="auto"):
         i, j, s = _expand_candidates(pos, cell, pbc, r_cut, ci[m], cj[m])
     else:
         raise ValueError(method)
+    if pair_cutoffs is not None:
+        rc = np.asarray(pair_cutoffs, dtype=np.float64)
+        if np.any(rc > r_cut) or np.any(rc <= 0):
+            raise ValueError("pair cutoffs must lie in (0, r_cut]")
+        Z = np.asarray(species, dtype=np.int64)
+        rcp = rc[Z[i], Z[j]]
+        keep = _d2(pos, cell, i, j, s) < rcp * rcp
+        i, j, s = i[keep], j[keep], s[keep]
     order = np.lexsort((s[:, 2], s[:, 1], s[:, 0], j, i))
     return i[order], j[order], s[order]
 

@@ -42,7 +42,8 @@ def _sh(v):
 def energy(mc, w, sysm):
     pos, Z = np.asarray(sysm.pos), np.asarray(sysm.species)
     L = np.where(np.asarray(sysm.pbc) != 0, np.asarray(sysm.cell, dtype=float), 0.0)
-    I, J, S = neighbor_list(pos, sysm.cell, sysm.pbc, mc.r_cut, n_local=sysm.n_local)
+    I, J, S = neighbor_list(pos, sysm.cell, sysm.pbc, mc.r_cut, n_local=sysm.n_local, species=Z,
+                            pair_cutoffs=mc.pair_cutoffs)
     n, lm, nS = mc.n_tensor, mc.l_max, mc.n_species
     dim = (lm + 1) ** 2
     lof = [l for l in range(lm + 1) for _ in range(2 * l + 1)]
@@ -51,9 +52,10 @@ def energy(mc, w, sysm):
     for (i, j, s) in zip(I.tolist(), J.tolist(), S.tolist()):
         r = [(pos[j, a] - pos[i, a]) + s[a] * L[a] for a in range(3)]
         d = math.sqrt(sum(c * c for c in r))
-        t, p = d / mc.r_cut, mc.envelope_p
+        rc = mc.r_cut if mc.pair_cutoffs is None else mc.pair_cutoffs[Z[i]][Z[j]]
+        t, p = d / rc, mc.envelope_p
         u = 1 - (p + 1) * (p + 2) / 2 * t ** p + p * (p + 2) * t ** (p + 1) - p * (p + 1) / 2 * t ** (p + 2)
-        Rb = [math.sqrt(2 / mc.r_cut) * math.sin(k * math.pi * d / mc.r_cut) / d * u
+        Rb = [math.sqrt(2 / rc) * math.sin(k * math.pi * d / rc) / d * u
               for k in range(1, mc.n_bessel + 1)]
         Y = _sh([c / d for c in r])[:dim]
         inp = [0.0] * (2 * nS)

@@ -8,6 +8,8 @@ permutation invariance; zero net force; virial against strained energies;
 strict locality (section "Allegro: Scalable Equivariant Deep Learning"); a
 ghost-shell box reproducing the periodic box; the pair-potential limit when
 every path weight is zero; continuity at the cutoff; NVE energy conservation.
+Per-ordered-species-pair cutoffs (section "Species-dependent cutoffs") get the
+loop form, finite differences and continuity at each pair's own cutoff.
 """
 import copy
 import math
@@ -275,3 +277,57 @@ def test_nve_energy_conservation_scales_dt2():
     ratio = fl[0] / fl[1]
     assert 3.0 < ratio < 5.0, (fl, ratio)
     assert fl[1] < 1e-3
+
+
+PAIR_TABLE = ((2.2, 1.3), (2.6, 3.0))   # ordered [Z_centre][Z_neighbour], r_cut 3.0
+
+
+def pair_model():
+    mc = tiny_model(2, 2, n=4, d=8, rc=3.0)
+    mc.pair_cutoffs = PAIR_TABLE
+    return mc
+
+
+def test_pair_cutoffs_loop_form():
+    mc = pair_model()
+    w = weights(mc, 31)
+    s = cluster(10, 7)
+    ref = oracle_loops.energy(mc, w, s)
+    got = model.evaluate(mc, w, s).edge_energy
+    assert ref.shape == got.shape and len(ref) > 10
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-13)
+    # fewer edges than with the single cutoff, and a different energy
+    full = model.evaluate(tiny_model(2, 2, n=4, d=8, rc=3.0), w, s)
+    assert len(full.edge_energy) > len(got)
+
+
+def test_pair_cutoffs_forces_finite_difference():
+    mc = pair_model()
+    w = weights(mc, 32)
+    s = cluster(14, 9)
+    _fd_check(mc, w, s, [(a, ax) for a in (1, 6, 12) for ax in range(3)])
+
+
+def test_continuity_at_pair_cutoff():
+    """Moving a species-1 neighbour of a species-0 centre across that ordered
+    pair's cutoff (1.3 A) changes the energy by O(h^3): every contribution of
+    the edge carries the envelope u, which vanishes there with its first two
+    derivatives; the reverse edge (cutoff 2.6 A) stays in the list."""
+    mc = pair_model()
+    w = weights(mc, 33)
+    base = np.array([[0.0, 0.0, 0.0], [1.9, 0.6, 0.0], [0.4, -1.8, 0.5]])
+    sp = np.array([0, 0, 1], dtype=np.int32)
+
+    def E(xd, table):
+        m = copy.copy(mc)
+        m.pair_cutoffs = table
+        pos = np.concatenate([base, [[-xd, 0.0, 0.0]]])
+        s = W.System(pos=pos, species=np.concatenate([sp, [1]]).astype(np.int32), cell=np.zeros(3),
+                     pbc=np.zeros(3, np.int32), n_local=4)
+        return model.evaluate(m, w, s).energy
+
+    without = ((2.2, 1.0), (2.6, 3.0))    # the same system with the 0 -> 1 pair below 1.0 A
+    diffs = [E(1.3 - h, PAIR_TABLE) - E(1.3 - h, without) for h in (2e-2, 4e-3)]
+    assert abs(diffs[1]) < 50 * 4e-3 ** 3
+    assert abs(diffs[0] / diffs[1]) > 60       # cubic: (2e-2 / 4e-3)^3 = 125
+    assert abs(E(1.0, PAIR_TABLE) - E(1.0, without)) > 1e-6

@@ -3,7 +3,9 @@
 The list is defined by exhaustive search (section "Allegro: Scalable
 Equivariant Deep Learning": ordered pairs within the cutoff).  It is checked
 against scipy's k-d tree (an independent library search), closed-form image
-counts, the ordered-pair symmetry and the strict cutoff tie rule.
+counts, the ordered-pair symmetry and the strict cutoff tie rule.  The
+per-ordered-species-pair cutoffs (section "Species-dependent cutoffs") are
+checked against a pure-Python loop over every atom pair and image.
 """
 import numpy as np
 import pytest
@@ -95,3 +97,66 @@ def test_ghost_shell_list_matches_periodic():
     own = np.concatenate([np.arange(s.n_local), g.ghost_owner])
     assert np.array_equal(i0, i1) or sorted(zip(i0, own[j1])) == sorted(zip(i0, j0))
     assert sorted(zip(i1.tolist(), own[j1].tolist())) == sorted(zip(i0.tolist(), j0.tolist()))
+
+
+def _loop_pairs(pos, cell, pbc, Z, table, r_max):
+    """The definition, written out: every (i, j, image) with
+    d2 < rc[Z_i][Z_j]^2 (d2 summed in the order the list fixes)."""
+    n = len(pos)
+    rng = [range(-(int(r_max // cell[a]) + 1), int(r_max // cell[a]) + 2) if pbc[a] else range(0, 1)
+           for a in range(3)]
+    out = set()
+    for i in range(n):
+        for j in range(n):
+            rc = table[Z[i]][Z[j]]
+            for sx in rng[0]:
+                for sy in rng[1]:
+                    for sz in rng[2]:
+                        if i == j and sx == 0 and sy == 0 and sz == 0:
+                            continue
+                        dx = (pos[j][0] - pos[i][0]) + sx * cell[0]
+                        dy = (pos[j][1] - pos[i][1]) + sy * cell[1]
+                        dz = (pos[j][2] - pos[i][2]) + sz * cell[2]
+                        if (dx * dx + dy * dy) + dz * dz < rc * rc:
+                            out.add((i, j, (sx, sy, sz)))
+    return out
+
+
+def _water_like(n_side, spacing, seed):
+    return W.jittered_lattice_box(n_side ** 3, n_side * spacing, 0.4, W.WATER_MIX, seed, sites_per_side=n_side)
+
+
+def test_pair_cutoffs_match_loop_definition():
+    s = _water_like(3, 2.9, 21)           # 27 atoms, 8.7 A box (< 2 r_c: several images)
+    table = W.paper_pair_cutoffs(2, 4.0)   # H-H 3.0, H-O 1.25, O-H 3.0, O-O 4.0
+    i, j, sh = neighbor_list(s.pos, s.cell, s.pbc, 4.0, species=s.species, pair_cutoffs=table)
+    ref = _loop_pairs(s.pos.tolist(), [float(c) for c in s.cell], s.pbc, s.species.tolist(), table, 4.0)
+    assert _as_set(i, j, sh) == ref and len(ref) == len(i) > 0
+    full = neighbor_list(s.pos, s.cell, s.pbc, 4.0)
+    assert len(i) < 0.7 * len(full[0])     # far fewer ordered pairs than with one 4 A cutoff
+
+
+def test_pair_cutoffs_equal_to_r_cut_change_nothing():
+    s = _water_like(4, 3.1, 5)
+    a = neighbor_list(s.pos, s.cell, s.pbc, 4.0)
+    b = neighbor_list(s.pos, s.cell, s.pbc, 4.0, species=s.species, pair_cutoffs=[[4.0, 4.0], [4.0, 4.0]])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_pair_cutoffs_are_ordered():
+    s = _water_like(4, 3.1, 8)
+    table = W.paper_pair_cutoffs(2, 4.0)
+    i, j, sh = neighbor_list(s.pos, s.cell, s.pbc, 4.0, species=s.species, pair_cutoffs=table)
+    L = np.asarray(s.cell, dtype=np.float64)
+    d = np.linalg.norm(s.pos[j] - s.pos[i] + sh * L, axis=1)
+    Z = s.species
+    h_o = (Z[i] == 0) & (Z[j] == 1)
+    o_h = (Z[i] == 1) & (Z[j] == 0)
+    assert np.all(d[h_o] < 1.25) and np.all(d[o_h] < 3.0)
+    # O-H pairs between 1.25 and 3 A are kept from the O side only
+    kept = _as_set(i, j, sh)
+    one_sided = [(a, b, c) for (a, b, c), dd in zip(zip(i.tolist(), j.tolist(), map(tuple, sh.tolist())), d)
+                 if Z[a] == 1 and Z[b] == 0 and dd >= 1.25]
+    assert one_sided
+    assert all((b, a, tuple(-x for x in c)) not in kept for (a, b, c) in one_sided)

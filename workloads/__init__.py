@@ -27,6 +27,17 @@ DENSITY = 0.1  # atoms / A^3, liquid-water number density
 MASSES_4 = (1.008, 12.011, 14.007, 15.999)
 MASSES_2 = (1.008, 15.999)
 
+# Ordered-pair cutoffs the paper used (section "Training details"): H-H 3.0,
+# H-C 1.25, H-O 1.25, O-H 3.0 A, every other ordered pair the default cutoff.
+PAPER_PAIR_CUTOFFS = {("H", "H"): 3.0, ("H", "C"): 1.25, ("H", "O"): 1.25, ("O", "H"): 3.0}
+
+
+def paper_pair_cutoffs(n_species: int, r_cut: float):
+    """[S][S] table of those cutoffs for the 2-species (H, O) or 4-species
+    (H, C, N, O) mixes used here; pairs the paper does not list get r_cut."""
+    names = ("H", "O") if n_species == 2 else ("H", "C", "N", "O")
+    return tuple(tuple(min(r_cut, PAPER_PAIR_CUTOFFS.get((a, b), r_cut)) for b in names) for a in names)
+
 
 @dataclasses.dataclass
 class ModelConfig:
@@ -43,6 +54,9 @@ class ModelConfig:
     edge_dims: Sequence[int] = (128,)
     avg_num_neighbors: Optional[float] = None
     channel_mix: bool = True
+    # ordered per-species-pair cutoffs rc[Z_centre][Z_neighbour] (A), each at
+    # most r_cut; None = r_cut for every pair
+    pair_cutoffs: Optional[Sequence[Sequence[float]]] = None
 
     def __post_init__(self):
         self.twobody_dims = tuple(int(v) for v in self.twobody_dims)
@@ -50,6 +64,10 @@ class ModelConfig:
         self.edge_dims = tuple(int(v) for v in self.edge_dims)
         if self.avg_num_neighbors is None:
             self.avg_num_neighbors = DENSITY * 4.0 / 3.0 * math.pi * self.r_cut ** 3
+        if self.pair_cutoffs is not None:
+            self.pair_cutoffs = tuple(tuple(float(v) for v in row) for row in self.pair_cutoffs)
+            if len(self.pair_cutoffs) != self.n_species or any(len(r) != self.n_species for r in self.pair_cutoffs):
+                raise ValueError("pair_cutoffs must be n_species x n_species")
 
     @property
     def latent(self) -> int:
