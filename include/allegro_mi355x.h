@@ -96,6 +96,14 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *                    be reused over several MD steps; pairs beyond r_cut carry
  *                    a zero envelope and contribute exactly zero.  0 = the list
  *                    holds exactly the pairs inside r_cut.
+ *   r_cut_pair       host [n_species][n_species] cutoffs of ordered species pairs
+ *                    (A), row = species of the centre, column = species of the
+ *                    neighbour, each in (0, r_cut]; or NULL = r_cut for every
+ *                    pair (section "Species-dependent cutoffs": a pair (i, j) is
+ *                    a neighbour iff d_ij < r_cut_pair[Z_i][Z_j], and its radial
+ *                    basis and envelope are scaled to that cutoff).  Read by
+ *                    allegro_describe / allegro_create and copied; the skin is
+ *                    added to every pair's radius.
  * MLP widths must be multiples of 16 and at most 512; the latent width d at most 256.
  */
 typedef struct {
@@ -108,6 +116,7 @@ typedef struct {
   int32_t precision;
   int64_t edge_chunk;
   double neighbor_skin;
+  const double* r_cut_pair;
 } AllegroConfig;
 
 /* Host-side description of a configuration (no device work). */

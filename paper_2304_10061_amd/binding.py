@@ -38,7 +38,8 @@ class AllegroConfig(ctypes.Structure):
                 ("edge_dims", ctypes.c_int32 * 4), ("n_edge", ctypes.c_int32),
                 ("r_cut", ctypes.c_double), ("avg_num_neighbors", ctypes.c_double),
                 ("channel_mix", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("edge_chunk", ctypes.c_int64), ("neighbor_skin", ctypes.c_double)]
+                ("edge_chunk", ctypes.c_int64), ("neighbor_skin", ctypes.c_double),
+                ("r_cut_pair", ctypes.POINTER(ctypes.c_double))]
 
 
 class AllegroInfo(ctypes.Structure):
@@ -111,7 +112,9 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
                 n_layers: int = 2, n_tensor: int = 32, twobody_dims: Sequence[int] = (128, 128),
                 latent_dims: Sequence[int] = (128, 128), edge_dims: Sequence[int] = (128,),
                 avg_num_neighbors: Optional[float] = None, channel_mix: bool = True,
-                precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0) -> AllegroConfig:
+                precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0,
+                r_cut_pair=None) -> AllegroConfig:
+    """r_cut_pair: optional [n_species][n_species] ordered cutoffs (row = centre species)."""
     c = AllegroConfig()
     c.n_species, c.n_bessel, c.envelope_p, c.l_max = n_species, n_bessel, envelope_p, l_max
     c.n_layers, c.n_tensor = n_layers, n_tensor
@@ -129,6 +132,13 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
     c.precision = int(precision)
     c.edge_chunk = int(edge_chunk)
     c.neighbor_skin = float(neighbor_skin)
+    if r_cut_pair is not None:
+        flat = [float(v) for row in r_cut_pair for v in row]
+        if len(flat) != n_species * n_species:
+            raise ValueError("r_cut_pair must be n_species x n_species")
+        table = (ctypes.c_double * len(flat))(*flat)
+        c.r_cut_pair = ctypes.cast(table, ctypes.POINTER(ctypes.c_double))
+        c._r_cut_pair_table = table   # kept alive with the config; the library copies it
     return c
 
 
@@ -138,7 +148,8 @@ def config_from(mc, precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_sk
                        l_max=mc.l_max, n_layers=mc.n_layers, n_tensor=mc.n_tensor,
                        twobody_dims=mc.twobody_dims, latent_dims=mc.latent_dims, edge_dims=mc.edge_dims,
                        avg_num_neighbors=mc.avg_num_neighbors, channel_mix=mc.channel_mix,
-                       precision=precision, edge_chunk=edge_chunk, neighbor_skin=neighbor_skin)
+                       precision=precision, edge_chunk=edge_chunk, neighbor_skin=neighbor_skin,
+                       r_cut_pair=getattr(mc, "pair_cutoffs", None))
 
 
 def describe(cfg: AllegroConfig) -> AllegroInfo:

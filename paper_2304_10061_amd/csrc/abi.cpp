@@ -162,6 +162,10 @@ Validated validate(const AllegroConfig* c) {
           "precision must be 0, 1, 2 or 3");
   REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
   REQUIRE(c->neighbor_skin >= 0 && std::isfinite(c->neighbor_skin), "neighbor_skin must be >= 0");
+  if (c->r_cut_pair)
+    for (int k = 0; k < v.S * v.S; ++k)
+      REQUIRE(std::isfinite(c->r_cut_pair[k]) && c->r_cut_pair[k] > 0 && c->r_cut_pair[k] <= c->r_cut,
+              "r_cut_pair entries must lie in (0, r_cut]");
   v.dim = (v.lmax + 1) * (v.lmax + 1);
   v.LW = (v.lmax + 1) * v.n;
   // weight count, in the documented order
@@ -252,6 +256,10 @@ struct AllegroModel {
 
   Mlp twobody, latent[2];
   PackedMat head0, head0T, env2, env2T;   // [embed0 | env1] and env2
+  // ordered species-pair cutoffs (empty = r_cut for every pair): the host
+  // copy, FP32 radii for the edge kernels, squared list radii for the list
+  std::vector<double> rc_pair;
+  DevBuf rc_pair_f, rc2_pair;
   DevBuf mixF[2], mixB[2];                // packed FP32 mixing matrices per layer
   int mix_stride = 0;
   DevBuf tpw[2];                          // fused coupling non-zeros per layer
@@ -336,6 +344,17 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   for (int64_t k = 0; k < n_weights; ++k) REQUIRE(std::isfinite(w[k]), "weights contain non-finite values");
   HIP_OK(hipGetDevice(&m->device));
   const int n = v.n, d = v.d, LW = v.LW, L1 = v.lmax + 1;
+  if (!m->rc_pair.empty()) {
+    std::vector<float> rf(m->rc_pair.size());
+    std::vector<double> r2(m->rc_pair.size());
+    for (size_t k = 0; k < rf.size(); ++k) {
+      rf[k] = (float)m->rc_pair[k];
+      const double rl = m->rc_pair[k] + m->cfg.neighbor_skin;   // list radius of the pair
+      r2[k] = rl * rl;
+    }
+    upload(m->rc_pair_f, rf.data(), rf.size() * sizeof(float));
+    upload(m->rc2_pair, r2.data(), r2.size() * sizeof(double));
+  }
   int64_t off = 0;
   // two-body MLP
   std::vector<int> dims{2 * v.S + v.nb};
@@ -536,6 +555,7 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   NbrArgs a;
   a.n_local = n_local; a.n_total = n_total; a.pos = pos; a.r_cut2 = rc * rc;
   a.species = species; a.n_species = m->v.S;
+  a.rc2_pair = m->rc_pair.empty() ? nullptr : ptr<double>(m->rc2_pair);
   for (int ax = 0; ax < 3; ++ax) { a.L[ax] = L[ax]; a.pbc[ax] = pb[ax]; }
   const int64_t nt = std::max<int64_t>(n_total, 1);
   // bounding box of the open axes
@@ -735,6 +755,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     ea.E = E; ea.pos = pos; ea.ei = ei + eA; ea.ej = ej + eA; ea.es = es + 3 * eA; ea.species = species;
     for (int ax = 0; ax < 3; ++ax) ea.L[ax] = m->L[ax];
     ea.r_cut = m->cfg.r_cut; ea.p = v.p; ea.n_bessel = v.nb; ea.l_max = v.lmax;
+    ea.rc_pair = m->rc_pair.empty() ? nullptr : ptr<float>(m->rc_pair_f); ea.n_species = v.S;
     ea.eb = ptr<float>(m->eb);
     timed(m, "edge_basis", s, [&] { return launch_edge_basis(ea, s); });
 
@@ -1113,6 +1134,8 @@ int allegro_create(const AllegroConfig* cfg, const float* weights, int64_t n_wei
     m->cfg = *cfg;
     m->v = v;
     m->prec = cfg->precision;
+    if (cfg->r_cut_pair) m->rc_pair.assign(cfg->r_cut_pair, cfg->r_cut_pair + v.S * v.S);
+    m->cfg.r_cut_pair = nullptr;   // the caller's table is not kept
     switch (m->prec) {
       case ALLEGRO_PREC_FP32: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 0; break;
       case ALLEGRO_PREC_BF16: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 1; break;

@@ -59,7 +59,10 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
   const double dd = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
   const float d = (float)dd;
   const float x = (float)(r[0] / dd), y = (float)(r[1] / dd), z = (float)(r[2] / dd);
-  const float rc = (float)a.r_cut;
+  // species of the ordered pair (clamped into the table) and its cutoff
+  const int S = a.n_species;
+  const int zi = min(max(a.species[a.ei[e]], 0), S - 1), zj = min(max(a.species[a.ej[e]], 0), S - 1);
+  const float rc = a.rc_pair ? a.rc_pair[zi * S + zj] : (float)a.r_cut;
   const float t = d / rc;
   const int p = a.p;
   const float tp = ipow(t, p);
@@ -75,8 +78,8 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
   o[kEB_U] = u;
   o[kEB_D] = d;
   o[kEB_RHAT] = x; o[kEB_RHAT + 1] = y; o[kEB_RHAT + 2] = z;
-  o[kEB_ZI] = (float)a.species[a.ei[e]];
-  o[kEB_ZJ] = (float)a.species[a.ej[e]];
+  o[kEB_ZI] = (float)zi;
+  o[kEB_ZJ] = (float)zj;
   const float pref = sqrtf(2.0f / rc);
   for (int k = 0; k < 16; ++k) {
     float v = 0.0f;
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
   const float* o = a.eb + e * kEB;
   const float d = o[kEB_D], u = o[kEB_U];
   const float x = o[kEB_RHAT], y = o[kEB_RHAT + 1], z = o[kEB_RHAT + 2];
-  const float rc = (float)a.r_cut;
+  const float rc = a.rc_pair ? a.rc_pair[(int)o[kEB_ZI] * a.n_species + (int)o[kEB_ZJ]] : (float)a.r_cut;
   const float t = d / rc;
   const int p = a.p;
   // du/dd = -(p(p+1)(p+2)/2) t^(p-1) (1-t)^2 / r_c

@@ -106,6 +106,8 @@ struct EdgeArgs {
   const int32_t* species = nullptr;  // [n_total]
   double L[3] = {0, 0, 0};        // periodic lengths (0 = open axis)
   double r_cut = 0;
+  const float* rc_pair = nullptr; // [S][S] cutoff of each ordered species pair, or null (r_cut)
+  int n_species = 1;
   int p = 6, n_bessel = 8, l_max = 2;
   float* eb = nullptr;
   // backward
@@ -208,6 +210,7 @@ struct NbrArgs {
   int nc[3] = {1, 1, 1};          // cells per axis
   int R[3] = {1, 1, 1};           // stencil half-width per axis
   double r_cut2 = 0;
+  const double* rc2_pair = nullptr;  // [S][S] squared list radius of each ordered species pair, or null (r_cut2)
   int32_t* cell_of = nullptr;     // [n_total]
   int32_t* img = nullptr;         // [n_total][3] image index q (x = x_wrapped + q L)
   int32_t* cell_count = nullptr;  // [n_cells]

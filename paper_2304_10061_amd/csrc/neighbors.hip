@@ -108,6 +108,11 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
   const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= a.n_local) return;
   const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
+  // row of the centre's species in the ordered-pair radius table (species
+  // are clamped: this pass may run before the host has seen their check)
+  const int S = a.n_species;
+  const int zc = min(max(a.species[i], 0), S - 1);
+  const double* rc2_row = a.rc2_pair ? a.rc2_pair + zc * S : nullptr;
   const int ci = a.cell_of[i];
   const int cc[3] = {ci / (a.nc[1] * a.nc[2]), (ci / a.nc[2]) % a.nc[1], ci % a.nc[2]};
   const int qi[3] = {a.img[3 * i], a.img[3 * i + 1], a.img[3 * i + 2]};
@@ -168,7 +173,8 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
         const double dy = __dadd_rn(__dsub_rn(a.pos[3 * j + 1], yi), __dmul_rn((double)sy, a.L[1]));
         const double dz = __dadd_rn(__dsub_rn(a.pos[3 * j + 2], zi), __dmul_rn((double)sz, a.L[2]));
         const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-        hit = same_sys && d2 < a.r_cut2 && !(j == i && sx == 0 && sy == 0 && sz == 0);
+        const double rc2 = rc2_row ? rc2_row[min(max(a.species[j], 0), S - 1)] : a.r_cut2;
+        hit = same_sys && d2 < rc2 && !(j == i && sx == 0 && sy == 0 && sz == 0);
       }
       if (WRITE) {
         const unsigned long long mask = __ballot(hit);

@@ -46,7 +46,10 @@ def test_describe_matches_oracle(cfg):
 
 @pytest.mark.parametrize("bad", [dict(l_max=3), dict(n_layers=3), dict(n_tensor=24), dict(n_species=20),
                                  dict(twobody_dims=(100, 100), latent_dims=(100, 100)),
-                                 dict(latent_dims=(64, 32)), dict(edge_dims=(64, 64)), dict(r_cut=-1.0)])
+                                 dict(latent_dims=(64, 32)), dict(edge_dims=(64, 64)), dict(r_cut=-1.0),
+                                 dict(r_cut_pair=((3.0, 4.5), (3.0, 4.0))),      # above r_cut
+                                 dict(r_cut_pair=((3.0, 0.0), (3.0, 4.0))),      # not positive
+                                 dict(r_cut_pair=((3.0, float("nan")), (3.0, 4.0)))])
 def test_describe_rejects_unsupported(bad):
     kw = dict(n_species=2, r_cut=4.0, l_max=2, n_layers=2, n_tensor=32, twobody_dims=(64, 64),
               latent_dims=(64, 64), edge_dims=(32,))
@@ -68,3 +71,13 @@ def test_create_rejects_wrong_weight_count_without_device_work():
     assert lib.allegro_status_string(-3) == b"ALLEGRO_E_CAPACITY"
     assert lib.allegro_num_edges(None) == -1
     lib.allegro_destroy(None)
+
+
+def test_describe_accepts_pair_cutoffs():
+    kw = dict(n_species=2, r_cut=4.0, l_max=2, n_layers=2, n_tensor=32, twobody_dims=(64, 64),
+              latent_dims=(64, 64), edge_dims=(32,))
+    a = P.describe(P.make_config(**kw))
+    b = P.describe(P.make_config(r_cut_pair=W.paper_pair_cutoffs(2, 4.0), **kw))
+    assert a.n_weights == b.n_weights
+    with pytest.raises(ValueError):
+        P.make_config(r_cut_pair=((3.0, 4.0),), **kw)
