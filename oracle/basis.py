@@ -67,3 +67,22 @@ def spherical_harmonics_np(rhat: np.ndarray, l_max: int) -> np.ndarray:
 def irrep_of_component(l_max: int):
     """l of each component index c = l^2 + (m + l)."""
     return [l for l in range(l_max + 1) for _ in range(2 * l + 1)]
+
+
+# Ziegler-Biersack-Littmark universal screened Coulomb repulsion (the "ZBL
+# term" the paper adds for stability, section "Training details"; the form and
+# constants are those of the ZBL universal potential): k_e = e^2 / (4 pi eps0)
+# in eV A, screening length a = 0.8854 a_0 / (Z_i^0.23 + Z_j^0.23), and the
+# universal screening function phi as four exponentials with phi(0) = 1.
+ZBL_KE = 14.399645
+ZBL_A0 = 0.46850
+ZBL_C = (0.18175, 0.50986, 0.28022, 0.02817)
+ZBL_D = (3.19980, 0.94229, 0.40290, 0.20162)
+
+
+def zbl_energy(d: torch.Tensor, zn_i: torch.Tensor, zn_j: torch.Tensor) -> torch.Tensor:
+    """ZBL pair energy (eV) at distances d for atomic numbers zn_i, zn_j."""
+    a = ZBL_A0 / (zn_i ** 0.23 + zn_j ** 0.23)
+    x = d / a
+    phi = sum(c * torch.exp(-k * x) for c, k in zip(ZBL_C, ZBL_D))
+    return ZBL_KE * zn_i * zn_j / d * phi

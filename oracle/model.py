@@ -130,6 +130,23 @@ def edge_energies(p: Params, r: torch.Tensor, ci: torch.Tensor, zi: torch.Tensor
     return (x @ p.edge[0] @ p.edge[1] if len(p.edge) == 2 else _mlp_linear(x, p.edge)).view(E)
 
 
+def pair_energies(mc, r: torch.Tensor, zi: torch.Tensor, zj: torch.Tensor) -> torch.Tensor:
+    """Per-ordered-edge share of the ZBL repulsion, 1/2 E_ZBL(d) u(d / r_c,ij):
+    each pair counts in full when both of its ordered edges are in the list,
+    and the envelope of the edge takes it smoothly to zero at that edge's
+    cutoff.  Zero when the model has no atomic numbers (no ZBL term)."""
+    if getattr(mc, "atomic_numbers", None) is None:
+        return torch.zeros(r.shape[0], dtype=torch.float64)
+    d = torch.sqrt((r * r).sum(1))
+    if mc.pair_cutoffs is None:
+        rc = mc.r_cut
+    else:
+        rc = torch.as_tensor(np.asarray(mc.pair_cutoffs, dtype=np.float64))[zi, zj]
+    zn = torch.as_tensor(np.asarray(mc.atomic_numbers, dtype=np.float64))
+    u = basis.envelope(d / rc, mc.envelope_p)
+    return 0.5 * basis.zbl_energy(d, zn[zi], zn[zj]) * u
+
+
 def _mlp_linear(x, Ws):
     for W in Ws:
         x = x @ W
@@ -155,6 +172,7 @@ def evaluate(mc, weights, sysm, scale=None, shift=None, nbr=None, params=None,
     rvec = (pos[j] - pos[i]) + s.astype(np.float64) * L[None, :]
     E = rvec.shape[0]
     edge_e = np.zeros(E)
+    edge_z = np.zeros(E)
     edge_g = np.zeros((E, 3))
     atom_e_raw = np.zeros(nl)
     # chunks of whole centre segments
@@ -167,16 +185,21 @@ def evaluate(mc, weights, sysm, scale=None, shift=None, nbr=None, params=None,
         if e1 > e0:
             r = torch.tensor(rvec[e0:e1], requires_grad=True)
             ci = torch.as_tensor(i[e0:e1] - a)
-            eij = edge_energies(p, r, ci, torch.as_tensor(Z[i[e0:e1]]), torch.as_tensor(Z[j[e0:e1]]), b - a)
-            # dE/dE_ij = sigma_{Z_i}
+            zi_t, zj_t = torch.as_tensor(Z[i[e0:e1]]), torch.as_tensor(Z[j[e0:e1]])
+            eij = edge_energies(p, r, ci, zi_t, zj_t, b - a)
+            ez = pair_energies(mc, r, zi_t, zj_t)
+            # dE/dE_ij = sigma_{Z_i}; the pair term is added unscaled
             w = torch.as_tensor(sig[Z[i[e0:e1]]])
-            tot = (eij * w).sum()
+            tot = (eij * w).sum() + ez.sum()
             (g,) = torch.autograd.grad(tot, r)
             edge_e[e0:e1] = eij.detach().numpy()
+            edge_z[e0:e1] = ez.detach().numpy()
             edge_g[e0:e1] = g.numpy()
         a = b
     np.add.at(atom_e_raw, i, edge_e)
-    atom_e = sig[Z[:nl]] * atom_e_raw + mu[Z[:nl]]
+    atom_z = np.zeros(nl)
+    np.add.at(atom_z, i, edge_z)
+    atom_e = sig[Z[:nl]] * atom_e_raw + mu[Z[:nl]] + atom_z
     energy = float(atom_e.sum())
     F = np.zeros((nt, 3))
     np.add.at(F, i, edge_g)
@@ -207,6 +230,8 @@ def evaluate_centres(mc, weights, sysm, centres, nbr, scale=None, params=None):
     subset is evaluated exactly like the whole system restricted to those
     segments.  Returns (atom_energy[len(centres)], {edge index: dE/dr_e}).
     """
+    if getattr(mc, "atomic_numbers", None) is not None:
+        raise NotImplementedError("evaluate_centres returns network energies only (no ZBL term)")
     p = params or Params(mc, weights)
     pos = np.asarray(sysm.pos, dtype=np.float64)
     L = np.where(np.asarray(sysm.pbc) != 0, np.asarray(sysm.cell, dtype=np.float64), 0.0)

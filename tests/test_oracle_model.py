@@ -9,7 +9,11 @@ strict locality (section "Allegro: Scalable Equivariant Deep Learning"); a
 ghost-shell box reproducing the periodic box; the pair-potential limit when
 every path weight is zero; continuity at the cutoff; NVE energy conservation.
 Per-ordered-species-pair cutoffs (section "Species-dependent cutoffs") get the
-loop form, finite differences and continuity at each pair's own cutoff.
+loop form, finite differences and continuity at each pair's own cutoff.  The
+ZBL repulsion (section "Training details") is pinned by its Coulomb limit
+(the screening function is 1 at zero separation), the dimer with a silent
+network, finite differences, continuity at the cutoff and its symmetry; its
+published constants themselves have no printed value to compare with here.
 """
 import copy
 import math
@@ -331,3 +335,72 @@ def test_continuity_at_pair_cutoff():
     assert abs(diffs[1]) < 50 * 4e-3 ** 3
     assert abs(diffs[0] / diffs[1]) > 60       # cubic: (2e-2 / 4e-3)^3 = 125
     assert abs(E(1.0, PAIR_TABLE) - E(1.0, without)) > 1e-6
+
+
+def zbl_model(S=2, pairs=False):
+    mc = tiny_model(2, 2, n=4, d=8, S=S, rc=3.0)
+    mc.atomic_numbers = (1, 8) if S == 2 else (1, 6, 7, 8)
+    if pairs:
+        mc.pair_cutoffs = PAIR_TABLE
+    return mc
+
+
+def test_zbl_coulomb_limit_and_repulsion():
+    import torch
+    from oracle import basis
+    d = torch.tensor([1e-5, 1e-4, 0.3, 0.6, 1.2, 2.4], dtype=torch.float64)
+    for zi, zj in ((1.0, 1.0), (1.0, 8.0), (8.0, 8.0), (6.0, 7.0)):
+        e = basis.zbl_energy(d, torch.tensor(zi, dtype=torch.float64), torch.tensor(zj, dtype=torch.float64))
+        coul = 14.399645 * zi * zj / d
+        assert abs(float(e[0] / coul[0]) - 1.0) < 1e-3          # screening -> 1 as r -> 0
+        assert torch.all(e > 0) and torch.all(e[1:] < e[:-1])   # repulsive, decreasing
+        assert torch.all(e <= coul)                             # screened below bare Coulomb
+        e2 = basis.zbl_energy(d, torch.tensor(zj, dtype=torch.float64), torch.tensor(zi, dtype=torch.float64))
+        assert torch.allclose(e, e2, rtol=1e-15, atol=0)
+
+
+def test_zbl_dimer_with_silent_network():
+    """With all network weights zero only the ZBL term remains: the dimer's
+    energy is the pair energy times the envelope (two ordered halves), and
+    the force is minus its radial derivative (central difference)."""
+    import torch
+    from oracle import basis
+    mc = zbl_model()
+    w = {k: np.zeros_like(v) for k, v in weights(mc, 40).items()}
+    for dd in (0.7, 1.6, 2.5):
+        pos = np.array([[0.1, 0.2, 0.3], [0.1 + dd, 0.2, 0.3]])
+        s = W.System(pos=pos, species=np.array([0, 1], np.int32), cell=np.zeros(3), pbc=np.zeros(3, np.int32),
+                     n_local=2)
+        r = model.evaluate(mc, w, s)
+        u = basis.envelope(torch.tensor([dd / 3.0], dtype=torch.float64), 6)
+        ez = basis.zbl_energy(torch.tensor([dd], dtype=torch.float64), torch.tensor(1.0, dtype=torch.float64),
+                              torch.tensor(8.0, dtype=torch.float64))
+        assert abs(r.energy - float(ez * u)) < 1e-12 * max(1.0, abs(r.energy))
+        h = 1e-6
+        ep = model.energy_of_positions(mc, w, s, pos + np.array([[0, 0, 0], [h, 0, 0]]))
+        em = model.energy_of_positions(mc, w, s, pos - np.array([[0, 0, 0], [h, 0, 0]]))
+        assert abs(-(ep - em) / (2 * h) - r.forces[1, 0]) < 1e-6 * max(1.0, abs(r.forces[1, 0]))
+        assert abs(r.forces[0, 0] + r.forces[1, 0]) < 1e-9 * max(1.0, abs(r.forces[1, 0]))
+
+
+def test_zbl_forces_finite_difference():
+    mc = zbl_model(pairs=True)
+    w = weights(mc, 41)
+    s = cluster(12, 13)
+    _fd_check(mc, w, s, [(a, ax) for a in (0, 4, 11) for ax in range(3)], tol=1e-6)
+
+
+def test_zbl_continuity_at_cutoff():
+    mc = zbl_model()
+    w = weights(mc, 42)
+    base = np.array([[0.0, 0.0, 0.0], [1.2, 0.4, 0.0], [0.5, -1.0, 0.3]])
+    sp = np.array([0, 1, 1], dtype=np.int32)
+
+    def E(xd):
+        pos = np.concatenate([base, [[-xd, 0.0, 0.0]]])
+        s = W.System(pos=pos, species=np.concatenate([sp, [1]]).astype(np.int32), cell=np.zeros(3),
+                     pbc=np.zeros(3, np.int32), n_local=4)
+        return model.evaluate(mc, w, s).energy
+    e_out = E(3.6)
+    for eps in (1e-2, 1e-3):
+        assert abs(E(3.0 - eps) - e_out) < 50 * eps ** 3

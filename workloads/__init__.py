@@ -32,6 +32,11 @@ MASSES_2 = (1.008, 15.999)
 PAPER_PAIR_CUTOFFS = {("H", "H"): 3.0, ("H", "C"): 1.25, ("H", "O"): 1.25, ("O", "H"): 3.0}
 
 
+def atomic_numbers(n_species: int):
+    """Atomic numbers of the 2-species (H, O) or 4-species (H, C, N, O) mixes."""
+    return (1, 8) if n_species == 2 else (1, 6, 7, 8)
+
+
 def paper_pair_cutoffs(n_species: int, r_cut: float):
     """[S][S] table of those cutoffs for the 2-species (H, O) or 4-species
     (H, C, N, O) mixes used here; pairs the paper does not list get r_cut."""
@@ -57,6 +62,8 @@ class ModelConfig:
     # ordered per-species-pair cutoffs rc[Z_centre][Z_neighbour] (A), each at
     # most r_cut; None = r_cut for every pair
     pair_cutoffs: Optional[Sequence[Sequence[float]]] = None
+    # atomic number of each species for the ZBL repulsion; None = no ZBL term
+    atomic_numbers: Optional[Sequence[int]] = None
 
     def __post_init__(self):
         self.twobody_dims = tuple(int(v) for v in self.twobody_dims)
