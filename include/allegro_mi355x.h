@@ -104,6 +104,15 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *                    basis and envelope are scaled to that cutoff).  Read by
  *                    allegro_describe / allegro_create and copied; the skin is
  *                    added to every pair's radius.
+ *   atomic_numbers   host [n_species] atomic number of each species (1..118), or
+ *                    NULL = no pair term.  When given, the ZBL screened-Coulomb
+ *                    repulsion the paper adds for stability (section "Training
+ *                    details") enters every atom's energy unscaled:
+ *                    A_i += sum_j 1/2 E_ZBL(d_ij) u(d_ij / r_c,ij), the ZBL
+ *                    universal potential (k_e Z_i Z_j / d phi(d / a),
+ *                    a = 0.4685 A / (Z_i^0.23 + Z_j^0.23)) under each edge's own
+ *                    envelope; forces and virial include it.  Read at create and
+ *                    copied.
  * MLP widths must be multiples of 16 and at most 512; the latent width d at most 256.
  */
 typedef struct {
@@ -117,6 +126,7 @@ typedef struct {
   int64_t edge_chunk;
   double neighbor_skin;
   const double* r_cut_pair;
+  const int32_t* atomic_numbers;
 } AllegroConfig;
 
 /* Host-side description of a configuration (no device work). */

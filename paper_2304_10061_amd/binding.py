@@ -39,7 +39,8 @@ class AllegroConfig(ctypes.Structure):
                 ("r_cut", ctypes.c_double), ("avg_num_neighbors", ctypes.c_double),
                 ("channel_mix", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("edge_chunk", ctypes.c_int64), ("neighbor_skin", ctypes.c_double),
-                ("r_cut_pair", ctypes.POINTER(ctypes.c_double))]
+                ("r_cut_pair", ctypes.POINTER(ctypes.c_double)),
+                ("atomic_numbers", ctypes.POINTER(ctypes.c_int32))]
 
 
 class AllegroInfo(ctypes.Structure):
@@ -113,8 +114,9 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
                 latent_dims: Sequence[int] = (128, 128), edge_dims: Sequence[int] = (128,),
                 avg_num_neighbors: Optional[float] = None, channel_mix: bool = True,
                 precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0,
-                r_cut_pair=None) -> AllegroConfig:
-    """r_cut_pair: optional [n_species][n_species] ordered cutoffs (row = centre species)."""
+                r_cut_pair=None, atomic_numbers=None) -> AllegroConfig:
+    """r_cut_pair: optional [n_species][n_species] ordered cutoffs (row = centre species);
+    atomic_numbers: optional [n_species] (switches on the ZBL pair term)."""
     c = AllegroConfig()
     c.n_species, c.n_bessel, c.envelope_p, c.l_max = n_species, n_bessel, envelope_p, l_max
     c.n_layers, c.n_tensor = n_layers, n_tensor
@@ -139,6 +141,12 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
         table = (ctypes.c_double * len(flat))(*flat)
         c.r_cut_pair = ctypes.cast(table, ctypes.POINTER(ctypes.c_double))
         c._r_cut_pair_table = table   # kept alive with the config; the library copies it
+    if atomic_numbers is not None:
+        if len(atomic_numbers) != n_species:
+            raise ValueError("atomic_numbers must have n_species entries")
+        zt = (ctypes.c_int32 * n_species)(*[int(z) for z in atomic_numbers])
+        c.atomic_numbers = ctypes.cast(zt, ctypes.POINTER(ctypes.c_int32))
+        c._atomic_numbers_table = zt
     return c
 
 
@@ -149,7 +157,8 @@ def config_from(mc, precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_sk
                        twobody_dims=mc.twobody_dims, latent_dims=mc.latent_dims, edge_dims=mc.edge_dims,
                        avg_num_neighbors=mc.avg_num_neighbors, channel_mix=mc.channel_mix,
                        precision=precision, edge_chunk=edge_chunk, neighbor_skin=neighbor_skin,
-                       r_cut_pair=getattr(mc, "pair_cutoffs", None))
+                       r_cut_pair=getattr(mc, "pair_cutoffs", None),
+                       atomic_numbers=getattr(mc, "atomic_numbers", None))
 
 
 def describe(cfg: AllegroConfig) -> AllegroInfo:

@@ -162,6 +162,9 @@ Validated validate(const AllegroConfig* c) {
           "precision must be 0, 1, 2 or 3");
   REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
   REQUIRE(c->neighbor_skin >= 0 && std::isfinite(c->neighbor_skin), "neighbor_skin must be >= 0");
+  if (c->atomic_numbers)
+    for (int k = 0; k < v.S; ++k)
+      REQUIRE(c->atomic_numbers[k] >= 1 && c->atomic_numbers[k] <= 118, "atomic_numbers must lie in 1..118");
   if (c->r_cut_pair)
     for (int k = 0; k < v.S * v.S; ++k)
       REQUIRE(std::isfinite(c->r_cut_pair[k]) && c->r_cut_pair[k] > 0 && c->r_cut_pair[k] <= c->r_cut,
@@ -260,6 +263,10 @@ struct AllegroModel {
   // copy, FP32 radii for the edge kernels, squared list radii for the list
   std::vector<double> rc_pair;
   DevBuf rc_pair_f, rc2_pair;
+  // ZBL term: atomic numbers (empty = none), their device table [Z | Z^0.23]
+  // and the per-edge pair shares of the current chunk
+  std::vector<int> znum;
+  DevBuf zbl_tab, epair;
   DevBuf mixF[2], mixB[2];                // packed FP32 mixing matrices per layer
   int mix_stride = 0;
   DevBuf tpw[2];                          // fused coupling non-zeros per layer
@@ -354,6 +361,14 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     }
     upload(m->rc_pair_f, rf.data(), rf.size() * sizeof(float));
     upload(m->rc2_pair, r2.data(), r2.size() * sizeof(double));
+  }
+  if (!m->znum.empty()) {
+    std::vector<float> zt(2 * v.S);
+    for (int k = 0; k < v.S; ++k) {
+      zt[k] = (float)m->znum[k];
+      zt[v.S + k] = (float)std::pow((double)m->znum[k], 0.23);
+    }
+    upload(m->zbl_tab, zt.data(), zt.size() * sizeof(float));
   }
   int64_t off = 0;
   // two-body MLP
@@ -723,6 +738,7 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   m->gY.ensure(Ec * 9 * f);
   m->gu.ensure(Ec * f);
   m->gR.ensure(Ec * v.nb * f);
+  if (!m->znum.empty()) m->epair.ensure(Ec * f);
   if (m->prec != ALLEGRO_PREC_FP32) m->zscr.ensure(mlp_tall_scratch_bytes(Ec, v.d));
   m->g_e.ensure(Ee * 3 * f);
   m->atom_e.ensure(std::max<int64_t>(n_local, 1) * sizeof(double));
@@ -756,6 +772,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     for (int ax = 0; ax < 3; ++ax) ea.L[ax] = m->L[ax];
     ea.r_cut = m->cfg.r_cut; ea.p = v.p; ea.n_bessel = v.nb; ea.l_max = v.lmax;
     ea.rc_pair = m->rc_pair.empty() ? nullptr : ptr<float>(m->rc_pair_f); ea.n_species = v.S;
+    if (!m->znum.empty()) { ea.zbl = ptr<float>(m->zbl_tab); ea.e_pair = ptr<float>(m->epair); }
     ea.eb = ptr<float>(m->eb);
     timed(m, "edge_basis", s, [&] { return launch_edge_basis(ea, s); });
 
@@ -809,6 +826,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
 
     ReduceArgs ra;
     ra.n_centres = nc; ra.centre_base = (int)cA; ra.row_ptr = drp; ra.eij = ptr<float>(m->eij);
+    ra.e_pair = m->znum.empty() ? nullptr : ptr<float>(m->epair);
     ra.species = species; ra.scale = ptr<double>(m->scale); ra.shift = ptr<double>(m->shift); ra.atom_energy = aE;
     timed(m, "atom_energy", s, [&] { return launch_atom_energy(ra, s); });
 
@@ -1135,7 +1153,9 @@ int allegro_create(const AllegroConfig* cfg, const float* weights, int64_t n_wei
     m->v = v;
     m->prec = cfg->precision;
     if (cfg->r_cut_pair) m->rc_pair.assign(cfg->r_cut_pair, cfg->r_cut_pair + v.S * v.S);
-    m->cfg.r_cut_pair = nullptr;   // the caller's table is not kept
+    if (cfg->atomic_numbers) m->znum.assign(cfg->atomic_numbers, cfg->atomic_numbers + v.S);
+    m->cfg.r_cut_pair = nullptr;   // the caller's tables are not kept
+    m->cfg.atomic_numbers = nullptr;
     switch (m->prec) {
       case ALLEGRO_PREC_FP32: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 0; break;
       case ALLEGRO_PREC_BF16: m->prec_two = m->prec_lat = m->prec_lat_first = m->prec_lat_rest = 1; break;

@@ -45,6 +45,29 @@ __device__ __forceinline__ float ipow(float t, int p) {
   return r;
 }
 
+// ZBL universal screened Coulomb repulsion (the paper's stabilising pair
+// term, section "Training details"): E(d) = k_e Z_i Z_j / d * phi(d / a_s),
+// a_s = 0.46850 A / (Z_i^0.23 + Z_j^0.23), phi a sum of four exponentials
+// with phi(0) = 1.  Returns E and dE/dd.
+constexpr float kZblKe = 14.399645f;
+__device__ __forceinline__ void zbl_pair(const float* zbl, int S, int zi, int zj, float d, float* E, float* dE) {
+  const float zz = zbl[zi] * zbl[zj];
+  const float as = 0.46850f / (zbl[S + zi] + zbl[S + zj]);
+  const float x = d / as;
+  const float c[4] = {0.18175f, 0.50986f, 0.28022f, 0.02817f};
+  const float k[4] = {3.19980f, 0.94229f, 0.40290f, 0.20162f};
+  float phi = 0.0f, dphi = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float ex = c[q] * expf(-k[q] * x);
+    phi += ex;
+    dphi -= k[q] * ex;
+  }
+  const float pre = kZblKe * zz / d;
+  *E = pre * phi;
+  *dE = pre * (dphi / as - phi / d);
+}
+
 __device__ __forceinline__ void edge_vector(const EdgeArgs& a, int64_t e, double* r) {
   const int i = a.ei[e], j = a.ej[e];
   for (int ax = 0; ax < 3; ++ax)
@@ -80,6 +103,11 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
   o[kEB_RHAT] = x; o[kEB_RHAT + 1] = y; o[kEB_RHAT + 2] = z;
   o[kEB_ZI] = (float)zi;
   o[kEB_ZJ] = (float)zj;
+  if (a.zbl) {   // half of the pair's repulsion per ordered edge, under the edge's envelope
+    float Ez, dEz;
+    zbl_pair(a.zbl, S, zi, zj, d, &Ez, &dEz);
+    a.e_pair[e] = 0.5f * Ez * u;
+  }
   const float pref = sqrtf(2.0f / rc);
   for (int k = 0; k < 16; ++k) {
     float v = 0.0f;
@@ -114,6 +142,12 @@ __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
     gd += gR * dB * u;
   }
   gd += gu * du;
+  if (a.zbl) {
+    const int zi = (int)o[kEB_ZI], zj = (int)o[kEB_ZJ];
+    float Ez, dEz;
+    zbl_pair(a.zbl, a.n_species, zi, zj, d, &Ez, &dEz);
+    gd += 0.5f * (dEz * u + Ez * du);
+  }
   const float* gY = a.g_Y + e * 9;
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
   if (a.l_max >= 1) {
@@ -136,13 +170,18 @@ __global__ __launch_bounds__(256) void k_atom_energy(ReduceArgs a) {
   const int lane = lane_id();
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.n_centres) return;
-  float s = 0.0f;
-  for (int e = a.row_ptr[c] + lane; e < a.row_ptr[c + 1]; e += kWave) s += a.eij[e];
+  float s = 0.0f, sp = 0.0f;
+  for (int e = a.row_ptr[c] + lane; e < a.row_ptr[c + 1]; e += kWave) {
+    s += a.eij[e];
+    if (a.e_pair) sp += a.e_pair[e];
+  }
   s = wave_sum(s);
+  sp = wave_sum(sp);
   if (lane == 0) {
     const int g = a.centre_base + c;
     const int z = a.species[g];   // validated by the neighbour build
-    a.atom_energy[g] = a.scale[z] * (double)s + a.shift[z];
+    // the pair term is added after the species scale and shift
+    a.atom_energy[g] = a.scale[z] * (double)s + a.shift[z] + (double)sp;
   }
 }
 

@@ -108,6 +108,8 @@ struct EdgeArgs {
   double r_cut = 0;
   const float* rc_pair = nullptr; // [S][S] cutoff of each ordered species pair, or null (r_cut)
   int n_species = 1;
+  const float* zbl = nullptr;     // [2][S] atomic number and its 0.23 power per species, or null (no ZBL)
+  float* e_pair = nullptr;        // [E] ZBL share of each ordered edge (written when zbl is set)
   int p = 6, n_bessel = 8, l_max = 2;
   float* eb = nullptr;
   // backward
@@ -171,6 +173,7 @@ struct ReduceArgs {
   int centre_base = 0;            // global index of the chunk's first centre
   const int32_t* row_ptr = nullptr;  // chunk-relative [n_centres+1]
   const float* eij = nullptr;
+  const float* e_pair = nullptr;  // [E] unscaled pair-term shares, or null
   const int32_t* species = nullptr;
   const double* scale = nullptr;
   const double* shift = nullptr;

@@ -49,7 +49,8 @@ def test_describe_matches_oracle(cfg):
                                  dict(latent_dims=(64, 32)), dict(edge_dims=(64, 64)), dict(r_cut=-1.0),
                                  dict(r_cut_pair=((3.0, 4.5), (3.0, 4.0))),      # above r_cut
                                  dict(r_cut_pair=((3.0, 0.0), (3.0, 4.0))),      # not positive
-                                 dict(r_cut_pair=((3.0, float("nan")), (3.0, 4.0)))])
+                                 dict(r_cut_pair=((3.0, float("nan")), (3.0, 4.0))),
+                                 dict(atomic_numbers=(0, 8)), dict(atomic_numbers=(1, 119))])
 def test_describe_rejects_unsupported(bad):
     kw = dict(n_species=2, r_cut=4.0, l_max=2, n_layers=2, n_tensor=32, twobody_dims=(64, 64),
               latent_dims=(64, 64), edge_dims=(32,))
