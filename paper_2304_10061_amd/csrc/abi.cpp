@@ -827,7 +827,8 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     ReduceArgs ra;
     ra.n_centres = nc; ra.centre_base = (int)cA; ra.row_ptr = drp; ra.eij = ptr<float>(m->eij);
     ra.e_pair = m->znum.empty() ? nullptr : ptr<float>(m->epair);
-    ra.species = species; ra.scale = ptr<double>(m->scale); ra.shift = ptr<double>(m->shift); ra.atom_energy = aE;
+    ra.species = species; ra.n_species = v.S;
+    ra.scale = ptr<double>(m->scale); ra.shift = ptr<double>(m->shift); ra.atom_energy = aE;
     timed(m, "atom_energy", s, [&] { return launch_atom_energy(ra, s); });
 
     // ---- adjoint ----

@@ -179,7 +179,8 @@ __global__ __launch_bounds__(256) void k_atom_energy(ReduceArgs a) {
   sp = wave_sum(sp);
   if (lane == 0) {
     const int g = a.centre_base + c;
-    const int z = a.species[g];   // validated by the neighbour build
+    // validated by the neighbour build; clamped like the edge records' species
+    const int z = min(max(a.species[g], 0), a.n_species - 1);
     // the pair term is added after the species scale and shift
     a.atom_energy[g] = a.scale[z] * (double)s + a.shift[z] + (double)sp;
   }

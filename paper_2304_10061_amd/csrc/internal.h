@@ -175,6 +175,7 @@ struct ReduceArgs {
   const float* eij = nullptr;
   const float* e_pair = nullptr;  // [E] unscaled pair-term shares, or null
   const int32_t* species = nullptr;
+  int n_species = 1;
   const double* scale = nullptr;
   const double* shift = nullptr;
   double* atom_energy = nullptr;  // global [n_local]
