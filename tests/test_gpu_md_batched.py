@@ -23,8 +23,12 @@ def _cluster_batch():
     return W.clusters(10, 17, lo=20, hi=250)
 
 
-def test_batched_neighbors_and_energies_equal_individual():
+@pytest.mark.parametrize("extras", [False, True], ids=["plain", "pair_cutoffs_zbl"])
+def test_batched_neighbors_and_energies_equal_individual(extras):
     mc = W.model_config(5)
+    if extras:   # the paper's ordered pair cutoffs and the ZBL term
+        mc.pair_cutoffs = W.paper_pair_cutoffs(mc.n_species, mc.r_cut)
+        mc.atomic_numbers = W.atomic_numbers(mc.n_species)
     w = W.make_weights(mc, np.random.default_rng(4))
     sc, sh = W.species_scale_shift(mc, np.random.default_rng(5))
     b = _cluster_batch()
@@ -48,7 +52,8 @@ def test_batched_neighbors_and_energies_equal_individual():
         a, z = int(off[k]), int(off[k + 1])
         sub = W.System(pos=b.pos[a:z], species=b.species[a:z], cell=np.zeros(3), pbc=np.zeros(3, np.int32),
                        n_local=z - a)
-        ri, rj, rs = neighbor_list(sub.pos, sub.cell, sub.pbc, mc.r_cut)
+        ri, rj, rs = neighbor_list(sub.pos, sub.cell, sub.pbc, mc.r_cut, species=sub.species,
+                                   pair_cutoffs=mc.pair_cutoffs)
         edges.append((ri + a, rj + a))
         ref = OM.evaluate(mc, w, sub, sc, sh)
         assert abs(Es[k] - ref.energy) / (z - a) < 1e-6
