@@ -160,3 +160,27 @@ def test_pair_cutoffs_are_ordered():
                  if Z[a] == 1 and Z[b] == 0 and dd >= 1.25]
     assert one_sided
     assert all((b, a, tuple(-x for x in c)) not in kept for (a, b, c) in one_sided)
+
+
+def test_paper_pair_cutoff_table_matches_printed_values():
+    """The table the code uses for the paper's cutoffs equals the printed one
+    (tests/golden/pair_cutoffs_training_details.txt), ordering included."""
+    import os
+    names = ("H", "C", "N", "O")
+    listed, default = {}, None
+    with open(os.path.join(os.path.dirname(__file__), "golden", "pair_cutoffs_training_details.txt")) as f:
+        for line in f:
+            parts = line.split("#", 1)[0].split()
+            if not parts:
+                continue
+            if parts[0] == "default":
+                default = float(parts[1])
+            else:
+                listed[(parts[0], parts[1])] = float(parts[2])
+    table = W.paper_pair_cutoffs(4, default)
+    for a, za in enumerate(names):
+        for b, zb in enumerate(names):
+            assert table[a][b] == listed.get((za, zb), default), (za, zb)
+    assert table[0][1] == 1.25 and table[1][0] == default       # H-C restricted, C-H not
+    two = W.paper_pair_cutoffs(2, default)                       # (H, O) mix
+    assert two == ((3.0, 1.25), (3.0, default))
