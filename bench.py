@@ -176,6 +176,27 @@ def mlp_macs_per_edge(mc):
     return out
 
 
+def mlp_bytes_per_edge(mc):
+    """Algorithmic HBM bytes per edge of each MLP kernel kind: every input
+    row read once and every output row written once (FP32 arrays; per-centre
+    and per-species rows, which stay in cache, are not counted)."""
+    d, n, LW, f = mc.latent, mc.n_tensor, (mc.l_max + 1) * mc.n_tensor, 4
+    dim = (mc.l_max + 1) ** 2
+    edge_in = f * (mc.n_bessel + 3)                 # radial basis, u and the species pair of the edge record
+    out = {
+        "mlp_fwd_twobody": edge_in + f * (d + 2 * LW),
+        "mlp_fwd_latent": f * (d + n + 1) + f * (d + LW),
+        "mlp_fwd_final": f * (d + dim * n + 1) + f * (1 + n),
+        "mlp_bwd_final": f * (d + n + 1) + f * (d + n + 1),
+        "mlp_bwd_latent": f * (d + LW + d + n + 1) + f * (d + n + 1),
+        "mlp_bwd_twobody": edge_in + f * (d + 2 * LW) + f * (mc.n_bessel + 1),
+    }
+    if mc.n_layers == 1:
+        out.pop("mlp_fwd_latent")
+        out.pop("mlp_bwd_latent")
+    return out
+
+
 def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times, autotune=True):
     import torch
     import paper_2304_10061_amd as P
@@ -413,10 +434,15 @@ def main():
         flops = 2.0 * macs[dom] * bf["edges"] * bf["kernel_launches"].get(dom, 1)
         achieved = flops / (kms[dom] * 1e-3) / 1e12
         sym = mlp_symbol(dom, 1, (bf["tiles"] or {}).get(dom, 0), mc.latent)
+        launches = max(1, bf["kernel_launches"].get(dom, 1))
+        avg_ms = kms[dom] / launches
+        alg_bytes = mlp_bytes_per_edge(mc)[dom] * bf["edges"]   # per launch (one launch per chunk)
         roof = {"kernel": dom, "symbol": sym, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": traffic_per_launch(sym),
-                "flops_per_launch": flops / max(1, bf["kernel_launches"].get(dom, 1)),
-                "avg_launch_ms": kms[dom] / max(1, bf["kernel_launches"].get(dom, 1))}
+                "flops_per_launch": flops / launches, "avg_launch_ms": avg_ms,
+                # the same launch against the HBM roof, on algorithmic bytes
+                "alg_bytes_per_launch": alg_bytes / launches,
+                "hbm_frac_alg": alg_bytes / launches / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
                 "frac": None, "traffic": None}
