@@ -16,7 +16,10 @@ paper; the readings used are:
   (sum_m Y_lm(r)^2 = 2l + 1 on the unit sphere), m ordered -l..l:
     Y_0 = 1
     Y_1 = sqrt(3) (y, z, x)
-    Y_2 = (sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2 - 1), sqrt15 xz, sqrt15/2 (x^2 - y^2)).
+    Y_2 = (sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2 - 1), sqrt15 xz, sqrt15/2 (x^2 - y^2))
+    Y_3 = (sqrt70/4 y(3x^2 - y^2), sqrt105 xyz, sqrt42/4 y(5z^2 - 1),
+           sqrt7/2 z(5z^2 - 3), sqrt42/4 x(5z^2 - 1), sqrt105/2 z(x^2 - y^2),
+           sqrt70/4 x(x^2 - 3y^2)).
   The parity of Y_l is (-1)^l.
 """
 from __future__ import annotations
@@ -46,8 +49,8 @@ def bessel(d: torch.Tensor, r_cut, n_bessel: int) -> torch.Tensor:
 
 def spherical_harmonics(rhat: torch.Tensor, l_max: int) -> torch.Tensor:
     """[E, (l_max+1)^2] real spherical harmonics of unit vectors."""
-    if l_max > 2:
-        raise NotImplementedError("l_max <= 2")
+    if l_max > 3:
+        raise NotImplementedError("l_max <= 3")
     x, y, z = rhat[:, 0], rhat[:, 1], rhat[:, 2]
     cols = [torch.ones_like(x)]
     if l_max >= 1:
@@ -57,6 +60,12 @@ def spherical_harmonics(rhat: torch.Tensor, l_max: int) -> torch.Tensor:
         s15, s5 = math.sqrt(15.0), math.sqrt(5.0)
         cols += [s15 * x * y, s15 * y * z, s5 / 2.0 * (3.0 * z * z - 1.0), s15 * x * z,
                  s15 / 2.0 * (x * x - y * y)]
+    if l_max >= 3:
+        s70, s105, s42, s7 = math.sqrt(70.0), math.sqrt(105.0), math.sqrt(42.0), math.sqrt(7.0)
+        zz = 5.0 * z * z
+        cols += [s70 / 4.0 * y * (3.0 * x * x - y * y), s105 * x * y * z, s42 / 4.0 * y * (zz - 1.0),
+                 s7 / 2.0 * z * (zz - 3.0), s42 / 4.0 * x * (zz - 1.0), s105 / 2.0 * z * (x * x - y * y),
+                 s70 / 4.0 * x * (x * x - 3.0 * y * y)]
     return torch.stack(cols, dim=1)
 
 

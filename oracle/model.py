@@ -14,7 +14,8 @@ layer L = 1..N_l:
   w      = x^{L-1} @ W_env^L                        (the linear "embedding MLP")
   Gamma_i[b, u] = (1/sqrt(avg_nbrs)) sum_{k in N(i)} w^{ik}[l(b), u] Y^{ik}[b]
   T[c, u]       = sum_{a, b} W^L[a, b, c] V^{L-1}[a, u] Gamma_i[b, u]   (Eq. tp, factored)
-  V^L[c, v]     = sum_u M^L_{l(c)}[v, u] T[c, u] / sqrt(n)   (linear channel mixing)
+  V^L[c, v]     = sum_u M^L_{irrep(c)}[v, u] T[c, u] / sqrt(n)   (linear channel mixing,
+                  one matrix per output irrep (l, p))
   x^L    = (x^{L-1} + u * MLP_L([x^{L-1}, V^L[0, :]])) / sqrt(2)
 edge energy:  E_ij = (x^{N_l} @ W_e1) @ W_e2        (one hidden layer, no nonlinearity)
 atom energy:  A_i = sigma_{Z_i} sum_j E_ij + mu_{Z_i};  E = sum_i A_i
@@ -64,12 +65,14 @@ class Params:
         self.twobody = [t(weights[f"twobody.W{k}"]) for k in range(nb)]
         self.embed0 = t(weights["embed0"])
         self.paths = cg.layer_paths(mc.l_max, mc.n_layers)
+        self.widths = cg.layer_widths(mc.l_max, mc.n_layers)
         self.env, self.W, self.mix, self.mlp = [], [], [], []
         for L in range(1, mc.n_layers + 1):
             self.env.append(t(weights[f"layer{L}.env"]))
             final = L == mc.n_layers
+            n_in, n_out = self.widths[L - 1]
             self.W.append(t(cg.fused_table(mc.l_max, self.paths[L - 1],
-                                           np.asarray(weights[f"layer{L}.alpha"]), final)))
+                                           np.asarray(weights[f"layer{L}.alpha"]), final, n_in, n_out)))
             self.mix.append(t(weights[f"layer{L}.mix"]))
             self.mlp.append([t(weights[f"layer{L}.mlp.W{k}"]) for k in range(nl)])
         ne = len(mc.edge_dims) + 1
@@ -92,6 +95,9 @@ def edge_energies(p: Params, r: torch.Tensor, ci: torch.Tensor, zi: torch.Tensor
     n, lm, S = mc.n_tensor, mc.l_max, mc.n_species
     lc = torch.as_tensor(basis.irrep_of_component(lm))
     dim = (lm + 1) ** 2
+    # mixing-matrix slot of each strided component: natural (l, (-1)^l) -> l,
+    # the other parity (components dim..2 dim) -> l_max + 1 + l
+    slot = torch.cat([lc, lc + lm + 1])
     E = r.shape[0]
 
     d = torch.sqrt((r * r).sum(1))
@@ -121,7 +127,7 @@ def edge_energies(p: Params, r: torch.Tensor, ci: torch.Tensor, zi: torch.Tensor
         T = torch.einsum("abc,eau,ebu->ecu", p.W[L], V, gam[ci])
         n_out = T.shape[1]
         if mc.channel_mix:
-            M = p.mix[L][lc[:n_out]]                          # [n_out, v, u]
+            M = p.mix[L][slot[:n_out]]                        # [n_out, v, u]
             V = torch.einsum("cvu,ecu->ecv", M, T) / math.sqrt(n)
         else:
             V = T

@@ -5,7 +5,8 @@ paper's equations allow: per ordered pair, per neighbour k, per path, with the
 unfused coupling tensors and the tensor product taken *inside* the neighbour
 sum (the left-hand side of Eq. tp), in plain Python floats.  Agreement with the
 oracle pins its indexing (strided components, segment grouping, path fusion,
-factorisation of the neighbour sum).
+factorisation of the neighbour sum, and for deeper models the parity blocks
+of the strided layout and the per-irrep mixing).
 """
 import math
 
@@ -35,8 +36,13 @@ def _mlp(x, Ws):
 def _sh(v):
     x, y, z = v
     s3, s15, s5 = math.sqrt(3), math.sqrt(15), math.sqrt(5)
-    return [1.0, s3 * y, s3 * z, s3 * x, s15 * x * y, s15 * y * z, s5 / 2 * (3 * z * z - 1),
-            s15 * x * z, s15 / 2 * (x * x - y * y)]
+    out = [1.0, s3 * y, s3 * z, s3 * x, s15 * x * y, s15 * y * z, s5 / 2 * (3 * z * z - 1),
+           s15 * x * z, s15 / 2 * (x * x - y * y)]
+    c70, c105, c42, c7 = math.sqrt(70) / 4, math.sqrt(105), math.sqrt(42) / 4, math.sqrt(7) / 2
+    out += [c70 * y * (3 * x * x - y * y), c105 * x * y * z, c42 * y * (5 * z * z - 1),
+            c7 * z * (5 * z * z - 3), c42 * x * (5 * z * z - 1), c105 / 2 * z * (x * x - y * y),
+            c70 * x * (x * x - 3 * y * y)]
+    return out
 
 
 def energy(mc, w, sysm):
@@ -48,6 +54,15 @@ def energy(mc, w, sysm):
     dim = (lm + 1) ** 2
     lof = [l for l in range(lm + 1) for _ in range(2 * l + 1)]
     paths = cg.layer_paths(lm, mc.n_layers)
+
+    def off(l, p):   # first component of irrep (l, p): natural block, then the other parity
+        return l * l + (0 if p == (-1) ** l else dim)
+
+    def slot(c):     # mixing matrix of component c
+        return lof[c] if c < dim else lm + 1 + lof[c - dim]
+
+    def width(irreps):
+        return 2 * dim if any(p != (-1) ** l for (l, p) in irreps) else dim
     edges = []
     for (i, j, s) in zip(I.tolist(), J.tolist(), S.tolist()):
         r = [(pos[j, a] - pos[i, a]) + s[a] * L[a] for a in range(3)]
@@ -72,30 +87,31 @@ def energy(mc, w, sysm):
         M = np.asarray(w[f"layer{Lr}.mix"], dtype=np.float64)
         kept = paths[Lr - 1]
         cnt = {}
-        for (_, _, lo) in kept:
-            cnt[lo] = cnt.get(lo, 0) + 1
+        for (_, _, _, lo, po) in kept:
+            cnt[(lo, po)] = cnt.get((lo, po), 0) + 1
         wk = [_matvec(e["x"], w[f"layer{Lr}.env"]) for e in edges]
-        n_out = 1 if final else dim
+        n_out = 1 if final else width([(lo, po) for (_, _, _, lo, po) in kept])
         newV = []
         for e in edges:
             T = [[0.0] * n for _ in range(n_out)]
             for (k, f) in enumerate(edges):
                 if f["i"] != e["i"]:
                     continue
-                for (l1, l2, lo) in kept:
+                for (l1, p1, l2, lo, po) in kept:
                     C = cg.coupling(l1, l2, lo)
-                    a = al[l1, l2, lo] / math.sqrt(cnt[lo])
+                    raw = al[0 if p1 == (-1) ** l1 else 1, l1, l2, lo] if al.ndim == 4 else al[l1, l2, lo]
+                    a = raw / math.sqrt(cnt[(lo, po)])
                     for m1 in range(2 * l1 + 1):
                         for m2 in range(2 * l2 + 1):
                             for m3 in range(2 * lo + 1):
                                 cf = C[m1, m2, m3]
                                 if cf == 0.0:
                                     continue
-                                c1, c2, c3 = l1 * l1 + m1, l2 * l2 + m2, lo * lo + m3
+                                c1, c2, c3 = off(l1, p1) + m1, l2 * l2 + m2, off(lo, po) + m3
                                 for q in range(n):
                                     T[c3][q] += a * cf * e["V"][c1][q] * cn * wk[k][l2 * n + q] * f["Y"][c2]
             if mc.channel_mix:
-                Vn = [[sum(M[lof[c], v, q] * T[c][q] for q in range(n)) / math.sqrt(n) for v in range(n)]
+                Vn = [[sum(M[slot(c), v, q] * T[c][q] for q in range(n)) / math.sqrt(n) for v in range(n)]
                       for c in range(n_out)]
             else:
                 Vn = T

@@ -64,6 +64,20 @@ def test_matches_loop_form(l_max, n_layers, mix):
     assert np.allclose(got, ref, rtol=1e-11, atol=1e-13)
 
 
+@pytest.mark.parametrize("l_max,n_layers,n_atoms", [(2, 3, 8), (1, 4, 8), (3, 3, 6), (3, 2, 7)])
+def test_deep_matches_loop_form(l_max, n_layers, n_atoms):
+    """Three or more layers bring unnatural-parity irreps (parity blocks of the
+    strided layout, the triple-product couplings, per-irrep mixing); l_max 3
+    brings the l = 3 harmonics."""
+    mc = tiny_model(l_max, n_layers, n=3, d=8)
+    w = weights(mc, 21 + n_layers)
+    s = cluster(n_atoms, 4)
+    ref = oracle_loops.energy(mc, w, s)
+    got = model.evaluate(mc, w, s).edge_energy
+    assert ref.shape == got.shape and len(ref) > 10
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-13)
+
+
 def test_periodic_loop_form():
     mc = tiny_model(2, 2)
     w = weights(mc, 2)
@@ -101,8 +115,18 @@ def test_forces_finite_difference_two_layers():
     _fd_check(mc, w, s, [(a, ax) for a in (0, 5, 13) for ax in range(3)])
 
 
-def test_invariances_and_covariant_forces():
-    mc = tiny_model(2, 2, n=6, d=16, rc=3.2)
+def test_forces_finite_difference_deep():
+    mc = tiny_model(3, 3, n=4, d=16, rc=3.2)
+    w = weights(mc, 14)
+    s = cluster(12, 15)
+    _fd_check(mc, w, s, [(a, ax) for a in (0, 7, 11) for ax in range(3)])
+
+
+@pytest.mark.parametrize("l_max,n_layers", [(2, 2), (2, 3), (3, 3), (1, 4)])
+def test_invariances_and_covariant_forces(l_max, n_layers):
+    """E(3) with reflections: a path whose output parity were mislabelled would
+    leave a pseudoscalar in the energy and break the mirror case."""
+    mc = tiny_model(l_max, n_layers, n=6, d=16, rc=3.2)
     w = weights(mc, 6)
     s = cluster(20, 7)
     r0 = model.evaluate(mc, w, s)

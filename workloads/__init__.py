@@ -274,9 +274,14 @@ def weight_shapes(mc: ModelConfig) -> List[tuple]:
     (y = x @ W).  Columns of `embed0` and `layer*.env` are indexed l*n + u
     (irrep order l = 0..l_max, channel u).  `alpha` is indexed
     [l1][l2][l_out] over 0..l_max (entries of unused paths are ignored);
-    `mix` is [l][v][u] (output channel v, input channel u).
+    `mix` is [l][v][u] (output channel v, input channel u).  Models of three
+    or more layers, whose middle layers carry both parities, use
+    [2][l1][l2][l_out] for `alpha` (leading index 0 for a natural-parity
+    input irrep (l1, (-1)^l1), 1 for the other parity) and 2 (l_max + 1)
+    mixing matrices (natural l = 0..l_max, then the other parity).
     """
     n, lm1, d = mc.n_tensor, mc.l_max + 1, mc.latent
+    par = 2 if mc.n_layers >= 3 else 1
     out = []
     dims = [2 * mc.n_species + mc.n_bessel] + list(mc.twobody_dims)
     for k in range(len(dims) - 1):
@@ -285,8 +290,8 @@ def weight_shapes(mc: ModelConfig) -> List[tuple]:
     prev = mc.twobody_dims[-1]
     for L in range(1, mc.n_layers + 1):
         out.append((f"layer{L}.env", (prev, lm1 * n)))
-        out.append((f"layer{L}.alpha", (lm1, lm1, lm1)))
-        out.append((f"layer{L}.mix", (lm1, n, n)))
+        out.append((f"layer{L}.alpha", (2, lm1, lm1, lm1) if par == 2 else (lm1, lm1, lm1)))
+        out.append((f"layer{L}.mix", (par * lm1, n, n)))
         dims = [prev + n] + list(mc.latent_dims)
         for k in range(len(dims) - 1):
             out.append((f"layer{L}.mlp.W{k}", (dims[k], dims[k + 1])))
