@@ -197,6 +197,29 @@ def mlp_bytes_per_edge(mc):
     return out
 
 
+def tensor_flops_per_edge(mc, info):
+    """Algorithmic FP32 flops per edge of each tensor-track launch kind, summed
+    over the layers that launch it (timings are summed the same way): the
+    fused tables' non-zeros (one multiply-add per non-zero and channel), the
+    channel mixing (n^2 multiply-adds per mixed component) and the
+    environment products (one multiply-add per harmonic component and
+    channel).  Index arithmetic and the recomputation-free adjoint's
+    bookkeeping are not counted."""
+    n, D, nl = mc.n_tensor, (mc.l_max + 1) ** 2, mc.n_layers
+    nnz = [int(info.n_nonzero[k]) for k in range(nl)]
+    wout = [int(info.width[k]) for k in range(nl)]
+    mixed = [(wout[k] - (1 if wout[k] > D else 0)) if mc.channel_mix else 0 for k in range(nl)]
+    out = {"env": nl * 2 * D * n,
+           "tp_env_adjoint_final": 2 * nnz[-1] * n + 4 * D * n + (2 * nnz[-1] * n + 4 * D * n if nl == 1 else 0)}
+    if nl > 1:
+        out["tp_mix"] = sum(2 * nnz[k] * n + 2 * n * n * mixed[k] for k in range(nl - 1))
+        out["mix_adjoint"] = sum((2 * nnz[k + 1] * n if k + 1 < nl - 1 else 3 * D * n) + 2 * n * n * mixed[k]
+                                 for k in range(nl - 1))
+        out["tp_env_adjoint"] = sum(2 * nnz[k] * n + 4 * D * n + (2 * nnz[k] * n + 4 * D * n if k == 0 else 0)
+                                    for k in range(nl - 1))
+    return out
+
+
 def run_gpu(mc, s, w, precision, steps, warmup, want_kernel_times, autotune=True):
     import torch
     import paper_2304_10061_amd as P
@@ -270,6 +293,58 @@ def cpu_baseline(mc, s, w, n_centres):
             "kind": "oracle",
             "sample": f"{n_centres} random centres of the same box (their {int(np.sum(np.isin(nbr[0], cents)))} "
                       f"edges, energy + edge gradients in FP64), {t:.1f} s"}
+
+
+def deep_workload_line(steps, warmup, cpu_sample, no_cpu):
+    """The deeper tensor track (three layers, l_max 3: unnatural-parity
+    irreps and l = 3 harmonics) on the 3,000-atom water box."""
+    import paper_2304_10061_amd as P
+    import workloads as W
+    mc, s, w = W.deep_workload()
+    info = P.describe(P.config_from(mc))
+    bf = run_gpu(mc, s, w, HEADLINE_PREC, steps, warmup, want_kernel_times=True)
+    fp = run_gpu(mc, s, w, 0, max(3, steps // 2), min(2, warmup), want_kernel_times=True)
+    kms = bf["kernel_ms"]
+    macs = mlp_macs_per_edge(mc)
+    tfl = tensor_flops_per_edge(mc, info)
+    dom = max(kms, key=kms.get)
+    E = bf["edges"]
+    if dom in macs:
+        flops = 2.0 * macs[dom] * E * bf["kernel_launches"].get(dom, 1)
+        roof = {"kernel": dom, "bound": "mfma", "peak": BF16_PEAK_TFLOPS}
+    else:
+        flops = float(tfl.get(dom, 0)) * E
+        roof = {"kernel": dom, "bound": "alu", "peak": FP32_PEAK_TFLOPS}
+    achieved = flops / (kms[dom] * 1e-3) / 1e12
+    launches = max(1, bf["kernel_launches"].get(dom, 1))
+    roof.update({"achieved": achieved, "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": None,
+                 "flops_per_launch": flops / launches, "avg_launch_ms": kms[dom] / launches})
+    tensor = {k: {"ms": round(kms[k], 4), "tflops": float(tfl[k]) * E / (kms[k] * 1e-3) / 1e12}
+              for k in tfl if k in kms}
+    out = {
+        "metric": "atom-steps/s (E+forces), 3,000-atom water box, three-layer l_max 3 model",
+        "value": s.n_local / (bf["ms_per_step"] * 1e-3), "unit": "atom-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": bf["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "water-like periodic box: 3000 atoms, 31.1 A cube, H:O 2:1, jittered lattice "
+                               "+-0.4 A, r_c 4 A; Allegro l_max 3, 3 layers (unnatural-parity irreps in the "
+                               "middle layer), 32 tensor channels, latent MLP [128,128], edge MLP [128]; "
+                               "random weights",
+                   "atoms": int(s.n_local), "edges": int(E),
+                   "paths_per_layer": [int(info.n_paths[k]) for k in range(mc.n_layers)],
+                   "nonzeros_per_layer": [int(info.n_nonzero[k]) for k in range(mc.n_layers)],
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "tensor_track": tensor,
+        "fp32": {"value": s.n_local / (fp["ms_per_step"] * 1e-3), "ms_per_step": fp["ms_per_step"],
+                 "energy_bf16_minus_fp32_per_atom": (bf["energy"] - fp["energy"]) / s.n_local},
+        "kernel_ms": {k: round(v, 4) for k, v in sorted(kms.items(), key=lambda kv: -kv[1])},
+        "neighbors_ms": bf["neighbors_ms"], "workspace_GB": bf["workspace_GB"], "tiles": bf["tiles"],
+        "source_hash": kernel_source_hash(),
+    }
+    if not no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mc, s, w, min(cpu_sample, s.n_local))
+    return out
 
 
 MD_SIGMA = 0.02
@@ -390,8 +465,9 @@ def main():
                     help="centres of the box in the oracle timing sample (about 10 s on 16 cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 and single-rounded BF16 comparisons")
-    ap.add_argument("--workload", default="protein-box", choices=["protein-box", "subdomain", "clusters"],
-                    help="protein-box (default, the headline); subdomain / clusters run MD")
+    ap.add_argument("--workload", default="protein-box", choices=["protein-box", "subdomain", "clusters", "deep"],
+                    help="protein-box (default, the headline); subdomain / clusters run MD; deep = three-layer "
+                         "l_max 3 model on the 3,000-atom water box")
     ap.add_argument("--dt", type=float, default=1.0, help="MD time step (fs) for the MD workloads")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (counter calibration under rocprofv3 --pmc)")
@@ -407,6 +483,10 @@ def main():
               "(spatial decomposition across GPUs is not part of this build)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "deep":
+        print(json.dumps(deep_workload_line(args.steps, args.warmup, min(args.cpu_sample, 512),
+                                            args.no_cpu_baseline)), flush=True)
+        return
     if args.workload != "protein-box":
         print(json.dumps(md_workload(args.workload, args.steps, args.warmup, args.dt)), flush=True)
         return

@@ -74,11 +74,16 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  * MLP with one hidden layer and no nonlinearity, 8 Bessel functions with a
  * polynomial envelope, l_max = 2, full O(3)).
  *   n_species        number of atom types (one-hot width), 1..12, with 2 n_species + n_bessel <= 32
- *   n_bessel         radial basis size, 1..16
+ *   n_bessel         radial basis size, 1..16 (1..8 with l_max = 3)
  *   envelope_p       polynomial envelope exponent p (u(r_c) = u' = u'' = 0)
- *   l_max            1 or 2
- *   n_layers         1 or 2 Allegro (tensor product) layers
- *   n_tensor         tensor feature channels n: 8, 16, 32 or 64
+ *   l_max            1, 2 or 3
+ *   n_layers         1..4 Allegro (tensor product) layers.  With three or more
+ *                    layers the features of all but the last two layers carry
+ *                    both parities (section "Optimized tensor product": every
+ *                    path with p_out = p1 p2 is kept when it can still reach the
+ *                    scalar output), e.g. 1o x 1o -> 1e
+ *   n_tensor         tensor feature channels n: 8, 16, 32 or 64 (32 or 64 with
+ *                    l_max = 3 or three or more layers)
  *   twobody_dims     output widths of the two-body MLP (1..3 layers); the last
  *                    one is the latent width d
  *   latent_dims      output widths of each later latent MLP (1..3 layers); last = d
@@ -132,8 +137,10 @@ typedef struct {
 /* Host-side description of a configuration (no device work). */
 typedef struct {
   int64_t n_weights;          /* floats expected by allegro_create */
-  int32_t n_paths[2];         /* kept tensor-product paths per layer */
-  int32_t n_nonzero[2];       /* non-zeros of each layer's fused coupling table */
+  int32_t n_paths[4];         /* kept tensor-product paths per layer */
+  int32_t n_nonzero[4];       /* non-zeros of each layer's fused coupling table */
+  int32_t width[4];           /* strided components of each layer's output features
+                                 ((l_max+1)^2, twice that with both parities, 1 for the last) */
   int32_t dim;                /* (l_max+1)^2 strided components */
   int32_t latent;             /* latent width d */
 } AllegroInfo;
@@ -157,6 +164,12 @@ int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info);
  *                  [l1][l2][l_out] (raw path weights; unused entries ignored),
  *                  mix [l_max+1][n][n] indexed [l][v][u], mlp.W0..Wk with
  *                  fan_in of W0 = d + n ([x, scalar tensor features]);
+ *                  with three or more layers (both parities) alpha is
+ *                  [2][l_max+1]^3 indexed [s1][l1][l2][l_out] (s1 = 0 for a
+ *                  natural-parity input irrep (l1, (-1)^l1), 1 for the other
+ *                  parity; the output parity follows) and mix is
+ *                  [2 (l_max+1)][n][n] indexed [slot][v][u] (slot l for the
+ *                  natural-parity irrep of order l, l_max + 1 + l for the other);
  *                  edge.W0 [d][h], edge.W1 [h][1].
  *   species_scale  host [n_species] sigma (NULL = 1)
  *   species_shift  host [n_species] mu (NULL = 0)

@@ -44,8 +44,9 @@ class AllegroConfig(ctypes.Structure):
 
 
 class AllegroInfo(ctypes.Structure):
-    _fields_ = [("n_weights", ctypes.c_int64), ("n_paths", ctypes.c_int32 * 2),
-                ("n_nonzero", ctypes.c_int32 * 2), ("dim", ctypes.c_int32), ("latent", ctypes.c_int32)]
+    _fields_ = [("n_weights", ctypes.c_int64), ("n_paths", ctypes.c_int32 * 4),
+                ("n_nonzero", ctypes.c_int32 * 4), ("width", ctypes.c_int32 * 4), ("dim", ctypes.c_int32),
+                ("latent", ctypes.c_int32)]
 
 
 class AllegroError(RuntimeError):
@@ -65,6 +66,9 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} not found: build it with `python -m paper_2304_10061_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # rather than loading a second copy that torch's device setup would trip over
+    import torch  # noqa: F401
     lib = ctypes.CDLL(p)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.allegro_describe.argtypes = [ctypes.POINTER(AllegroConfig), ctypes.POINTER(AllegroInfo)]

@@ -23,6 +23,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # MFMA accumulators in ordinary VGPRs: avoids AGPR<->VGPR copies of
          # the accumulators around the GEMM loops
          "-mllvm", "-amdgpu-mfma-vgpr-form",
+         # the coupling tables of the larger patterns are evaluated at compile time
+         "-fconstexpr-steps=200000000",
          "-Wno-unused-result"]
 
 SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "mlp_fp32.hip", "mlp_bf16.hip", "mlp_bf16s.hip",

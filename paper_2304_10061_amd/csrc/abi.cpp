@@ -125,6 +125,11 @@ void make_packed(PackedMat& pm, const std::vector<double>& W, int K, int N, int 
 
 struct Validated {
   int S, nb, p, lmax, nl, n, d, dim, LW, h;
+  // irrep kinds (TpKind) of each layer's input and output features, their
+  // widths in strided components, and whether the weight file uses the
+  // parity-extended alpha / mixing layouts (models with unnatural irreps)
+  int in_kind[kMaxLayers], out_kind[kMaxLayers], w_in[kMaxLayers], w_out[kMaxLayers];
+  bool parity = false;
   std::vector<int> dims2b, dimsL;
   int64_t n_weights;
 };
@@ -140,9 +145,12 @@ Validated validate(const AllegroConfig* c) {
   REQUIRE(v.nb >= 1 && v.nb <= 16, "n_bessel must be in 1..16");
   REQUIRE(2 * v.S + v.nb <= 32, "2 n_species + n_bessel must be at most 32");
   REQUIRE(v.p >= 2 && v.p <= 12, "envelope_p must be in 2..12");
-  REQUIRE(v.lmax == 1 || v.lmax == 2, "l_max must be 1 or 2");
-  REQUIRE(v.nl == 1 || v.nl == 2, "n_layers must be 1 or 2 (deeper models need odd-parity paths)");
+  REQUIRE(v.lmax >= 1 && v.lmax <= 3, "l_max must be 1, 2 or 3");
+  REQUIRE(v.nl >= 1 && v.nl <= kMaxLayers, "n_layers must be 1..4");
   REQUIRE(pow2_in(v.n), "n_tensor must be 8, 16, 32 or 64");
+  REQUIRE((v.lmax <= 2 && v.nl <= 2) || v.n == 32 || v.n == 64,
+          "l_max 3 and models of 3 or more layers need n_tensor 32 or 64");
+  REQUIRE(v.lmax <= 2 || v.nb <= 8, "l_max 3 allows at most 8 Bessel functions");
   REQUIRE(c->n_twobody >= 1 && c->n_twobody <= 3, "n_twobody must be 1..3");
   REQUIRE(c->n_latent >= 1 && c->n_latent <= 3, "n_latent must be 1..3");
   REQUIRE(c->n_edge == 1, "edge MLP must have exactly one hidden layer");
@@ -171,6 +179,17 @@ Validated validate(const AllegroConfig* c) {
               "r_cut_pair entries must lie in (0, r_cut]");
   v.dim = (v.lmax + 1) * (v.lmax + 1);
   v.LW = (v.lmax + 1) * v.n;
+  // with three or more layers the first layer's cross-parity products (such as
+  // 1o x 1o -> 1e) reach the scalar output through a later layer, so the
+  // features of every layer but the last two hold both parities
+  for (int L = 0; L < v.nl; ++L) {
+    const bool last = L == v.nl - 1, penult = L == v.nl - 2;
+    v.in_kind[L] = (L == 0 || last) ? kNatural : kBothParities;
+    v.out_kind[L] = last ? kScalarOut : ((v.nl >= 3 && !penult) ? kBothParities : kNatural);
+    v.w_in[L] = kind_width(v.in_kind[L], v.lmax);
+    v.w_out[L] = kind_width(v.out_kind[L], v.lmax);
+  }
+  v.parity = v.nl >= 3;
   // weight count, in the documented order
   int64_t cnt = 0;
   int prev = 2 * v.S + v.nb;
@@ -179,8 +198,8 @@ Validated validate(const AllegroConfig* c) {
   const int L1 = v.lmax + 1;
   for (int L = 0; L < v.nl; ++L) {
     cnt += (int64_t)v.d * v.LW;                            // env
-    cnt += (int64_t)L1 * L1 * L1;                          // alpha
-    cnt += (int64_t)L1 * v.n * v.n;                        // mix
+    cnt += (int64_t)(v.parity ? 2 : 1) * L1 * L1 * L1;      // alpha
+    cnt += (int64_t)(v.parity ? 2 : 1) * L1 * v.n * v.n;    // mix
     prev = v.d + v.n;
     for (int w : v.dimsL) { cnt += (int64_t)prev * w; prev = w; }
   }
@@ -189,49 +208,88 @@ Validated validate(const AllegroConfig* c) {
   return v;
 }
 
-// Fused coupling-table values of one layer, in the compile-time pattern order.
-template <int LMAX, bool FINAL>
-std::vector<float> fused_values(const double* alpha_raw, int* nnz) {
-  using Pat = TpPattern<LMAX, FINAL>;
-  const int L1 = LMAX + 1;
-  // paths into each output l, and Frobenius norm of each path block
-  int per_out[3] = {0, 0, 0};
-  double norm2[3][3][3] = {};
-  for (int l1 = 0; l1 <= LMAX; ++l1)
-    for (int l2 = 0; l2 <= LMAX; ++l2)
-      for (int lo = 0; lo <= LMAX; ++lo) {
-        if (!path_kept(l1, l2, lo, LMAX, FINAL)) continue;
-        per_out[lo]++;
-        for (int a = l1 * l1; a < (l1 + 1) * (l1 + 1); ++a)
-          for (int b = l2 * l2; b < (l2 + 1) * (l2 + 1); ++b)
-            for (int c = lo * lo; c < (lo + 1) * (lo + 1); ++c) {
-              const double g = gaunt_raw(a, b, c);
-              norm2[l1][l2][lo] += g * g;
-            }
-      }
-  std::vector<float> out(Pat::NNZ);
-  for (int k = 0; k < Pat::NNZ; ++k) {
-    const TpEntry t = Pat::list.e[k];
-    const int l1 = l_of(t.a), l2 = l_of(t.b), lo = l_of(t.c);
-    const double al = alpha_raw[(l1 * L1 + l2) * L1 + lo] / std::sqrt((double)per_out[lo]);
-    out[k] = (float)(al * gaunt_raw(t.a, t.b, t.c) / std::sqrt(norm2[l1][l2][lo]));
-  }
-  *nnz = Pat::NNZ;
+// Paths of a layer with the given kinds, as (l1, s1, l2, l_out, s_out) with s = 0
+// for natural and 1 for unnatural parity.
+struct PathId { int l1, s1, l2, lo, so; };
+
+std::vector<PathId> layer_path_ids(int lmax, int in_kind, int out_kind) {
+  std::vector<PathId> out;
+  const int D = (lmax + 1) * (lmax + 1);
+  for (int s1 = 0; s1 < 2; ++s1)
+    for (int l1 = 0; l1 <= lmax; ++l1)
+      for (int l2 = 0; l2 <= lmax; ++l2)
+        for (int so = 0; so < 2; ++so)
+          for (int lo = 0; lo <= lmax; ++lo) {
+            // representative components: the path is kept iff they are
+            const int a = s1 * D + l1 * l1, b = l2 * l2, c = so * D + lo * lo;
+            if (path_kept(a, b, c, lmax, in_kind, out_kind)) out.push_back(PathId{l1, s1, l2, lo, so});
+          }
   return out;
 }
 
-std::vector<float> fused_values_rt(int lmax, bool final_layer, const double* alpha, int* nnz) {
-  if (lmax == 1) return final_layer ? fused_values<1, true>(alpha, nnz) : fused_values<1, false>(alpha, nnz);
-  return final_layer ? fused_values<2, true>(alpha, nnz) : fused_values<2, false>(alpha, nnz);
+// Fused coupling-table values of one layer, in the compile-time pattern order:
+// w_k = alpha_p / sqrt(P_out) * C_p[a, b, c] / |C_p|.
+template <class Pat>
+std::vector<float> fused_values(const double* alpha_raw, bool parity_layout) {
+  constexpr int LMAX = Pat::Lmax, L1 = LMAX + 1, D = Pat::DIM;
+  int per_out[2][kMaxLmax + 1] = {};
+  double norm2[2][kMaxLmax + 1][kMaxLmax + 1][kMaxLmax + 1] = {};
+  for (const PathId& p : layer_path_ids(LMAX, Pat::In, Pat::Out)) {
+    per_out[p.so][p.lo]++;
+    for (int a = p.l1 * p.l1; a < (p.l1 + 1) * (p.l1 + 1); ++a)
+      for (int b = p.l2 * p.l2; b < (p.l2 + 1) * (p.l2 + 1); ++b)
+        for (int c = p.lo * p.lo; c < (p.lo + 1) * (p.lo + 1); ++c) {
+          const double g = coupling_raw(a, b, c);
+          norm2[p.s1][p.l1][p.l2][p.lo] += g * g;
+        }
+  }
+  std::vector<float> out(Pat::NNZ);
+  for (int k = 0; k < Pat::NNZ; ++k) {
+    const TpEntry t = Pat::list.e[k];
+    const int s1 = t.a >= D, so = t.c >= D;
+    const int a = t.a - s1 * D, c = t.c - so * D;
+    const int l1 = l_of(a), l2 = l_of(t.b), lo = l_of(c);
+    const double raw = parity_layout ? alpha_raw[((s1 * L1 + l1) * L1 + l2) * L1 + lo] : alpha_raw[(l1 * L1 + l2) * L1 + lo];
+    const double al = raw / std::sqrt((double)per_out[so][lo]);
+    out[k] = (float)(al * coupling_raw(a, t.b, c) / std::sqrt(norm2[s1][l1][l2][lo]));
+  }
+  return out;
 }
 
-int count_paths(int lmax, bool final_layer) {
-  int c = 0;
-  for (int l1 = 0; l1 <= lmax; ++l1)
-    for (int l2 = 0; l2 <= lmax; ++l2)
-      for (int lo = 0; lo <= lmax; ++lo) c += path_kept(l1, l2, lo, lmax, final_layer) ? 1 : 0;
-  return c;
+template <int LMAX>
+std::vector<float> fused_values_l(int in, int out, const double* alpha, bool parity) {
+  if (in == kNatural) {
+    if (out == kScalarOut) return fused_values<TpPattern<LMAX, kNatural, kScalarOut>>(alpha, parity);
+    if (out == kNatural) return fused_values<TpPattern<LMAX, kNatural, kNatural>>(alpha, parity);
+    return fused_values<TpPattern<LMAX, kNatural, kBothParities>>(alpha, parity);
+  }
+  if (out == kNatural) return fused_values<TpPattern<LMAX, kBothParities, kNatural>>(alpha, parity);
+  return fused_values<TpPattern<LMAX, kBothParities, kBothParities>>(alpha, parity);
 }
+
+std::vector<float> fused_values_rt(int lmax, int in, int out, const double* alpha, bool parity) {
+  if (lmax == 1) return fused_values_l<1>(in, out, alpha, parity);
+  if (lmax == 2) return fused_values_l<2>(in, out, alpha, parity);
+  return fused_values_l<3>(in, out, alpha, parity);
+}
+
+int count_paths(int lmax, int in, int out) { return (int)layer_path_ids(lmax, in, out).size(); }
+
+template <int LMAX>
+int count_nonzeros_l(int in, int out) {
+  if (in == kNatural) {
+    if (out == kScalarOut) return TpPattern<LMAX, kNatural, kScalarOut>::NNZ;
+    if (out == kNatural) return TpPattern<LMAX, kNatural, kNatural>::NNZ;
+    return TpPattern<LMAX, kNatural, kBothParities>::NNZ;
+  }
+  if (out == kNatural) return TpPattern<LMAX, kBothParities, kNatural>::NNZ;
+  return TpPattern<LMAX, kBothParities, kBothParities>::NNZ;
+}
+
+int count_nonzeros(int lmax, int in, int out) {
+  return lmax == 1 ? count_nonzeros_l<1>(in, out) : (lmax == 2 ? count_nonzeros_l<2>(in, out) : count_nonzeros_l<3>(in, out));
+}
+
 
 struct Mlp {
   PackedMat fwd[kMaxMlpLayers], bwd[kMaxMlpLayers];
@@ -257,8 +315,9 @@ struct AllegroModel {
   std::string err;
   int device = 0;
 
-  Mlp twobody, latent[2];
-  PackedMat head0, head0T, env2, env2T;   // [embed0 | env1] and env2
+  Mlp twobody, latent[kMaxLayers];
+  PackedMat head0, head0T;                // [embed0 | env of layer 1] after the two-body MLP
+  PackedMat envH[kMaxLayers], envHT[kMaxLayers];   // env of layer L+1 after latent MLP L
   // ordered species-pair cutoffs (empty = r_cut for every pair): the host
   // copy, FP32 radii for the edge kernels, squared list radii for the list
   std::vector<double> rc_pair;
@@ -267,11 +326,11 @@ struct AllegroModel {
   // and the per-edge pair shares of the current chunk
   std::vector<int> znum;
   DevBuf zbl_tab, epair;
-  DevBuf mixF[2], mixB[2];                // packed FP32 mixing matrices per layer
+  DevBuf mixF[kMaxLayers], mixB[kMaxLayers];   // packed FP32 mixing matrices per layer and irrep slot
   int mix_stride = 0;
-  DevBuf tpw[2];                          // fused coupling non-zeros per layer
-  std::vector<float> tpw_host[2];
-  float tp_final[9] = {0};                // final-layer diagonal weights
+  DevBuf tpw[kMaxLayers];                 // fused coupling non-zeros per layer
+  std::vector<float> tpw_host[kMaxLayers];
+  float tp_final[16] = {0};               // final-layer diagonal weights
   DevBuf we, gconst, scale, shift;
   double c_norm = 1.0;
 
@@ -312,7 +371,11 @@ struct AllegroModel {
   std::vector<std::pair<size_t, std::pair<hipEvent_t, hipEvent_t>>> pending;
 
   // workspace
-  DevBuf eb, x[2], head0o, wenv2, V1, gam[2], eij, gxa, gxb, gTf, gs, ghead0, gw2, gT, gY, gu, gR;
+  // x[L]: input of layer L; wenv[L] (L >= 1): its environment weights; V[L]:
+  // output features of non-final layer L; gT[2]: dE/dT of consecutive
+  // non-final layers during the adjoint
+  DevBuf eb, x[kMaxLayers], head0o, wenv[kMaxLayers], V[kMaxLayers], gam[kMaxLayers], eij, gxa, gxb, gTf, gs,
+      ghead0, gw2, gT[2], gY, gu, gR;
   DevBuf ggam;   // dE/dGamma of the layer being differentiated [centres][dim][n]
   DevBuf zscr;   // hidden pre-activations of the 128-row backward MLP kernels
   DevBuf g_e, atom_e, partial;
@@ -380,12 +443,13 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   }
   build_mlp(m->twobody, Ws, dims, m->prec_two, m->prec_two);
   const std::vector<double> embed0 = slice(w, off, (int64_t)d * LW);
-  std::vector<double> env[2], alpha[2], mix[2];
-  std::vector<std::vector<double>> mlpW[2];
+  std::vector<double> env[kMaxLayers], alpha[kMaxLayers], mix[kMaxLayers];
+  std::vector<std::vector<double>> mlpW[kMaxLayers];
+  const int nslot = (v.parity ? 2 : 1) * L1;   // mixing matrices per layer
   for (int L = 0; L < v.nl; ++L) {
     env[L] = slice(w, off, (int64_t)d * LW);
-    alpha[L] = slice(w, off, (int64_t)L1 * L1 * L1);
-    mix[L] = slice(w, off, (int64_t)L1 * n * n);
+    alpha[L] = slice(w, off, (int64_t)(v.parity ? 2 : 1) * L1 * L1 * L1);
+    mix[L] = slice(w, off, (int64_t)nslot * n * n);
     int prev = d + n;
     for (int wd : v.dimsL) {
       mlpW[L].push_back(slice(w, off, (int64_t)prev * wd));
@@ -417,7 +481,8 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   for (int wd : v.dimsL) ldims.push_back(wd);
   for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, m->prec_lat_first, m->prec_lat_rest);
 
-  // heads: [embed0 | env1] after the two-body MLP, env2 after the first latent MLP
+  // heads: [embed0 | env of layer 1] after the two-body MLP, env of layer L+1
+  // after latent MLP L
   {
     std::vector<double> H((size_t)d * 2 * LW);
     for (int r = 0; r < d; ++r)
@@ -427,16 +492,16 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
       }
     make_packed(m->head0, H, d, 2 * LW, m->prec_two);
     make_packed(m->head0T, transpose(H, d, 2 * LW), 2 * LW, d, m->prec_two);
-    if (v.nl == 2) {
-      make_packed(m->env2, env[1], d, LW, m->prec_lat_rest);
-      make_packed(m->env2T, transpose(env[1], d, LW), LW, d, m->prec_lat_rest);
+    for (int L = 0; L + 1 < v.nl; ++L) {
+      make_packed(m->envH[L], env[L + 1], d, LW, m->prec_lat_rest);
+      make_packed(m->envHT[L], transpose(env[L + 1], d, LW), LW, d, m->prec_lat_rest);
     }
   }
   // channel mixing matrices of non-final layers (FP32): forward W[u][v] = M[v][u],
   // adjoint W[v][u] = M[v][u]
   for (int L = 0; L + 1 < v.nl; ++L) {
     std::vector<char> allF, allB;
-    for (int l = 0; l < L1; ++l) {
+    for (int l = 0; l < nslot; ++l) {
       std::vector<double> M(mix[L].begin() + (size_t)l * n * n, mix[L].begin() + (size_t)(l + 1) * n * n);
       std::vector<char> hf, hb;
       GemmB g;
@@ -452,13 +517,12 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   // fused coupling tables
   for (int L = 0; L < v.nl; ++L) {
     const bool fin = L == v.nl - 1;
-    int nnz = 0;
-    std::vector<float> vals = fused_values_rt(v.lmax, fin, alpha[L].data(), &nnz);
+    std::vector<float> vals = fused_values_rt(v.lmax, v.in_kind[L], v.out_kind[L], alpha[L].data(), v.parity);
     upload(m->tpw[L], vals.data(), vals.size() * sizeof(float));
     m->tpw_host[L] = vals;
     if (fin) {
       // final pattern entries are (a, a, 0) in ascending a
-      for (int k = 0; k < 9; ++k) m->tp_final[k] = k < nnz ? vals[k] : 0.0f;
+      for (int k = 0; k < 16; ++k) m->tp_final[k] = k < (int)vals.size() ? vals[k] : 0.0f;
     }
   }
   // folded edge-energy vector and sigma_Z-scaled copies (the constant dE/dx^{N_l})
@@ -490,7 +554,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   for (int L = 0; L < v.nl; ++L) {
     MlpArgs q;
     q.d = d; q.n = n; q.w = m->latent[L].view();
-    if (L + 1 < v.nl) { q.head = m->env2.g; q.head_bwd = m->env2T.g; }
+    if (L + 1 < v.nl) { q.head = m->envH[L].g; q.head_bwd = m->envHT[L].g; }
     REQUIRE(mlp_lds_bytes(q, m->prec_lat, false) != (size_t)-1 &&
                 mlp_lds_bytes(q, m->prec_lat, true) != (size_t)-1,
             "latent MLP too wide for the fused kernel");
@@ -500,7 +564,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
 template <class T> T* ptr(const DevBuf& b, int64_t off = 0) { return b.as<T>() + off; }
 
 void set_tpw(TensorArgs& t, const std::vector<float>& v) {
-  for (size_t k = 0; k < v.size() && k < 83; ++k) t.tpw_v[k] = v[k];
+  for (size_t k = 0; k < v.size() && k < (size_t)kTpwArgs; ++k) t.tpw_v[k] = v[k];
 }
 
 // Runs `launch` and, when timing is on, brackets it with events on `s`.
@@ -721,11 +785,16 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   m->eb.ensure(Ec * kEB * f);
   for (int L = 0; L < v.nl; ++L) m->x[L].ensure(Ec * v.d * f);
   m->head0o.ensure(Ec * 2 * v.LW * f);
-  if (v.nl == 2) {
-    m->wenv2.ensure(Ec * v.LW * f);
-    m->V1.ensure(Ec * v.dim * v.n * f);
+  if (v.nl >= 2) {
+    int wmax = 0;
+    for (int L = 0; L + 1 < v.nl; ++L) {
+      m->wenv[L + 1].ensure(Ec * v.LW * f);
+      m->V[L].ensure(Ec * v.w_out[L] * v.n * f);
+      wmax = std::max(wmax, v.w_out[L]);
+    }
     m->gw2.ensure(Ec * v.LW * f);
-    m->gT.ensure(Ec * v.dim * v.n * f);
+    m->gT[0].ensure(Ec * wmax * v.n * f);
+    if (v.nl >= 3) m->gT[1].ensure(Ec * wmax * v.n * f);
     m->gxb.ensure(Ec * v.d * f);
     m->gs.ensure(Ec * v.n * f);
   }
@@ -735,7 +804,7 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   m->gxa.ensure(Ec * v.d * f);
   m->gTf.ensure(Ec * v.n * f);
   m->ghead0.ensure(Ec * 2 * v.LW * f);
-  m->gY.ensure(Ec * 9 * f);
+  m->gY.ensure(Ec * gy_width(v.lmax) * f);
   m->gu.ensure(Ec * f);
   m->gR.ensure(Ec * v.nb * f);
   if (!m->znum.empty()) m->epair.ensure(Ec * f);
@@ -798,28 +867,35 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     timed(m, "env", s, [&] { return launch_env(t1, s); });
 
     const VSrc v_a0{ptr<float>(m->head0o), 2 * LW, 1};
-    const VSrc v_1{ptr<float>(m->V1), dim * n, 0};
     MlpArgs mf = base;
     mf.kind = kLatentFinal; mf.we = ptr<float>(m->we); mf.g_const = ptr<float>(m->gconst);
-    for (int k = 0; k < 9; ++k) mf.tp_w[k] = m->tp_final[k];
+    for (int k = 0; k < 16; ++k) mf.tp_w[k] = m->tp_final[k];
     mf.eij = ptr<float>(m->eij);
-    MlpArgs m1 = base;
-    if (v.nl == 2) {
-      TensorArgs t1m = t1;
-      t1m.v = v_a0; t1m.tile = m->tt_choice[0]; t1m.tpw = ptr<float>(m->tpw[0]); set_tpw(t1m, m->tpw_host[0]); t1m.mixB = m->mixF[0].p; t1m.v_out = ptr<float>(m->V1);
-      timed(m, "tp_mix", s, [&] { return launch_tp_mix(t1m, false, s); });
-      m1.kind = kLatent; m1.w = m->latent[0].view(); m1.head = m->env2.g; m1.head_bwd = m->env2T.g;
-      m1.x_prev = ptr<float>(m->x[0]); m1.s_in = ptr<float>(m->V1); m1.s_ld = dim * n;
-      m1.x_out = ptr<float>(m->x[1]); m1.head_out = ptr<float>(m->wenv2);
-      m1.tm = m->tm_choice[1];
-      timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(m1, m->prec_lat, s); });
-      TensorArgs t2 = tb;
-      t2.w_env = ptr<float>(m->wenv2); t2.ld_w = LW; t2.gam = ptr<float>(m->gam[1]);
-      timed(m, "env", s, [&] { return launch_env(t2, s); });
-      mf.w = m->latent[1].view(); mf.x_prev = ptr<float>(m->x[1]); mf.tp_v = v_1; mf.tp_gam = ptr<float>(m->gam[1]);
-    } else {
-      mf.w = m->latent[0].view(); mf.x_prev = ptr<float>(m->x[0]); mf.tp_v = v_a0; mf.tp_gam = ptr<float>(m->gam[0]);
+    // non-final layers: tensor product + mixing, then the latent MLP that
+    // produces the next layer's scalars and environment weights
+    MlpArgs ml[kMaxLayers];
+    VSrc vin = v_a0;
+    for (int L = 0; L + 1 < v.nl; ++L) {
+      TensorArgs tl = tb;
+      tl.in_kind = v.in_kind[L]; tl.out_kind = v.out_kind[L];
+      tl.v = vin; tl.gam = ptr<float>(m->gam[L]); tl.tile = m->tt_choice[0];
+      tl.tpw = ptr<float>(m->tpw[L]); set_tpw(tl, m->tpw_host[L]); tl.mixB = m->mixF[L].p;
+      tl.v_out = ptr<float>(m->V[L]);
+      timed(m, "tp_mix", s, [&] { return launch_tp_mix(tl, false, s); });
+      MlpArgs& mL = ml[L];
+      mL = base;
+      mL.kind = kLatent; mL.w = m->latent[L].view(); mL.head = m->envH[L].g; mL.head_bwd = m->envHT[L].g;
+      mL.x_prev = ptr<float>(m->x[L]); mL.s_in = ptr<float>(m->V[L]); mL.s_ld = v.w_out[L] * n;
+      mL.x_out = ptr<float>(m->x[L + 1]); mL.head_out = ptr<float>(m->wenv[L + 1]);
+      mL.tm = m->tm_choice[1];
+      timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(mL, m->prec_lat, s); });
+      TensorArgs te = tb;
+      te.w_env = ptr<float>(m->wenv[L + 1]); te.ld_w = LW; te.gam = ptr<float>(m->gam[L + 1]);
+      timed(m, "env", s, [&] { return launch_env(te, s); });
+      vin = VSrc{ptr<float>(m->V[L]), v.w_out[L] * n, 0};
     }
+    mf.w = m->latent[v.nl - 1].view(); mf.x_prev = ptr<float>(m->x[v.nl - 1]); mf.tp_v = vin;
+    mf.tp_gam = ptr<float>(m->gam[v.nl - 1]);
     mf.tm = m->tm_choice[2];
     mf.tp_out = ptr<float>(m->gTf);   // the final scalars, read back by the backward pass
     timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, m->prec_lat, s); });
@@ -843,35 +919,55 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     tf.g_t = ptr<float>(m->gTf); tf.g_Y = ptr<float>(m->gY); tf.gy_accum = 0; tf.g_gam = ptr<float>(m->ggam);
     tf.tpw = ptr<float>(m->tpw[v.nl - 1]);
     set_tpw(tf, m->tpw_host[v.nl - 1]);
-    if (v.nl == 2) {
-      tf.v = v_1; tf.gam = ptr<float>(m->gam[1]); tf.w_env = ptr<float>(m->wenv2); tf.ld_w = LW;
-      tf.g_w = ptr<float>(m->gw2); tf.ld_gw = LW;
+    tf.v = vin; tf.gam = ptr<float>(m->gam[v.nl - 1]);
+    if (v.nl >= 2) {
+      tf.w_env = ptr<float>(m->wenv[v.nl - 1]); tf.ld_w = LW; tf.g_w = ptr<float>(m->gw2); tf.ld_gw = LW;
     } else {
-      tf.v = v_a0; tf.gam = ptr<float>(m->gam[0]); tf.w_env = ptr<float>(m->head0o) + LW; tf.ld_w = 2 * LW;
+      tf.w_env = ptr<float>(m->head0o) + LW; tf.ld_w = 2 * LW;
       tf.g_w = ptr<float>(m->ghead0) + LW; tf.ld_gw = 2 * LW; tf.g_a0 = ptr<float>(m->ghead0);
     }
     timed(m, "tp_env_adjoint_final", s, [&] { return launch_tp_env_adjoint(tf, true, s); });
 
-    float* gx_two = ptr<float>(m->gxa);
-    if (v.nl == 2) {
-      m1.g_head = ptr<float>(m->gw2); m1.g_x = ptr<float>(m->gxa); m1.g_xprev = ptr<float>(m->gxb);
-      m1.g_s = ptr<float>(m->gs); m1.g_u = ptr<float>(m->gu); m1.gu_accum = 1;
-      m1.g_store = m1.g_xprev; m1.act_scratch = m->zscr.p;
-      m1.tm = m->tm_choice[4];
-      timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(m1, m->prec_lat, s); });
+    // non-final layers, last to first: latent-MLP adjoint (dE/dx of the layer's
+    // input, dE/ds of its scalars), mixing adjoint (dE/dT from the next layer),
+    // tensor-product / environment adjoint (dE/dw of its environment weights)
+    float* gx_cur = ptr<float>(m->gxa);     // dE/dx of the input of layer L+1
+    float* gx_other = ptr<float>(m->gxb);
+    const float* gt_next = ptr<float>(m->gTf);
+    int slot = 0;
+    for (int L = v.nl - 2; L >= 0; --L) {
+      MlpArgs& mL = ml[L];
+      mL.g_head = ptr<float>(m->gw2); mL.g_x = gx_cur; mL.g_xprev = gx_other;
+      mL.g_s = ptr<float>(m->gs); mL.g_u = ptr<float>(m->gu); mL.gu_accum = 1;
+      mL.g_store = mL.g_xprev; mL.act_scratch = m->zscr.p;
+      mL.tm = m->tm_choice[4];
+      timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(mL, m->prec_lat, s); });
+      std::swap(gx_cur, gx_other);
       TensorArgs tm = tb;
-      tm.g_tnext = ptr<float>(m->gTf); tm.gam_next = ptr<float>(m->gam[1]);
-      for (int k = 0; k < 9; ++k) tm.tp_wnext[k] = m->tp_final[k];
-      tm.g_s = ptr<float>(m->gs); tm.tile = m->tt_choice[1]; tm.mixB = m->mixB[0].p; tm.g_tout = ptr<float>(m->gT);
+      tm.next_in = v.in_kind[L + 1]; tm.next_out = v.out_kind[L + 1];
+      tm.g_tnext = gt_next; tm.gam_next = ptr<float>(m->gam[L + 1]);
+      for (int k = 0; k < 16; ++k) tm.tp_wnext[k] = m->tp_final[k];
+      tm.tpw = ptr<float>(m->tpw[L + 1]); set_tpw(tm, m->tpw_host[L + 1]);
+      tm.g_s = ptr<float>(m->gs); tm.tile = m->tt_choice[1]; tm.mixB = m->mixB[L].p;
+      tm.g_tout = ptr<float>(m->gT[slot]);
       timed(m, "mix_adjoint", s, [&] { return launch_mix_adjoint(tm, s); });
-      TensorArgs t1b = tb;
-      t1b.g_t = ptr<float>(m->gT); t1b.v = v_a0; t1b.gam = ptr<float>(m->gam[0]);
-      t1b.w_env = ptr<float>(m->head0o) + LW; t1b.ld_w = 2 * LW; t1b.tpw = ptr<float>(m->tpw[0]); set_tpw(t1b, m->tpw_host[0]);
-      t1b.g_w = ptr<float>(m->ghead0) + LW; t1b.ld_gw = 2 * LW; t1b.g_a0 = ptr<float>(m->ghead0);
-      t1b.g_Y = ptr<float>(m->gY); t1b.gy_accum = 1; t1b.g_gam = ptr<float>(m->ggam);
-      timed(m, "tp_env_adjoint", s, [&] { return launch_tp_env_adjoint(t1b, false, s); });
-      gx_two = ptr<float>(m->gxb);
+      TensorArgs tl = tb;
+      tl.in_kind = v.in_kind[L]; tl.out_kind = v.out_kind[L];
+      tl.g_t = ptr<float>(m->gT[slot]); tl.tpw = ptr<float>(m->tpw[L]); set_tpw(tl, m->tpw_host[L]);
+      tl.g_Y = ptr<float>(m->gY); tl.gy_accum = 1; tl.g_gam = ptr<float>(m->ggam);
+      tl.gam = ptr<float>(m->gam[L]);
+      if (L == 0) {
+        tl.v = v_a0; tl.w_env = ptr<float>(m->head0o) + LW; tl.ld_w = 2 * LW;
+        tl.g_w = ptr<float>(m->ghead0) + LW; tl.ld_gw = 2 * LW; tl.g_a0 = ptr<float>(m->ghead0);
+      } else {
+        tl.v = VSrc{ptr<float>(m->V[L - 1]), v.w_out[L - 1] * n, 0};
+        tl.w_env = ptr<float>(m->wenv[L]); tl.ld_w = LW; tl.g_w = ptr<float>(m->gw2); tl.ld_gw = LW;
+      }
+      timed(m, "tp_env_adjoint", s, [&] { return launch_tp_env_adjoint(tl, false, s); });
+      gt_next = ptr<float>(m->gT[slot]);
+      slot ^= 1;
     }
+    float* gx_two = gx_cur;
     m0.g_head = ptr<float>(m->ghead0); m0.g_x = gx_two; m0.g_u = ptr<float>(m->gu); m0.gu_accum = 1;
     m0.g_R = ptr<float>(m->gR);
     m0.g_store = gx_two; m0.act_scratch = m->zscr.p;   // the two-body backward reuses its g_x rows
@@ -1123,14 +1219,15 @@ int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info) {
       info->n_weights = v.n_weights;
       info->dim = v.dim;
       info->latent = v.d;
-      for (int L = 0; L < 2; ++L) {
+      for (int L = 0; L < kMaxLayers; ++L) {
         info->n_paths[L] = 0;
         info->n_nonzero[L] = 0;
+        info->width[L] = 0;
       }
       for (int L = 0; L < v.nl; ++L) {
-        const bool fin = L == v.nl - 1;
-        info->n_paths[L] = count_paths(v.lmax, fin);
-        info->n_nonzero[L] = tp_list(v.lmax, fin).n;
+        info->n_paths[L] = count_paths(v.lmax, v.in_kind[L], v.out_kind[L]);
+        info->n_nonzero[L] = count_nonzeros(v.lmax, v.in_kind[L], v.out_kind[L]);
+        info->width[L] = v.w_out[L];
       }
     }
     return ALLEGRO_OK;
@@ -1304,9 +1401,10 @@ int64_t allegro_workspace_bytes(const AllegroModel* m) {
   const DevBuf* bufs[] = {&m->ei, &m->ej, &m->es, &m->row_ptr, &m->rrow_ptr, &m->redge, &m->keys, &m->cell_of,
                           &m->img, &m->cell_count, &m->cell_start, &m->cell_cursor, &m->cell_atoms, &m->count,
                           &m->rcount, &m->rcursor, &m->bbox, &m->scan_tmp, &m->eb, &m->x[0], &m->x[1],
-                          &m->head0o, &m->wenv2, &m->V1, &m->gam[0], &m->gam[1], &m->eij, &m->gxa, &m->gxb,
-                          &m->gTf, &m->gs, &m->ghead0, &m->gw2, &m->gT, &m->gY, &m->gu, &m->gR, &m->g_e,
-                          &m->atom_e, &m->partial, &m->chunk_rp};
+                          &m->x[2], &m->x[3], &m->head0o, &m->wenv[1], &m->wenv[2], &m->wenv[3], &m->V[0],
+                          &m->V[1], &m->V[2], &m->gam[0], &m->gam[1], &m->gam[2], &m->gam[3], &m->eij,
+                          &m->gxa, &m->gxb, &m->gTf, &m->gs, &m->ghead0, &m->gw2, &m->gT[0], &m->gT[1], &m->gY,
+                          &m->gu, &m->gR, &m->g_e, &m->atom_e, &m->partial, &m->chunk_rp};
   int64_t s = 0;
   for (const DevBuf* b : bufs) s += (int64_t)b->bytes;
   return s;

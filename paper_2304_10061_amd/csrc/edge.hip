@@ -7,7 +7,9 @@
 //   u(t) = 1 - (p+1)(p+2)/2 t^p + p(p+2) t^(p+1) - p(p+1)/2 t^(p+2),  t = d / r_c
 //   R_n  = sqrt(2/r_c) sin(n pi d / r_c) / d * u,   n = 1..n_bessel
 //   Y    = real harmonics with sum_m Y_lm^2 = 2l+1:
-//          1;  sqrt3 (y, z, x);  sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2-1), sqrt15 xz, sqrt15/2 (x^2-y^2)
+//          1;  sqrt3 (y, z, x);  sqrt15 xy, sqrt15 yz, sqrt5/2 (3z^2-1), sqrt15 xz, sqrt15/2 (x^2-y^2);
+//          sqrt70/4 y(3x^2-y^2), sqrt105 xyz, sqrt42/4 y(5z^2-1), sqrt7/2 z(5z^2-3),
+//          sqrt42/4 x(5z^2-1), sqrt105/2 z(x^2-y^2), sqrt70/4 x(x^2-3y^2)
 // The edge vector r = (x_j - x_i) + s L is formed in FP64 and then rounded to
 // FP32; the basis is FP32.
 //
@@ -31,12 +33,27 @@ constexpr float kPi = 3.14159265358979323846f;
 constexpr float kS3 = 1.7320508075688772f;
 constexpr float kS5 = 2.23606797749979f;
 constexpr float kS15 = 3.872983346207417f;
+constexpr float kS7 = 2.6457513110645907f;
+constexpr float kS42 = 6.48074069840786f;
+constexpr float kS70 = 8.366600265340756f;
+constexpr float kS105 = 10.246950765959598f;
 
 __device__ __forceinline__ void sh9(float x, float y, float z, float* Y) {
   Y[0] = 1.0f;
   Y[1] = kS3 * y; Y[2] = kS3 * z; Y[3] = kS3 * x;
   Y[4] = kS15 * x * y; Y[5] = kS15 * y * z; Y[6] = 0.5f * kS5 * (3.0f * z * z - 1.0f);
   Y[7] = kS15 * x * z; Y[8] = 0.5f * kS15 * (x * x - y * y);
+}
+
+__device__ __forceinline__ void sh3(float x, float y, float z, float* Y) {
+  const float zz = 5.0f * z * z;
+  Y[0] = 0.25f * kS70 * y * (3.0f * x * x - y * y);
+  Y[1] = kS105 * x * y * z;
+  Y[2] = 0.25f * kS42 * y * (zz - 1.0f);
+  Y[3] = 0.5f * kS7 * z * (zz - 3.0f);
+  Y[4] = 0.25f * kS42 * x * (zz - 1.0f);
+  Y[5] = 0.5f * kS105 * z * (x * x - y * y);
+  Y[6] = 0.25f * kS70 * x * (x * x - 3.0f * y * y);
 }
 
 __device__ __forceinline__ float ipow(float t, int p) {
@@ -98,6 +115,11 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
   sh9(x, y, z, Y);
   const int dim = (a.l_max + 1) * (a.l_max + 1);
   for (int c = 0; c < 9; ++c) o[c] = c < dim ? Y[c] : 0.0f;
+  if (a.l_max >= 3) {
+    float Y3[7];
+    sh3(x, y, z, Y3);
+    for (int c = 0; c < 7; ++c) o[eb_y(9 + c)] = Y3[c];
+  }
   o[kEB_U] = u;
   o[kEB_D] = d;
   o[kEB_RHAT] = x; o[kEB_RHAT + 1] = y; o[kEB_RHAT + 2] = z;
@@ -109,7 +131,8 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
     a.e_pair[e] = 0.5f * Ez * u;
   }
   const float pref = sqrtf(2.0f / rc);
-  for (int k = 0; k < 16; ++k) {
+  const int nr = a.l_max >= 3 ? kEB_Y3 - kEB_R : 16;   // radial slots of the record
+  for (int k = 0; k < nr; ++k) {
     float v = 0.0f;
     if (k < a.n_bessel) v = pref * sinf((float)(k + 1) * kPi * d / rc) / d * u;
     o[kEB_R + k] = v;
@@ -148,7 +171,7 @@ __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
     zbl_pair(a.zbl, a.n_species, zi, zj, d, &Ez, &dEz);
     gd += 0.5f * (dEz * u + Ez * du);
   }
-  const float* gY = a.g_Y + e * 9;
+  const float* gY = a.g_Y + e * gy_width(a.l_max);
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
   if (a.l_max >= 1) {
     gx += kS3 * gY[3]; gy += kS3 * gY[1]; gz += kS3 * gY[2];
@@ -157,6 +180,17 @@ __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
     gx += kS15 * (y * gY[4] + z * gY[7] + x * gY[8]);
     gy += kS15 * (x * gY[4] + z * gY[5] - y * gY[8]);
     gz += kS15 * (y * gY[5] + x * gY[7]) + 3.0f * kS5 * z * gY[6];
+  }
+  if (a.l_max >= 3) {   // Cartesian gradients of the l = 3 forms above
+    const float* g3 = gY + 9;
+    const float zz = 5.0f * z * z;
+    const float a70 = 0.25f * kS70, a42 = 0.25f * kS42, a7 = 0.5f * kS7;
+    gx += a70 * 6.0f * x * y * g3[0] + kS105 * y * z * g3[1] + a42 * (zz - 1.0f) * g3[4] +
+          kS105 * x * z * g3[5] + a70 * 3.0f * (x * x - y * y) * g3[6];
+    gy += a70 * 3.0f * (x * x - y * y) * g3[0] + kS105 * x * z * g3[1] + a42 * (zz - 1.0f) * g3[2] -
+          kS105 * y * z * g3[5] - a70 * 6.0f * x * y * g3[6];
+    gz += kS105 * x * y * g3[1] + a42 * 10.0f * y * z * g3[2] + a7 * (15.0f * z * z - 3.0f) * g3[3] +
+          a42 * 10.0f * x * z * g3[4] + 0.5f * kS105 * (x * x - y * y) * g3[5];
   }
   const float dot = gx * x + gy * y + gz * z;
   const float inv = 1.0f / d;

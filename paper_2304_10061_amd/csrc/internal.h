@@ -3,13 +3,16 @@
 //
 // Edge-major layouts in HBM (E = edges of the current chunk, rows ordered by
 // centre, each centre's neighbours sorted by (j, shift)):
-//   eb      [E][kEB]     float  edge record: Y[0..8], u, d, rhat[3], Z_i, Z_j, R[16..31]
+//   eb      [E][kEB]     float  edge record: Y[0..8], u, d, rhat[3], Z_i, Z_j, R[16..31];
+//                               with l_max = 3 (at most 8 radial functions) the
+//                               l = 3 harmonics Y[9..15] sit in slots 24..30
 //   x^L     [E][d]       float  latent (scalar-track) features, the residual stream
 //   head    [E][H]       float  outputs of the linear map that follows an MLP
 //                               (after the two-body MLP: [a0 | w^1], each
 //                               (l_max+1) n wide, column l n + u)
-//   V^L     [E][dim][n]  float  tensor features, component-major: the n channels
-//                               of one strided component are contiguous
+//   V^L     [E][w][n]    float  tensor features, component-major: the n channels
+//                               of one strided component are contiguous; w = dim
+//                               (natural parity only) or 2 dim (both parities)
 //   Gamma^L [N][dim][n]  float  per-centre environment sums
 // dim = (l_max+1)^2.
 #pragma once
@@ -25,7 +28,16 @@ constexpr int kEB_D = 10;
 constexpr int kEB_RHAT = 11;
 constexpr int kEB_ZI = 14;  // species of the centre and of the neighbour (small integers held
 constexpr int kEB_ZJ = 15;  // exactly as floats), so that edge-row readers need no index chase
-constexpr int kEB_R = 16;   // radial basis R_n = B_n u, n < 16
+constexpr int kEB_R = 16;   // radial basis R_n = B_n u, n < 16 (n < 8 with l_max = 3)
+constexpr int kEB_Y3 = 24;  // Y[9..15] when l_max = 3
+
+// Record slot of harmonic component c.
+__host__ __device__ constexpr int eb_y(int c) { return c < 9 ? c : kEB_Y3 + (c - 9); }
+// Row stride of the dE/dY buffers.
+__host__ __device__ constexpr int gy_width(int l_max) { return l_max >= 3 ? 16 : 9; }
+
+constexpr int kMaxLayers = 4;
+constexpr int kTpwArgs = 83;  // fused-table non-zeros passed by value (larger tables are read from memory)
 
 constexpr int kMaxMlpLayers = 3;
 
@@ -76,7 +88,7 @@ struct MlpArgs {
   const float* tp_gam = nullptr;  // Gamma [centres][dim][n]
   float* tp_out = nullptr;        // forward: receives those scalars [E][n] (optional); the
                                   // backward reads them back through s_in (s_ld = n)
-  float tp_w[9] = {0};            // diagonal coupling weight of each component
+  float tp_w[16] = {0};           // diagonal coupling weight of each component
   float res_scale = 0.70710678118654752f;
   // forward outputs
   float* x_out = nullptr;         // [E][d]
@@ -113,7 +125,7 @@ struct EdgeArgs {
   int p = 6, n_bessel = 8, l_max = 2;
   float* eb = nullptr;
   // backward
-  const float* g_Y = nullptr;     // [E][9]
+  const float* g_Y = nullptr;     // [E][gy_width(l_max)]
   const float* g_R = nullptr;     // [E][n_bessel]
   const float* g_u = nullptr;     // [E]
   float* g_e = nullptr;           // [E][3]
@@ -124,6 +136,8 @@ struct TensorArgs {
   int tile = 0;                   // edges per tile of the edge-tile kernels (16 or 32; 0 = 32)
   int n_centres = 0;
   int n = 0, l_max = 0;
+  int in_kind = 1, out_kind = 1;  // irrep kinds (TpKind) of this layer's input and output features
+  int next_in = 1, next_out = 0;  // kinds of the next layer (channel-mixing adjoint)
   const int32_t* row_ptr = nullptr;  // [n_centres+1], chunk-relative
   const int32_t* ei = nullptr;       // centre per edge (global atom index)
   int centre_base = 0;               // first centre of the chunk
@@ -134,23 +148,25 @@ struct TensorArgs {
   float* gam = nullptr;           // [n_centres][dim][n]
   VSrc v;                         // tensor-product input
   const float* tpw = nullptr;     // device: non-zero weights of the fused table
-  float tpw_v[83] = {0};          // the same values, passed by value (kernel argument)
-  const void* mixB = nullptr;     // packed FP32 mixing matrices, one GemmB block per l
-  int mix_stride = 0;             // floats between consecutive l blocks
+  float tpw_v[kTpwArgs] = {0};    // the same values, passed by value (kernel argument)
+  const void* mixB = nullptr;     // packed FP32 mixing matrices, one GemmB block per irrep slot
+                                  // (natural l = 0..l_max, then unnatural l = 0..l_max)
+  int mix_stride = 0;             // floats between consecutive blocks
   int channel_mix = 1;
   float mix_scale = 1.0f;         // 1/sqrt(n)
-  float* v_out = nullptr;         // [E][dim][n]
+  float* v_out = nullptr;         // [E][w_out][n]
   // backward
   const float* g_t = nullptr;     // [E][dout][n]
   const float* g_s = nullptr;     // [E][n] gradient w.r.t. scalar outputs (component 0)
-  const float* gam_next = nullptr;  // final layer Gamma (to rebuild dE/dV)
-  const float* g_tnext = nullptr;   // final-layer dE/dT [E][n]
-  float tp_wnext[9] = {0};
-  float* g_tout = nullptr;        // [E][dim][n]
+  const float* gam_next = nullptr;  // next layer's Gamma (to rebuild dE/dV)
+  const float* g_tnext = nullptr;   // next layer's dE/dT [E][w_next_out][n]
+  const float* tpw_next = nullptr;  // next layer's fused-table non-zeros (device)
+  float tp_wnext[16] = {0};         // final next layer: its diagonal weights
+  float* g_tout = nullptr;        // [E][w_out][n]
   float* g_w = nullptr;           // [E][(l_max+1) n] at row stride ld_gw
   int ld_gw = 0;
   float* g_a0 = nullptr;          // [E][(l_max+1) n] at row stride ld_gw (layer 1 only)
-  float* g_Y = nullptr;           // [E][9]
+  float* g_Y = nullptr;           // [E][gy_width(l_max)]
   int gy_accum = 0;
   float* g_gam = nullptr;         // [n_centres][dim][n] dE/dGamma (without the factor c)
 };

@@ -299,31 +299,40 @@ __device__ __forceinline__ void zero_cols(typename PT<PREC>::T* X, int ldx, int 
 
 // Final-layer scalar tensor product for channels u..u+3 of edge e:
 // T[u] = sum_c w_c V[c][u] Gamma[c][u] (V either stored or the rank-1
-// first-layer form a0[l(c)][u] Y_c).
+// first-layer form a0[l(c)][u] Y_c), over components C0 .. C0+NC-1 (those at
+// or beyond dim weigh zero).
+template <int C0, int NC>
+__device__ __forceinline__ void final_tp_part(const MlpArgs& a, int e, int dim, uint32_t gbase, uint32_t vbase,
+                                              float4& v) {
+  float4 g[NC], vv[NC];
+  float wy[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int c = C0 + k;
+    const bool on = c < dim;
+    const int cc = on ? c : 0;
+    const int l = c == 0 ? 0 : (c < 4 ? 1 : (c < 9 ? 2 : 3));
+    g[k] = ld4(a.tp_gam, gbase + cc * a.n);
+    vv[k] = ld4(a.tp_v.p, vbase + (a.tp_v.from_a0 ? (on ? l : 0) : cc) * a.n);
+    wy[k] = on ? a.tp_w[c] * (a.tp_v.from_a0 ? a.eb[(uint32_t)e * kEB + eb_y(cc)] : 1.0f) : 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const float w = wy[k];
+    v.x = fmaf(w * vv[k].x, g[k].x, v.x);
+    v.y = fmaf(w * vv[k].y, g[k].y, v.y);
+    v.z = fmaf(w * vv[k].z, g[k].z, v.z);
+    v.w = fmaf(w * vv[k].w, g[k].w, v.w);
+  }
+}
+
 __device__ __forceinline__ float4 final_tp4(const MlpArgs& a, int e, int centre, int u) {
   const int dim = (a.l_max + 1) * (a.l_max + 1);
   const uint32_t gbase = (uint32_t)(centre - a.centre_base) * dim * a.n + u;
   const uint32_t vbase = (uint32_t)e * a.tp_v.ld + u;
-  float4 g[9], vv[9];
-  float wy[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    const bool on = c < dim;               // components beyond dim weigh zero
-    const int cc = on ? c : 0;
-    const int l = c == 0 ? 0 : (c < 4 ? 1 : 2);
-    g[c] = ld4(a.tp_gam, gbase + cc * a.n);
-    vv[c] = ld4(a.tp_v.p, vbase + (a.tp_v.from_a0 ? (on ? l : 0) : cc) * a.n);
-    wy[c] = on ? a.tp_w[c] * (a.tp_v.from_a0 ? a.eb[(uint32_t)e * kEB + cc] : 1.0f) : 0.0f;
-  }
   float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    const float w = wy[c];
-    v.x = fmaf(w * vv[c].x, g[c].x, v.x);
-    v.y = fmaf(w * vv[c].y, g[c].y, v.y);
-    v.z = fmaf(w * vv[c].z, g[c].z, v.z);
-    v.w = fmaf(w * vv[c].w, g[c].w, v.w);
-  }
+  final_tp_part<0, 9>(a, e, dim, gbase, vbase, v);
+  if (dim > 9) final_tp_part<9, 7>(a, e, dim, gbase, vbase, v);   // l = 3
   return v;
 }
 

@@ -15,6 +15,12 @@
 // Linear channel mixing: V^L[e][c][v] = sum_u M_{l(c)}[v][u] T[e][c][u] / sqrt(n),
 // a dense contraction over channels run on FP32 MFMA.
 //
+// Deeper models (three or more layers) also carry unnatural-parity irreps
+// (1e, 2o, 3e): the features of those layers hold 2 dim components (natural
+// block, then unnatural block), and each (l, parity) has its own mixing
+// matrix.  Kernels are instantiated per pattern, TpPattern<l_max, input kind,
+// output kind>.
+//
 // Work mapping.  Per-centre kernels (environment sums and the tensor-product
 // adjoint, which both reduce over a centre's edges) give one wavefront to one
 // centre: lane = channel u (+ edge sub-group when n < 64), so every reduction
@@ -33,22 +39,53 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int lof(int c) { return c == 0 ? 0 : (c < 4 ? 1 : 2); }
+constexpr int lof(int c) { return l_of(c); }
 
+// Mixing-matrix slot of strided component c of a feature with D natural components.
 template <int LMAX>
+constexpr int mix_slot(int c) {
+  constexpr int D = (LMAX + 1) * (LMAX + 1);
+  return c < D ? l_of(c) : LMAX + 1 + l_of(c - D);
+}
+
+// Fused-table weights: by value for small tables, else from device memory
+// read through the constant address space (the table is not written while a
+// kernel runs), which lets the compiler use scalar loads.
+typedef const __attribute__((address_space(4))) float* ConstFloatPtr;
+
+template <class Pat>
+__device__ __forceinline__ auto tp_weights(const TensorArgs& a) {
+  if constexpr (Pat::NNZ <= kTpwArgs) return (const float*)a.tpw_v;
+  else return (ConstFloatPtr)a.tpw;
+}
+
+// Inside a loop, a large table's pointer is passed through an empty asm
+// statement at each iteration: its loads then stay inside the loop instead of
+// being hoisted out of it, which would keep hundreds of loop-invariant
+// weights live in registers.  The kernel-argument array is returned as is.
+__device__ __forceinline__ const float* per_iteration(const float* w) { return w; }
+__device__ __forceinline__ ConstFloatPtr per_iteration(ConstFloatPtr w) {
+  asm volatile("" : "+s"(w));
+  return w;
+}
+
+template <int LMAX, int DIN>
 __device__ __forceinline__ void load_v(const VSrc& v, const float* eb_e, int64_t e, int u, int n,
                                        float* V) {
   constexpr int DIM = (LMAX + 1) * (LMAX + 1);
   const float* p = v.p + (size_t)e * v.ld + u;
   if (v.from_a0) {
+    static_assert(DIN >= DIM, "first-layer features are natural");
     float a0[LMAX + 1];
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) a0[l] = p[l * n];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) V[c] = a0[lof(c)] * eb_e[c];
+    for (int c = 0; c < DIM; ++c) V[c] = a0[lof(c)] * eb_e[eb_y(c)];
+#pragma unroll
+    for (int c = DIM; c < DIN; ++c) V[c] = 0.0f;
   } else {
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) V[c] = p[c * n];
+    for (int c = 0; c < DIN; ++c) V[c] = p[c * n];
   }
 }
 
@@ -71,7 +108,7 @@ __global__ __launch_bounds__(256) void k_env(TensorArgs a) {
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) wl[l] = w[l * n];
 #pragma unroll
-    for (int b = 0; b < DIM; ++b) acc[b] = fmaf(wl[lof(b)], Y[b], acc[b]);
+    for (int b = 0; b < DIM; ++b) acc[b] = fmaf(wl[lof(b)], Y[eb_y(b)], acc[b]);
   }
 #pragma unroll
   for (int b = 0; b < DIM; ++b) acc[b] = group_cross_sum(acc[b], n);
@@ -83,8 +120,8 @@ __global__ __launch_bounds__(256) void k_env(TensorArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Edge-tile kernels staging a [DIM][TT][n] block in LDS, then mixing channels
-// on MFMA.  B operands are the packed mixing matrices (one per l).
+// Edge-tile kernels staging a [w][TT][n] block in LDS, then mixing channels
+// on MFMA.  B operands are the packed mixing matrices (one per irrep slot).
 
 __device__ __forceinline__ f32x4 mma8(const float* a, const float* b, f32x4 c) {
   // the K = 32 block as eight K = 4 steps (lane group g holds k = 8 g + s)
@@ -93,109 +130,147 @@ __device__ __forceinline__ f32x4 mma8(const float* a, const float* b, f32x4 c) {
   return c;
 }
 
-// Channel mixing out[e][c][v] = scale * sum_k S[c][e][k] B_{l(c)}[k][v] for
+// Channel mixing out[e][c][v] = scale * sum_k S[c][e][k] B_{slot(c)}[k][v] for
 // the rows of an edge tile.  Each wave owns one 16-wide column tile of the
 // output (with fewer column tiles than waves, the waves also split the
-// components); the B fragments of that column tile for every l stay in
-// registers for all the tiles a block processes.
+// components).  Natural-parity layers keep the B fragments of every slot in
+// registers for all the tiles a block processes; the wider parity layouts,
+// whose tensor-product phase needs those registers, load one slot's
+// fragments per component instead.
 constexpr int kMixKB = 2;   // K = n <= 64
 
-template <int LMAX>
+template <int NS>
 struct MixB {
-  float b[LMAX + 1][kMixKB][8];
+  float b[NS][kMixKB][8];
   int nt, csub, wpt;
 };
 
-template <int LMAX>
-__device__ __forceinline__ void load_mix_b(MixB<LMAX>& m, const float* Bbase, int b_stride, int Kp, int Np) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = lane_id();
-  const int nct = Np >> 4, nkb = Kp >> 5;   // nct is 2 or 4 (Np a multiple of 32, n <= 64)
+template <int NS>
+__device__ __forceinline__ void mix_geometry(MixB<NS>& m, int Np) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nct = Np >> 4;   // 2 or 4 (Np a multiple of 32, n <= 64)
   m.nt = wave % nct;
   m.wpt = nct >= 4 ? 1 : 4 / nct;
   m.csub = nct >= 4 ? 0 : wave / nct;
-#pragma unroll
-  for (int l = 0; l <= LMAX; ++l)
-#pragma unroll
-    for (int kb = 0; kb < kMixKB; ++kb) {
-      const int kk = kb < nkb ? kb : 0;
-      const float* bp = Bbase + (size_t)l * b_stride + ((size_t)(m.nt * nkb + kk) * 64 + lane) * 8;
-      const float4 lo = *(const float4*)bp, hi = *(const float4*)(bp + 4);
-      m.b[l][kb][0] = lo.x; m.b[l][kb][1] = lo.y; m.b[l][kb][2] = lo.z; m.b[l][kb][3] = lo.w;
-      m.b[l][kb][4] = hi.x; m.b[l][kb][5] = hi.y; m.b[l][kb][6] = hi.z; m.b[l][kb][7] = hi.w;
-    }
 }
 
-template <int LMAX, int TT>
-__device__ void mix_tile(const float* S, int lds_ld, const MixB<LMAX>& m, int n, int Kp, float scale, float* out,
-                         int64_t e0, int E) {
-  constexpr int DIM = (LMAX + 1) * (LMAX + 1);
+__device__ __forceinline__ void load_mix_slot(float (&b)[kMixKB][8], const float* Bslot, int nt, int nkb) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int kb = 0; kb < kMixKB; ++kb) {
+    const int kk = kb < nkb ? kb : 0;
+    const float* bp = Bslot + ((size_t)(nt * nkb + kk) * 64 + lane) * 8;
+    const float4 lo = *(const float4*)bp, hi = *(const float4*)(bp + 4);
+    b[kb][0] = lo.x; b[kb][1] = lo.y; b[kb][2] = lo.z; b[kb][3] = lo.w;
+    b[kb][4] = hi.x; b[kb][5] = hi.y; b[kb][6] = hi.z; b[kb][7] = hi.w;
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void load_mix_b(MixB<NS>& m, const float* Bbase, int b_stride, int Kp, int Np) {
+  mix_geometry(m, Np);
+  const int nkb = Kp >> 5;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) load_mix_slot(m.b[s], Bbase + (size_t)s * b_stride, m.nt, nkb);
+}
+
+// One strided component c of the tile: rows e0.., output row stride ldo components.
+template <int TT>
+__device__ __forceinline__ void mix_one(const float* S, int lds_ld, int c, const float (&b)[kMixKB][8], int nt,
+                                        int n, int Kp, float scale, float* out, int ldo, int64_t e0, int E) {
   constexpr int RT = TT / 16;
   const int lane = lane_id();
   const int nkb = Kp >> 5;
-  const int col = m.nt * 16 + (lane & 15);
+  const int col = nt * 16 + (lane & 15);
+  f32x4 acc[RT];
 #pragma unroll
-  for (int l = 0; l <= LMAX; ++l) {
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int kb = 0; kb < kMixKB; ++kb) {
+    if (kb < nkb) {
+      const float* ap = S + (size_t)c * TT * lds_ld + (lane & 15) * lds_ld + kb * 32 + 8 * (lane >> 4);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        // two 16-byte LDS reads (row stride = 4 mod 64 banks: conflict-free)
+        const float4 lo = *(const float4*)(ap + rt * 16 * lds_ld);
+        const float4 hi = *(const float4*)(ap + rt * 16 * lds_ld + 4);
+        const float af[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        acc[rt] = mma8(af, b[kb], acc[rt]);
+      }
+    }
+  }
+  if (col < n) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rt * 16 + 4 * (lane >> 4) + i;
+        if (e0 + r < E) out[((size_t)(e0 + r) * ldo + c) * n + col] = acc[rt][i] * scale;
+      }
+  }
+}
+
+// HOLD: m holds the fragments of slots 0..LMAX (natural-parity output).
+// Otherwise each component's slot is loaded from Bbase; the unnatural l = 0
+// slot (component D of a 2 D wide feature) is never kept and is skipped.
+template <int LMAX, int DOUT, int TT, bool HOLD, int NS>
+__device__ void mix_tile(const float* S, int lds_ld, const MixB<NS>& m, const float* Bbase, int b_stride, int n,
+                         int Kp, float scale, float* out, int64_t e0, int E) {
+  constexpr int D = (LMAX + 1) * (LMAX + 1);
+  if constexpr (HOLD) {
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
 #pragma unroll 1
-    for (int c = l * l; c < (l + 1) * (l + 1); ++c) {
-      if (c % m.wpt != m.csub) continue;
-      f32x4 acc[RT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0, 0, 0, 0};
-#pragma unroll
-      for (int kb = 0; kb < kMixKB; ++kb) {
-        if (kb < nkb) {
-          const float* ap = S + (size_t)c * TT * lds_ld + (lane & 15) * lds_ld + kb * 32 + 8 * (lane >> 4);
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            // two 16-byte LDS reads (row stride = 4 mod 64 banks: conflict-free)
-            const float4 lo = *(const float4*)(ap + rt * 16 * lds_ld);
-            const float4 hi = *(const float4*)(ap + rt * 16 * lds_ld + 4);
-            const float af[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-            acc[rt] = mma8(af, m.b[l][kb], acc[rt]);
-          }
-        }
+      for (int c = l * l; c < (l + 1) * (l + 1); ++c) {
+        if (c % m.wpt != m.csub) continue;
+        mix_one<TT>(S, lds_ld, c, m.b[l], m.nt, n, Kp, scale, out, DOUT, e0, E);
       }
-      if (col < n) {
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = rt * 16 + 4 * (lane >> 4) + i;
-            if (e0 + r < E) out[((size_t)(e0 + r) * DIM + c) * n + col] = acc[rt][i] * scale;
-          }
-      }
+    }
+  } else {
+#pragma unroll 1
+    for (int c = 0; c < DOUT; ++c) {
+      if (c % m.wpt != m.csub || (DOUT > D && c == D)) continue;
+      float b[kMixKB][8];
+      load_mix_slot(b, Bbase + (size_t)mix_slot<LMAX>(c) * b_stride, m.nt, Kp >> 5);
+      mix_one<TT>(S, lds_ld, c, b, m.nt, n, Kp, scale, out, DOUT, e0, E);
     }
   }
 }
 
-template <int LMAX, int TT>
+template <int DOUT, int TT>
 __device__ void copy_tile(const float* S, int lds_ld, int n, float* out, int64_t e0, int E) {
-  constexpr int DIM = (LMAX + 1) * (LMAX + 1);
-  for (int p = threadIdx.x; p < TT * DIM * n; p += 256) {
-    const int r = p / (DIM * n), rem = p - r * DIM * n, c = rem / n, u = rem - c * n;
-    if (e0 + r < E) out[((size_t)(e0 + r) * DIM + c) * n + u] = S[((size_t)c * TT + r) * lds_ld + u];
+  for (int p = threadIdx.x; p < TT * DOUT * n; p += 256) {
+    const int r = p / (DOUT * n), rem = p - r * DOUT * n, c = rem / n, u = rem - c * n;
+    if (e0 + r < E) out[((size_t)(e0 + r) * DOUT + c) * n + u] = S[((size_t)c * TT + r) * lds_ld + u];
   }
 }
+
+// Whether a layer's mixing keeps every slot's fragments in registers.
+template <class Pat>
+constexpr bool kHoldMix = Pat::In == kNatural && Pat::Out == kNatural && Pat::Lmax <= 2;
 
 // Tensor product (non-final layers) + channel mixing -> V^L.  Each block
 // walks edge tiles blockIdx.x, blockIdx.x + gridDim.x, ... with the mixing
 // fragments loaded once.
-template <int LMAX, int TT>
+template <class Pat, int TT>
 __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp, int Np) {
-  using Pat = TpPattern<LMAX, false>;
-  constexpr int DIM = Pat::DIM;
-  extern __shared__ __align__(16) float S[];   // [DIM][TT][lds_ld]
+  constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
+  constexpr bool HOLD = kHoldMix<Pat>;
+  extern __shared__ __align__(16) float S[];   // [DOUT][TT][lds_ld]
   const int n = a.n;
-  const float* w = a.tpw_v;   // kernel-argument array: uniform, read with scalar loads
-  MixB<LMAX> mb;
-  if (a.channel_mix) load_mix_b<LMAX>(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
+  const auto w = tp_weights<Pat>(a);   // uniform: read with scalar loads
+  MixB<HOLD ? LMAX + 1 : 1> mb;
+  if (a.channel_mix) {
+    if constexpr (HOLD) load_mix_b(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
+    else mix_geometry(mb, Np);
+  }
   const int ntiles = (a.E + TT - 1) / TT;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = (int64_t)tile * TT;
     // TT * Kp is a multiple of 512: two (edge, channel) items per thread per
     // step, loads of both issued before either is used
     for (int p0 = threadIdx.x; p0 < TT * Kp; p0 += 512) {
-      float V[2][DIM], G[2][DIM];
+      float V[2][DIN], G[2][DIM];
       bool ok[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -205,7 +280,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
         ok[h] = e < a.E && u < n;
         const int64_t ee = ok[h] ? e : 0;
         const int uu = ok[h] ? u : 0;
-        load_v<LMAX>(a.v, a.eb + (size_t)ee * kEB, ee, uu, n, V[h]);
+        load_v<LMAX, DIN>(a.v, a.eb + (size_t)ee * kEB, ee, uu, n, V[h]);
         const float* gp = a.gam + (size_t)(a.ei[ee] - a.centre_base) * DIM * n + uu;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) G[h][b] = gp[b * n];
@@ -214,35 +289,49 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
       for (int h = 0; h < 2; ++h) {
         const int p = p0 + 256 * h;
         const int r = p / Kp, u = p - r * Kp;
-        float T[DIM];
+        float T[DOUT];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) T[c] = 0.0f;
-        if (ok[h]) tp_forward<Pat>(V[h], G[h], T, w, std::make_index_sequence<Pat::NNZ>{});
+        for (int c = 0; c < DOUT; ++c) T[c] = 0.0f;
+        if (ok[h]) tp_forward<Pat>(V[h], G[h], T, per_iteration(w));
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) S[((size_t)c * TT + r) * lds_ld + u] = T[c];
+        for (int c = 0; c < DOUT; ++c) S[((size_t)c * TT + r) * lds_ld + u] = T[c];
       }
     }
     __syncthreads();
-    if (a.channel_mix) mix_tile<LMAX, TT>(S, lds_ld, mb, n, Kp, a.mix_scale, a.v_out, e0, a.E);
-    else copy_tile<LMAX, TT>(S, lds_ld, n, a.v_out, e0, a.E);
+    if (a.channel_mix)
+      mix_tile<LMAX, DOUT, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
+                                     a.v_out, e0, a.E);
+    else copy_tile<DOUT, TT>(S, lds_ld, n, a.v_out, e0, a.E);
     __syncthreads();   // S is rewritten by the next tile
   }
 }
 
-// Adjoint of channel mixing for a non-final layer.  dE/dV^L is rebuilt from
-// the final layer: dE/dV[a][u] = w_a Gamma'[a][u] dE/dT'[u] (+ dE/ds at a = 0).
-template <int LMAX, int TT>
+// Adjoint of channel mixing for a non-final layer L, given the next layer's
+// pattern PatN.  dE/dV^L is rebuilt from layer L+1:
+//   final next layer:  dE/dV[a][u] = w_a Gamma'[a][u] dE/dT'[u]
+//   otherwise:         dE/dV[a][u] = sum_{b,c} W'[a][b][c] Gamma'[b][u] dE/dT'[c][u]
+// plus dE/ds at a = 0 (the scalars read by layer L's latent MLP); then the
+// transposed mixing gives dE/dT^L.  The launch's tpw / tpw_v hold layer
+// L+1's table.
+template <class PatN, int TT>
 __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, int Kp, int Np) {
-  constexpr int DIM = (LMAX + 1) * (LMAX + 1);
+  constexpr int LMAX = PatN::Lmax, DIM = PatN::DIM, DW = PatN::DIN, DN = PatN::DOUT;
+  constexpr bool NEXT_FINAL = PatN::Out == kScalarOut;
+  constexpr bool HOLD = NEXT_FINAL && PatN::In == kNatural && LMAX <= 2;
+  static_assert(!NEXT_FINAL || DW == DIM, "the final layer reads natural-parity features");
   extern __shared__ __align__(16) float S[];
   const int n = a.n;
-  MixB<LMAX> mb;
-  if (a.channel_mix) load_mix_b<LMAX>(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
+  const auto wn = tp_weights<PatN>(a);
+  MixB<HOLD ? LMAX + 1 : 1> mb;
+  if (a.channel_mix) {
+    if constexpr (HOLD) load_mix_b(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
+    else mix_geometry(mb, Np);
+  }
   const int ntiles = (a.E + TT - 1) / TT;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = (int64_t)tile * TT;
     for (int p0 = threadIdx.x; p0 < TT * Kp; p0 += 512) {
-      float gam[2][DIM], gt[2], gs[2];
+      float gam[2][DIM], gt[2][DN], gs[2];
       bool ok[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -252,7 +341,8 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
         ok[h] = e < a.E && u < n;
         const int64_t ee = ok[h] ? e : 0;
         const int uu = ok[h] ? u : 0;
-        gt[h] = a.g_tnext[(size_t)ee * n + uu];
+#pragma unroll
+        for (int c = 0; c < DN; ++c) gt[h][c] = a.g_tnext[((size_t)ee * DN + c) * n + uu];
         gs[h] = a.g_s[(size_t)ee * n + uu];
         const float* gp = a.gam_next + (size_t)(a.ei[ee] - a.centre_base) * DIM * n + uu;
 #pragma unroll
@@ -262,17 +352,31 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
       for (int h = 0; h < 2; ++h) {
         const int p = p0 + 256 * h;
         const int r = p / Kp, u = p - r * Kp;
+        if constexpr (NEXT_FINAL) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-          float gV = ok[h] ? a.tp_wnext[c] * gam[h][c] * gt[h] : 0.0f;
-          if (c == 0 && ok[h]) gV += gs[h];
-          S[((size_t)c * TT + r) * lds_ld + u] = gV;
+          for (int c = 0; c < DIM; ++c) {
+            // one explicit fma per element: rows of both item halves round alike
+            const float gV = ok[h] ? fmaf(a.tp_wnext[c] * gam[h][c], gt[h][0], c == 0 ? gs[h] : 0.0f) : 0.0f;
+            S[((size_t)c * TT + r) * lds_ld + u] = gV;
+          }
+        } else {
+          float gV[DW];
+#pragma unroll
+          for (int c = 0; c < DW; ++c) gV[c] = 0.0f;
+          if (ok[h]) {
+            tp_adjoint_v<PatN>(gam[h], gt[h], gV, per_iteration(wn));
+            gV[0] += gs[h];
+          }
+#pragma unroll
+          for (int c = 0; c < DW; ++c) S[((size_t)c * TT + r) * lds_ld + u] = gV[c];
         }
       }
     }
     __syncthreads();
-    if (a.channel_mix) mix_tile<LMAX, TT>(S, lds_ld, mb, n, Kp, a.mix_scale, a.g_tout, e0, a.E);
-    else copy_tile<LMAX, TT>(S, lds_ld, n, a.g_tout, e0, a.E);
+    if (a.channel_mix)
+      mix_tile<LMAX, DW, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
+                                   a.g_tout, e0, a.E);
+    else copy_tile<DW, TT>(S, lds_ld, n, a.g_tout, e0, a.E);
     __syncthreads();
   }
 }
@@ -293,29 +397,34 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
 //   dE/dV_e[a][u] = sum_{b,c} W[a][b][c] Gamma_i[b][u] dE/dT_e[c][u]
 //   dE/da0_e[l][u] = sum_{a: l(a)=l} dE/dV_e[a][u] Y_e[a]
 //   dE/dY_e[a]   += sum_u dE/dV_e[a][u] a0_e[l(a)][u].
-// The sums over channels use DPP lane moves within each group of n lanes, in
-// a fixed order: deterministic.
-constexpr int kBatch = 4;
+// (For later layers dE/dV_e is formed by the previous layer's mixing
+// adjoint.)  The sums over channels use DPP lane moves within each group of n
+// lanes, in a fixed order: deterministic.
 
-template <int LMAX, bool FINAL, int G>
+// Edges per lane group whose loads are issued together: as many as fit a
+// register budget of about 80 values.
+template <class Pat>
+constexpr int kGammaBatch = 4 * (Pat::DIN + Pat::DOUT) <= 80 ? 4 : (2 * (Pat::DIN + Pat::DOUT) <= 80 ? 2 : 1);
+
+template <class Pat, int G>
 __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
-  using Pat = TpPattern<LMAX, FINAL>;
-  constexpr int DIM = Pat::DIM, DOUT = Pat::DOUT;
+  constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
+  constexpr int KB = kGammaBatch<Pat>;
   constexpr int n = kWave / G;
   const int lane = lane_id();
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.n_centres) return;
   const int u = lane & (n - 1), g = lane / n;
-  const float* w = a.tpw_v;
+  const auto w = tp_weights<Pat>(a);
   float gG[DIM];
 #pragma unroll
   for (int b = 0; b < DIM; ++b) gG[b] = 0.0f;
   const int eb0 = a.row_ptr[c], eb1 = a.row_ptr[c + 1];
   const bool from_a0 = a.v.from_a0 != 0;
-  for (int e0 = eb0; e0 < eb1; e0 += G * kBatch) {
-    float V[kBatch][DIM], gT[kBatch][DOUT];
+  for (int e0 = eb0; e0 < eb1; e0 += G * KB) {
+    float V[KB][DIN], gT[KB][DOUT];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
+    for (int j = 0; j < KB; ++j) {
       const int e = e0 + g + G * j;
       const bool act = e < eb1;
       const uint32_t ee = act ? e : eb0;
@@ -327,16 +436,16 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) a0v[l] = vp[l * n];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) V[j][k] = a0v[lof(k)] * Y[k];
+        for (int k = 0; k < DIN; ++k) V[j][k] = k < DIM ? a0v[lof(k < DIM ? k : 0)] * Y[eb_y(k < DIM ? k : 0)] : 0.0f;
       } else {
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) V[j][k] = vp[k * n];
+        for (int k = 0; k < DIN; ++k) V[j][k] = vp[k * n];
       }
 #pragma unroll
       for (int k = 0; k < DOUT; ++k) gT[j][k] = act ? gtp[k * n] : 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) tp_adjoint_g<Pat>(V[j], gT[j], gG, w, std::make_index_sequence<Pat::NNZ>{});
+    for (int j = 0; j < KB; ++j) tp_adjoint_g<Pat>(V[j], gT[j], gG, per_iteration(w));
   }
   if constexpr (G > 1) {
 #pragma unroll
@@ -352,17 +461,18 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
 constexpr int kEdgesPerWave = 32;
 
 // A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a].
-template <int LMAX, bool FINAL, int G, bool A0>
+template <class Pat, int G, bool A0>
 __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
-  using Pat = TpPattern<LMAX, FINAL>;
-  constexpr int DIM = Pat::DIM, DOUT = Pat::DOUT;
+  constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
+  constexpr int GYW = gy_width(LMAX);
   constexpr int n = kWave / G;
-  constexpr int KB = A0 ? 2 : 4;   // edges per lane group whose loads are issued together
+  // edges per lane group whose loads are issued together
+  constexpr int KB = A0 ? (DOUT > 16 ? 1 : 2) : (DIM > 9 ? 2 : 4);
   const int lane = lane_id();
   const int u = lane & (n - 1), g = lane / n;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t w0 = (int64_t)wave * kEdgesPerWave;
-  const float* w = a.tpw_v;
+  const auto w = tp_weights<Pat>(a);
   const bool keep_gy = a.gy_accum != 0;
   const float cn = a.c_norm;
   // centres of the wave's edges: one load per lane, read out per edge.  With
@@ -393,7 +503,7 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       const float* Y = a.eb + ee * kEB;
       const float* wp = a.w_env + ee * (uint32_t)a.ld_w + u;
 #pragma unroll
-      for (int b = 0; b < DIM; ++b) Yv[q][b] = Y[b];
+      for (int b = 0; b < DIM; ++b) Yv[q][b] = Y[eb_y(b)];
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) wv[q][l] = wp[l * n];
       if constexpr (!CACHE) {
@@ -437,10 +547,11 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
         r[b] = cn * gGq[b] * wv[q][lof(b)];
       }
       if constexpr (A0) {
-        float gV[DIM];
+        static_assert(Pat::In == kNatural, "the rank-1 form is natural");
+        float gV[DIN];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) gV[k] = 0.0f;
-        tp_adjoint_v<Pat>(Gm[q], gT[q], gV, w, std::make_index_sequence<Pat::NNZ>{});
+        for (int k = 0; k < DIN; ++k) gV[k] = 0.0f;
+        tp_adjoint_v<Pat>(Gm[q], gT[q], gV, per_iteration(w));
         float ga[LMAX + 1];
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
@@ -463,9 +574,9 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       for (int k = 0; k < DIM; ++k) r[k] = group_sum_dpp<n>(r[k]);
       if (act[q] && u == n - 1) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          float* o = a.g_Y + ee * 9u + k;
-          const float val = k < DIM ? r[k] : 0.0f;
+        for (int k = 0; k < GYW; ++k) {
+          float* o = a.g_Y + ee * (uint32_t)GYW + k;
+          const float val = k < DIM ? r[k < DIM ? k : 0] : 0.0f;
           *o = (keep_gy && k < DIM) ? *o + val : val;
         }
       }
@@ -495,76 +606,141 @@ hipError_t launch_lds(K kern, unsigned grid, size_t bytes, hipStream_t s, const 
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_env(const TensorArgs& a, hipStream_t s) {
-  if (a.n_centres <= 0) return hipSuccess;
-  if (a.l_max == 1) hipLaunchKernelGGL(k_env<1>, dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_env<2>, dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int TT>
-hipError_t launch_tp_mix_tt(const TensorArgs& a, hipStream_t s) {
-  const int dim = (a.l_max + 1) * (a.l_max + 1);
-  int ld, Kp, Np;
-  size_t bytes;
-  mix_dims(a.n, dim, TT, &ld, &Kp, &Np, &bytes);
-  // one tile per block: the tensor-product phase's load latency is hidden by
-  // many resident blocks rather than by a tile loop
-  const unsigned grid = blocks(a.E, TT);
-  if (a.l_max == 1) return launch_lds(k_tp_mix<1, TT>, grid, bytes, s, a, ld, Kp, Np);
-  return launch_lds(k_tp_mix<2, TT>, grid, bytes, s, a, ld, Kp, Np);
-}
-
-template <int TT>
-hipError_t launch_mix_adjoint_tt(const TensorArgs& a, hipStream_t s) {
-  const int dim = (a.l_max + 1) * (a.l_max + 1);
-  int ld, Kp, Np;
-  size_t bytes;
-  mix_dims(a.n, dim, TT, &ld, &Kp, &Np, &bytes);
-  const unsigned grid = std::min<unsigned>(blocks(a.E, TT), kMixBlocks);
-  if (a.l_max == 1) return launch_lds(k_mix_adjoint<1, TT>, grid, bytes, s, a, ld, Kp, Np);
-  return launch_lds(k_mix_adjoint<2, TT>, grid, bytes, s, a, ld, Kp, Np);
-}
-
-hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s) {
-  if (final_layer) return hipErrorInvalidValue;   // the final layer is fused into the last MLP
-  if (a.E <= 0) return hipSuccess;
-  return a.tile == 16 ? launch_tp_mix_tt<16>(a, s) : launch_tp_mix_tt<32>(a, s);
-}
-
-hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s) {
-  if (a.E <= 0) return hipSuccess;
-  return a.tile == 16 ? launch_mix_adjoint_tt<16>(a, s) : launch_mix_adjoint_tt<32>(a, s);
-}
-
-template <int LMAX, bool FINAL, int G>
-hipError_t launch_adjoint_g(const TensorArgs& a, hipStream_t s) {
-  if (a.n_centres > 0)
-    hipLaunchKernelGGL((k_tp_adjoint_gamma<LMAX, FINAL, G>), dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
-  if (a.E > 0) {
-    const dim3 grid(blocks(a.E, 4 * kEdgesPerWave));
-    if (a.v.from_a0) hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G, true>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_tp_adjoint_edges<LMAX, FINAL, G, false>), grid, dim3(256), 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-template <int LMAX, bool FINAL>
-hipError_t launch_adjoint_n(const TensorArgs& a, hipStream_t s) {
-  switch (a.n) {
-    case 64: return launch_adjoint_g<LMAX, FINAL, 1>(a, s);
-    case 32: return launch_adjoint_g<LMAX, FINAL, 2>(a, s);
-    case 16: return launch_adjoint_g<LMAX, FINAL, 4>(a, s);
-    case 8: return launch_adjoint_g<LMAX, FINAL, 8>(a, s);
+// Calls fn(TpPattern<l_max, in, out>{}) for the supported patterns: natural
+// input with scalar, natural or both-parity output, and both-parity input
+// with natural or both-parity output, for l_max 1..3.
+template <int LMAX, class Fn>
+hipError_t with_pattern_l(int in, int out, Fn&& fn) {
+  if (in == kNatural) {
+    if (out == kScalarOut) return fn(TpPattern<LMAX, kNatural, kScalarOut>{});
+    if (out == kNatural) return fn(TpPattern<LMAX, kNatural, kNatural>{});
+    if (out == kBothParities) return fn(TpPattern<LMAX, kNatural, kBothParities>{});
+  } else if (in == kBothParities) {
+    if (out == kNatural) return fn(TpPattern<LMAX, kBothParities, kNatural>{});
+    if (out == kBothParities) return fn(TpPattern<LMAX, kBothParities, kBothParities>{});
   }
   return hipErrorInvalidValue;
 }
 
+template <class Fn>
+hipError_t with_pattern(int l_max, int in, int out, Fn&& fn) {
+  switch (l_max) {
+    case 1: return with_pattern_l<1>(in, out, fn);
+    case 2: return with_pattern_l<2>(in, out, fn);
+    case 3: return with_pattern_l<3>(in, out, fn);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Whether a pattern is one of the natural-parity ones with l_max <= 2, which
+// support every channel count and both tile heights; the others run with 32
+// or 64 channels and 16-edge tiles.
+template <class Pat>
+constexpr bool kBasePattern = Pat::Lmax <= 2 && Pat::In == kNatural && Pat::Out != kBothParities;
+
+}  // namespace
+
+hipError_t launch_env(const TensorArgs& a, hipStream_t s) {
+  if (a.n_centres <= 0) return hipSuccess;
+  const dim3 grid(blocks(a.n_centres, 4));
+  if (a.l_max == 1) hipLaunchKernelGGL(k_env<1>, grid, dim3(256), 0, s, a);
+  else if (a.l_max == 2) hipLaunchKernelGGL(k_env<2>, grid, dim3(256), 0, s, a);
+  else if (a.l_max == 3) hipLaunchKernelGGL(k_env<3>, grid, dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+namespace {
+
+template <class Pat, int TT>
+hipError_t launch_tp_mix_pt(const TensorArgs& a, hipStream_t s) {
+  int ld, Kp, Np;
+  size_t bytes;
+  mix_dims(a.n, Pat::DOUT, TT, &ld, &Kp, &Np, &bytes);
+  // one tile per block: the tensor-product phase's load latency is hidden by
+  // many resident blocks rather than by a tile loop
+  const unsigned grid = blocks(a.E, TT);
+  return launch_lds(k_tp_mix<Pat, TT>, grid, bytes, s, a, ld, Kp, Np);
+}
+
+template <class PatN, int TT>
+hipError_t launch_mix_adjoint_pt(const TensorArgs& a, hipStream_t s) {
+  int ld, Kp, Np;
+  size_t bytes;
+  mix_dims(a.n, PatN::DIN, TT, &ld, &Kp, &Np, &bytes);
+  const unsigned grid = std::min<unsigned>(blocks(a.E, TT), kMixBlocks);
+  return launch_lds(k_mix_adjoint<PatN, TT>, grid, bytes, s, a, ld, Kp, Np);
+}
+
+template <class Pat, int G>
+hipError_t launch_adjoint_g(const TensorArgs& a, hipStream_t s) {
+  if (a.n_centres > 0)
+    hipLaunchKernelGGL((k_tp_adjoint_gamma<Pat, G>), dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
+  if (a.E > 0) {
+    const dim3 grid(blocks(a.E, 4 * kEdgesPerWave));
+    if constexpr (Pat::In == kNatural) {
+      if (a.v.from_a0) {
+        hipLaunchKernelGGL((k_tp_adjoint_edges<Pat, G, true>), grid, dim3(256), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_tp_adjoint_edges<Pat, G, false>), grid, dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s) {
+  if (final_layer) return hipErrorInvalidValue;   // the final layer is fused into the last MLP
+  if (a.E <= 0) return hipSuccess;
+  return with_pattern(a.l_max, a.in_kind, a.out_kind, [&](auto pat) -> hipError_t {
+    using Pat = decltype(pat);
+    if constexpr (Pat::Out == kScalarOut) {
+      return hipErrorInvalidValue;
+    } else if constexpr (kBasePattern<Pat>) {
+      return a.tile == 16 ? launch_tp_mix_pt<Pat, 16>(a, s) : launch_tp_mix_pt<Pat, 32>(a, s);
+    } else {
+      if (a.n != 32 && a.n != 64) return hipErrorInvalidValue;
+      return launch_tp_mix_pt<Pat, 16>(a, s);
+    }
+  });
+}
+
+hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s) {
+  if (a.E <= 0) return hipSuccess;
+  return with_pattern(a.l_max, a.next_in, a.next_out, [&](auto pat) -> hipError_t {
+    using PatN = decltype(pat);
+    if constexpr (PatN::Out == kScalarOut && PatN::Lmax <= 2) {
+      return a.tile == 16 ? launch_mix_adjoint_pt<PatN, 16>(a, s) : launch_mix_adjoint_pt<PatN, 32>(a, s);
+    } else if constexpr (PatN::In == kBothParities || PatN::Out == kScalarOut) {
+      if (a.n != 32 && a.n != 64) return hipErrorInvalidValue;
+      return launch_mix_adjoint_pt<PatN, 16>(a, s);
+    } else {
+      return hipErrorInvalidValue;   // a layer after the first reads both parities
+    }
+  });
+}
+
 hipError_t launch_tp_env_adjoint(const TensorArgs& a, bool final_layer, hipStream_t s) {
-  if (a.l_max == 1) return final_layer ? launch_adjoint_n<1, true>(a, s) : launch_adjoint_n<1, false>(a, s);
-  return final_layer ? launch_adjoint_n<2, true>(a, s) : launch_adjoint_n<2, false>(a, s);
+  const int out = final_layer ? (int)kScalarOut : a.out_kind;
+  return with_pattern(a.l_max, a.in_kind, out, [&](auto pat) -> hipError_t {
+    using Pat = decltype(pat);
+    if constexpr (kBasePattern<Pat>) {
+      switch (a.n) {
+        case 64: return launch_adjoint_g<Pat, 1>(a, s);
+        case 32: return launch_adjoint_g<Pat, 2>(a, s);
+        case 16: return launch_adjoint_g<Pat, 4>(a, s);
+        case 8: return launch_adjoint_g<Pat, 8>(a, s);
+      }
+    } else {
+      switch (a.n) {
+        case 64: return launch_adjoint_g<Pat, 1>(a, s);
+        case 32: return launch_adjoint_g<Pat, 2>(a, s);
+      }
+    }
+    return hipErrorInvalidValue;
+  });
 }
 
 }  // namespace allegro

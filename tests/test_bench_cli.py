@@ -23,3 +23,19 @@ def test_algorithmic_mac_counts():
     # latent chain (256+64)->256->256->256 plus the env2 head 256 -> 192
     assert macs["mlp_fwd_latent"] == 320 * 256 + 2 * 256 * 256 + 256 * 192
     assert macs["mlp_bwd_final"] == 320 * 256 + 2 * 256 * 256
+
+
+def test_tensor_flop_counts():
+    """Tensor-track flops per edge of the two-layer water model, by hand:
+    n = 32, 9 components, 83 / 9 table non-zeros."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import paper_2304_10061_amd as P
+    import workloads as W
+    mc = W.model_config(2)
+    f = bench.tensor_flops_per_edge(mc, P.describe(P.config_from(mc)))
+    assert f["env"] == 2 * 2 * 9 * 32
+    assert f["tp_mix"] == 2 * 83 * 32 + 2 * 32 * 32 * 9
+    assert f["mix_adjoint"] == 3 * 9 * 32 + 2 * 32 * 32 * 9
+    assert f["tp_env_adjoint"] == 2 * (2 * 83 * 32 + 4 * 9 * 32)
+    assert f["tp_env_adjoint_final"] == 2 * 9 * 32 + 4 * 9 * 32

@@ -30,21 +30,39 @@ def test_exports_every_declared_symbol():
     assert sorted(binding.EXPORTS) == decl
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
-def test_describe_matches_oracle(cfg):
-    mc = W.model_config(cfg)
+def _check_describe(mc):
     info = P.describe(P.config_from(mc))
     paths = cg.layer_paths(mc.l_max, mc.n_layers)
+    widths = cg.layer_widths(mc.l_max, mc.n_layers)
     assert [info.n_paths[k] for k in range(mc.n_layers)] == [len(p) for p in paths]
     rng = np.random.default_rng(0)
-    nnz = [np.count_nonzero(cg.fused_table(mc.l_max, p, rng.standard_normal((3, 3, 3)), k == len(paths) - 1))
+    lm1 = mc.l_max + 1
+    shape = (2, lm1, lm1, lm1) if cg.has_unnatural(mc.l_max, mc.n_layers) else (lm1, lm1, lm1)
+    nnz = [np.count_nonzero(cg.fused_table(mc.l_max, p, rng.standard_normal(shape), k == len(paths) - 1,
+                                           *widths[k]))
            for k, p in enumerate(paths)]
     assert [info.n_nonzero[k] for k in range(mc.n_layers)] == nnz
+    assert [info.width[k] for k in range(mc.n_layers)] == [w[1] for w in widths]
     assert info.n_weights == W.pack_weights(mc, W.make_weights(mc, rng)).size
     assert info.dim == (mc.l_max + 1) ** 2 and info.latent == mc.latent
 
 
-@pytest.mark.parametrize("bad", [dict(l_max=3), dict(n_layers=3), dict(n_tensor=24), dict(n_species=20),
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_describe_matches_oracle(cfg):
+    _check_describe(W.model_config(cfg))
+
+
+@pytest.mark.parametrize("l_max,n_layers", [(1, 3), (2, 3), (3, 3), (3, 2), (3, 1), (1, 4), (2, 4), (3, 4)])
+def test_describe_matches_oracle_deep(l_max, n_layers):
+    """Deeper models carry unnatural-parity irreps: the library's pattern kinds
+    must reproduce the oracle's pruned path sets, table non-zeros and widths."""
+    _check_describe(W.ModelConfig(n_species=2, r_cut=4.0, l_max=l_max, n_layers=n_layers, n_tensor=32,
+                                  twobody_dims=(64, 64), latent_dims=(64, 64), edge_dims=(32,)))
+
+
+@pytest.mark.parametrize("bad", [dict(l_max=4), dict(n_layers=5), dict(l_max=3, n_tensor=16),
+                                 dict(n_layers=3, n_tensor=8), dict(l_max=3, n_bessel=12),
+                                 dict(n_tensor=24), dict(n_species=20),
                                  dict(twobody_dims=(100, 100), latent_dims=(100, 100)),
                                  dict(latent_dims=(64, 32)), dict(edge_dims=(64, 64)), dict(r_cut=-1.0),
                                  dict(r_cut_pair=((3.0, 4.5), (3.0, 4.0))),      # above r_cut

@@ -218,6 +218,22 @@ def model_config(cfg: int) -> ModelConfig:
     raise ValueError(cfg)
 
 
+def deep_model_config() -> ModelConfig:
+    """The water-box model deepened to three tensor-product layers with
+    l_max = 3 (unnatural-parity irreps in the middle layer's input, l = 3
+    harmonics); same MLP widths, channels and cutoff as the 3,000-atom model."""
+    return ModelConfig(n_species=2, r_cut=4.0, l_max=3, n_layers=3, n_tensor=32,
+                       twobody_dims=(128, 128), latent_dims=(128, 128), edge_dims=(128,))
+
+
+def deep_workload():
+    """(ModelConfig, System, weights): the deep model on the 3,000-atom water box."""
+    mc = deep_model_config()
+    sysm = system(2)
+    w = make_weights(mc, np.random.default_rng(np.random.SeedSequence(6).spawn(6)[3]))
+    return mc, sysm, w
+
+
 def system(cfg: int) -> System:
     if cfg == 1:
         return jittered_lattice_box(64, 8.6, 0.3, WATER_MIX, 1, sites_per_side=4)
