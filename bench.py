@@ -103,7 +103,13 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, com
             "copy_fetch_KiB": cf, "copy_write_KiB": cw,
             "fetch_scale": copy_kib / cf if cf else None, "write_scale": copy_kib / cw if cw else None,
             "kernels": {}}
-    lines = ["# rocprofv3 summary: protein-like box (23,558 atoms, 2.05M edges), BF16 step", ""]
+    title = "protein-like box (23,558 atoms, 2.05M edges), BF16 step"
+    for line in open(bench_log):
+        if line.startswith("{"):
+            rec = json.loads(line)
+            cfg = rec.get("config", {})
+            title = f"{rec.get('metric', title)}: {cfg.get('atoms', '?')} atoms, {cfg.get('edges', '?')} edges"
+    lines = [f"# rocprofv3 summary: {title}", ""]
     for c in commands:
         lines.append(f"    {c}")
     lines += ["", "| kernel | calls | avg us | total ms | FETCH KiB/dispatch | WRITE KiB/dispatch |",
@@ -117,8 +123,11 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, com
                      f"{'' if fa is None else f'{fa:.0f}'} | {'' if wa is None else f'{wa:.0f}'} |")
         if fa is not None and wa is not None and "k_mlp" in name:
             blob["kernels"][short] = {"avg_us": avg, "fetch_KiB": fa, "write_KiB": wa}
-    lines += ["", "Counter scale factors from the plain copy of %d MiB (bytes per counted byte):" % copy_mib,
-              "", "```json", json.dumps(blob, indent=1), "```", ""]
+    if copy_mib:
+        lines += ["", "Counter scale factors from the plain copy of %d MiB (bytes per counted byte):" % copy_mib]
+    else:
+        lines += ["", "Kernel trace only (no counter passes); sources of the profiled build:"]
+    lines += ["", "```json", json.dumps(blob, indent=1), "```", ""]
     return "\n".join(lines)
 
 
