@@ -123,3 +123,40 @@ def test_deep_water_box_sampled(deep_box, prec):
         assert abs(dEi.mean()) <= 1e-3
         assert np.sqrt((dF ** 2).mean()) <= 0.01 * frms
     assert np.abs(got["forces"].sum(0)).max() < 1e-6 * s.n_local
+
+
+def test_deep_md_graph_replay_and_oracle_trajectory():
+    """FP64 velocity Verlet with a deep model: hipGraph replays equal eager
+    steps bit for bit, and a short trajectory follows the oracle's."""
+    import torch
+    from oracle import md as OMD
+    from test_gpu_md_batched import _md_arrays
+    mc = _small(dict(l_max=3, n_layers=3, n_tensor=32))
+    w = W.make_weights(mc, np.random.default_rng(36))
+    s = W.system(1)
+    m = P.Model(P.config_from(mc, precision=FP32, neighbor_skin=1.0), W.pack_weights(mc, w))
+    v0 = W.maxwell_boltzmann(s.masses, 300.0, np.random.default_rng(37))
+    n_steps, dt = 10, 0.25
+    runs = []
+    for use_graph in (False, True):
+        pos, sp, vel, masses, F = _md_arrays(s, v0)
+        m.neighbors(pos, sp, s.cell, s.pbc)
+        thermo = torch.zeros((n_steps, 2), dtype=torch.float64, device=pos.device)
+        m.md_run(n_steps, dt, masses, pos, vel, F, sp, thermo=thermo, init_forces=True, use_graph=use_graph)
+        torch.cuda.synchronize()
+        runs.append((pos.cpu().numpy(), vel.cpu().numpy(), thermo.cpu().numpy()))
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    p = OM.Params(mc, w)
+
+    def ff(x):
+        s2 = copy.copy(s)
+        s2.pos = x
+        r = OM.evaluate(mc, w, s2, params=p, need_atom_virial=False)
+        return r.energy, r.forces
+
+    xr, vr, et = OMD.velocity_verlet(ff, s.pos, v0, s.masses, dt, n_steps)
+    _report("deep_md", max_dx=float(np.abs(runs[0][0] - xr).max()))
+    assert np.abs(runs[0][0] - xr).max() < 1e-6
+    etot = runs[0][2][:, 0] + runs[0][2][:, 1]
+    assert np.abs(etot - et[1:]).max() < 1e-4
