@@ -160,3 +160,30 @@ def test_deep_md_graph_replay_and_oracle_trajectory():
     assert np.abs(runs[0][0] - xr).max() < 1e-6
     etot = runs[0][2][:, 0] + runs[0][2][:, 1]
     assert np.abs(etot - et[1:]).max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16M], ids=["fp32", "bf16_mixed"])
+def test_deep_empty_isolated_and_dimer(prec):
+    """Degenerate inputs with a deep model: no atoms, isolated atoms (energy =
+    species shift, zero force), and a single pair (every edge in one centre
+    segment, the tile mostly padding) against the oracle."""
+    mc = _small(dict(l_max=3, n_layers=3, n_tensor=32))
+    w = W.make_weights(mc, np.random.default_rng(38))
+    sc, sh = W.species_scale_shift(mc, np.random.default_rng(39))
+    m = gpu_model(mc, w, prec, sc, sh)
+    s0 = W.System(pos=np.zeros((0, 3)), species=np.zeros(0, np.int32), cell=np.zeros(3),
+                  pbc=np.zeros(3, np.int32), n_local=0)
+    assert gpu_eval(m, s0)["energy"][0] == 0.0
+    iso = W.System(pos=np.array([[0.0, 0.0, 0.0], [10.0, 0.0, 0.0]]), species=np.array([0, 1], np.int32),
+                   cell=np.zeros(3), pbc=np.zeros(3, np.int32), n_local=2)
+    got = gpu_eval(m, iso)
+    assert np.all(got["forces"] == 0.0)
+    assert np.allclose(got["atom_energy"], sh[[0, 1]])
+    dimer = W.System(pos=np.array([[0.0, 0.0, 0.0], [1.3, 0.4, -0.2]]), species=np.array([1, 0], np.int32),
+                     cell=np.zeros(3), pbc=np.zeros(3, np.int32), n_local=2)
+    ref = OM.evaluate(mc, w, dimer, sc, sh)
+    got = gpu_eval(m, dimer)
+    if prec == FP32:
+        _check_fp32("deep_dimer_fp32", got, ref, 2)
+    else:
+        _check_bf16("deep_dimer_bf16_mixed", got, ref, 2)
