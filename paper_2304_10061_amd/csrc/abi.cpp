@@ -824,7 +824,7 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE((pos && species && forces) || m->n_total == 0, "pos, species and forces must not be NULL");
   const Validated& v = m->v;
-  const int d = v.d, n = v.n, LW = v.LW, dim = v.dim;
+  const int d = v.d, n = v.n, LW = v.LW;
   double* aE = atom_energy ? atom_energy : ptr<double>(m->atom_e);
   const int32_t* ei = ptr<int32_t>(m->ei);
   const int32_t* ej = ptr<int32_t>(m->ej);

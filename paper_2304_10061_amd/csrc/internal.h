@@ -147,7 +147,8 @@ struct TensorArgs {
   float c_norm = 1.0f;
   float* gam = nullptr;           // [n_centres][dim][n]
   VSrc v;                         // tensor-product input
-  const float* tpw = nullptr;     // device: non-zero weights of the fused table
+  const float* tpw = nullptr;     // device: non-zero weights of the fused table (for the
+                                  // mixing adjoint: those of the next layer)
   float tpw_v[kTpwArgs] = {0};    // the same values, passed by value (kernel argument)
   const void* mixB = nullptr;     // packed FP32 mixing matrices, one GemmB block per irrep slot
                                   // (natural l = 0..l_max, then unnatural l = 0..l_max)
@@ -160,7 +161,6 @@ struct TensorArgs {
   const float* g_s = nullptr;     // [E][n] gradient w.r.t. scalar outputs (component 0)
   const float* gam_next = nullptr;  // next layer's Gamma (to rebuild dE/dV)
   const float* g_tnext = nullptr;   // next layer's dE/dT [E][w_next_out][n]
-  const float* tpw_next = nullptr;  // next layer's fused-table non-zeros (device)
   float tp_wnext[16] = {0};         // final next layer: its diagonal weights
   float* g_tout = nullptr;        // [E][w_out][n]
   float* g_w = nullptr;           // [E][(l_max+1) n] at row stride ld_gw
