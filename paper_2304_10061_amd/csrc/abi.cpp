@@ -125,10 +125,10 @@ void make_packed(PackedMat& pm, const std::vector<double>& W, int K, int N, int 
 
 struct Validated {
   int S, nb, p, lmax, nl, n, d, dim, LW, h;
-  // irrep kinds (TpKind) of each layer's input and output features, their
-  // widths in strided components, and whether the weight file uses the
+  // irrep kinds (TpKind) of each layer's input and output features, the
+  // output width in strided components, and whether the weight file uses the
   // parity-extended alpha / mixing layouts (models with unnatural irreps)
-  int in_kind[kMaxLayers], out_kind[kMaxLayers], w_in[kMaxLayers], w_out[kMaxLayers];
+  int in_kind[kMaxLayers], out_kind[kMaxLayers], w_out[kMaxLayers];
   bool parity = false;
   std::vector<int> dims2b, dimsL;
   int64_t n_weights;
@@ -186,7 +186,6 @@ Validated validate(const AllegroConfig* c) {
     const bool last = L == v.nl - 1, penult = L == v.nl - 2;
     v.in_kind[L] = (L == 0 || last) ? kNatural : kBothParities;
     v.out_kind[L] = last ? kScalarOut : ((v.nl >= 3 && !penult) ? kBothParities : kNatural);
-    v.w_in[L] = kind_width(v.in_kind[L], v.lmax);
     v.w_out[L] = kind_width(v.out_kind[L], v.lmax);
   }
   v.parity = v.nl >= 3;

@@ -257,14 +257,14 @@ __device__ __forceinline__ void tp_run(const float* X, const float* Y, float* Z,
   (tp_term<Pat, OP, K0 + (int)K>(X, Y, Z, w), ...);
 }
 
-template <class Pat, int OP, int J>
+template <class Pat, int J>
 constexpr int tp_block_len() {
   return Pat::NNZ - J * kTpBlock < kTpBlock ? Pat::NNZ - J * kTpBlock : kTpBlock;
 }
 
 template <class Pat, int OP, class WP, std::size_t... J>
 __device__ __forceinline__ void tp_blocks(const float* X, const float* Y, float* Z, WP w, std::index_sequence<J...>) {
-  ((tp_run<Pat, OP, (int)J * kTpBlock>(X, Y, Z, w, std::make_index_sequence<tp_block_len<Pat, OP, (int)J>()>{}),
+  ((tp_run<Pat, OP, (int)J * kTpBlock>(X, Y, Z, w, std::make_index_sequence<tp_block_len<Pat, (int)J>()>{}),
     __builtin_amdgcn_sched_barrier(0)),
    ...);
 }
