@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0         # MI355X HBM3E
 # precision p: template arguments <precision, kind, tile rows, column tiles>.
 MLP_KIND = {"twobody": 0, "latent": 1, "final": 2}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_protein_box.md")
+TRAFFIC_SUMMARY_DEEP = os.path.join(ROOT, "profiles", "hbm_traffic_deep_water_box.md")
 
 
 MLP_WAVES = 8                 # waves per MLP block
@@ -114,14 +115,14 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, com
         lines.append(f"    {c}")
     lines += ["", "| kernel | calls | avg us | total ms | FETCH KiB/dispatch | WRITE KiB/dispatch |",
               "|---|---|---|---|---|---|"]
-    for name, (calls, avg, tot) in sorted(stats.items(), key=lambda kv: -kv[1][2])[:24]:
+    for name, (calls, avg, tot) in sorted(stats.items(), key=lambda kv: -kv[1][2])[:28]:
         fv, wv = fetch.get(name), write.get(name)
         fa = sum(fv) / len(fv) if fv else None
         wa = sum(wv) / len(wv) if wv else None
         short = name.replace("allegro::", "").replace("(anonymous namespace)::", "")[:90]
         lines.append(f"| `{short}` | {calls} | {avg:.1f} | {tot:.3f} | "
                      f"{'' if fa is None else f'{fa:.0f}'} | {'' if wa is None else f'{wa:.0f}'} |")
-        if fa is not None and wa is not None and "k_mlp" in name:
+        if fa is not None and wa is not None:
             blob["kernels"][short] = {"avg_us": avg, "fetch_KiB": fa, "write_KiB": wa}
     if copy_mib:
         lines += ["", "Counter scale factors from the plain copy of %d MiB (bytes per counted byte):" % copy_mib]
@@ -144,11 +145,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch(symbol):
+def traffic_per_launch(symbol, summary=None):
     """HBM bytes per launch of `symbol` from the committed counter summary,
     or None when it is missing or the sources changed since it was taken."""
     try:
-        txt = open(TRAFFIC_SUMMARY).read()
+        txt = open(summary or TRAFFIC_SUMMARY).read()
         blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
@@ -226,6 +227,27 @@ def tensor_flops_per_edge(mc, info):
                                  for k in range(nl - 1))
         out["tp_env_adjoint"] = sum(2 * nnz[k] * n + 4 * D * n + (2 * nnz[k] * n + 4 * D * n if k == 0 else 0)
                                     for k in range(nl - 1))
+    return out
+
+
+def tensor_symbols(mc):
+    """Kernel symbols (as rocprofv3 prints them) behind each timed tensor-track
+    launch kind of one step: the layers' patterns TpPattern<l_max, input kind,
+    output kind> (1 natural parity, 2 both parities, 0 the final scalar), the
+    lane groups of the adjoint kernels (64 / n channels) and, for the first
+    layer's adjoint, the rank-1 form of its input."""
+    nl, lm, G = mc.n_layers, mc.l_max, 64 // mc.n_tensor
+    kin = [1 if (L == 0 or L == nl - 1) else 2 for L in range(nl)]
+    kout = [0 if L == nl - 1 else (2 if nl >= 3 and L < nl - 2 else 1) for L in range(nl)]
+    pat = lambda L: f"TpPattern<{lm}, {kin[L]}, {kout[L]}>"
+    out = {"tp_env_adjoint_final": [f"k_tp_adjoint_gamma<{pat(nl - 1)}, {G}>",
+                                    f"k_tp_adjoint_edges<{pat(nl - 1)}, {G}, {'true' if nl == 1 else 'false'}>"]}
+    if nl > 1:
+        out["tp_mix"] = [f"k_tp_mix<{pat(L)}, 16>" for L in range(nl - 1)]
+        out["mix_adjoint"] = [f"k_mix_adjoint<{pat(L + 1)}, 16>" for L in range(nl - 1)]
+        out["tp_env_adjoint"] = [s for L in range(nl - 1)
+                                 for s in (f"k_tp_adjoint_gamma<{pat(L)}, {G}>",
+                                           f"k_tp_adjoint_edges<{pat(L)}, {G}, {'true' if L == 0 else 'false'}>")]
     return out
 
 
@@ -341,8 +363,16 @@ def deep_workload_line(steps, warmup, cpu_sample, no_cpu):
         roof = {"kernel": dom, "bound": "alu", "peak": FP32_PEAK_TFLOPS}
     achieved = flops / (kms[dom] * 1e-3) / 1e12
     launches = max(1, bf["kernel_launches"].get(dom, 1))
-    roof.update({"achieved": achieved, "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": None,
-                 "flops_per_launch": flops / launches, "avg_launch_ms": kms[dom] / launches})
+    syms = tensor_symbols(mc).get(dom)
+    traffic = None
+    if syms:
+        per = [traffic_per_launch(sym, TRAFFIC_SUMMARY_DEEP) for sym in syms]
+        traffic = sum(per) / launches if all(v is not None for v in per) else None
+    roof.update({"achieved": achieved, "unit": "TFLOP/s", "frac": achieved / roof["peak"], "traffic": traffic,
+                 "symbols": syms, "flops_per_launch": flops / launches, "avg_launch_ms": kms[dom] / launches})
+    if traffic is not None:
+        # the same launch against the HBM roof on its measured traffic
+        roof["hbm_frac_traffic"] = traffic / (kms[dom] / launches * 1e-3) / (HBM_PEAK_GBS * 1e9)
     tensor = {k: {"ms": round(kms[k], 4), "tflops": float(tfl[k]) * E / (kms[k] * 1e-3) / 1e12}
               for k in tfl if k in kms}
     out = {
@@ -510,6 +540,8 @@ def main():
               "(spatial decomposition across GPUs is not part of this build)", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibration_copy_mib:
+        calibration_copy(args.calibration_copy_mib)
     if args.workload == "deep":
         print(json.dumps(deep_workload_line(args.steps, args.warmup, min(args.cpu_sample, 512),
                                             args.no_cpu_baseline)), flush=True)
@@ -519,8 +551,6 @@ def main():
         return
 
     import workloads as W
-    if args.calibration_copy_mib:
-        calibration_copy(args.calibration_copy_mib)
     mc, s, w = W.workload(3)
     bf = run_gpu(mc, s, w, HEADLINE_PREC, args.steps, args.warmup, want_kernel_times=True)
     fp = None if args.no_fp32 else run_gpu(mc, s, w, 0, max(3, args.steps // 4), min(2, args.warmup), True)
