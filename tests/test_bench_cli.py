@@ -39,3 +39,17 @@ def test_tensor_flop_counts():
     assert f["mix_adjoint"] == 3 * 9 * 32 + 2 * 32 * 32 * 9
     assert f["tp_env_adjoint"] == 2 * (2 * 83 * 32 + 4 * 9 * 32)
     assert f["tp_env_adjoint_final"] == 2 * 9 * 32 + 4 * 9 * 32
+
+
+def test_tensor_symbols_name_profiled_kernels():
+    """The kernel symbols the deep roofline sums are the ones the committed
+    kernel-trace summary of that workload lists."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    txt = open(os.path.join(ROOT, "profiles", "hbm_traffic_deep_water_box.md")).read()
+    syms = bench.tensor_symbols(W.deep_model_config())
+    for kind, names in syms.items():
+        for s in names:
+            assert s in txt, (kind, s)
+    assert len(syms["tp_env_adjoint"]) == 4 and len(syms["tp_mix"]) == 2
