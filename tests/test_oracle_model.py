@@ -428,3 +428,24 @@ def test_zbl_continuity_at_cutoff():
     e_out = E(3.6)
     for eps in (1e-2, 1e-3):
         assert abs(E(3.0 - eps) - e_out) < 50 * eps ** 3
+
+
+@pytest.mark.parametrize("l_max,n_layers", [(2, 2), (3, 3)])
+def test_evaluate_centres_equals_whole_system(l_max, n_layers):
+    """The sampled reference of the large-box GPU tests: a subset of centres
+    evaluated from their own edges gives exactly the whole evaluation's
+    (unscaled) atom energies and edge gradients for those centres."""
+    mc = tiny_model(l_max, n_layers, n=4, d=8, rc=3.2)
+    w = weights(mc, 41)
+    s = cluster(16, 42)
+    whole = model.evaluate(mc, w, s)
+    i, j, sh = whole.nbr
+    cents = np.array([1, 5, 11, 14])
+    e_raw, g = model.evaluate_centres(mc, w, s, cents, whole.nbr)
+    atom_raw = np.zeros(s.n_local)
+    np.add.at(atom_raw, i, whole.edge_energy)
+    assert np.allclose(e_raw, atom_raw[cents], rtol=1e-12, atol=1e-13)
+    for e, ge in g.items():
+        assert i[e] in cents
+        assert np.allclose(ge, whole.edge_grad[e], rtol=1e-10, atol=1e-13)
+    assert len(g) == int(np.isin(i, cents).sum())
