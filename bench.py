@@ -561,6 +561,11 @@ def main():
     mcp.pair_cutoffs = W.paper_pair_cutoffs(mc.n_species, mc.r_cut)
     pc = None if args.no_fp32 else run_gpu(mcp, s, w, HEADLINE_PREC, max(3, args.steps // 2), min(2, args.warmup),
                                            False)
+    # the same box with the ZBL pair term (atomic numbers H 1, C 6, N 7, O 8)
+    mcz = copy.copy(mc)
+    mcz.atomic_numbers = W.atomic_numbers(mc.n_species)
+    zb = None if args.no_fp32 else run_gpu(mcz, s, w, HEADLINE_PREC, max(3, args.steps // 2), min(2, args.warmup),
+                                           False)
 
     value = s.n_local / (bf["ms_per_step"] * 1e-3)
     macs = mlp_macs_per_edge(mc)
@@ -640,6 +645,9 @@ def main():
             "value": s.n_local / (pc["ms_per_step"] * 1e-3), "ms_per_step": pc["ms_per_step"],
             "edges": pc["edges"], "edges_single_cutoff": bf["edges"],
             "speedup_vs_single_cutoff": bf["ms_per_step"] / pc["ms_per_step"], "tiles": pc["tiles"]}
+    if zb is not None:
+        out["zbl"] = {"value": s.n_local / (zb["ms_per_step"] * 1e-3), "ms_per_step": zb["ms_per_step"],
+                      "overhead_vs_plain": zb["ms_per_step"] / bf["ms_per_step"] - 1.0}
     out["tiles"] = bf["tiles"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mc, s, w, args.cpu_sample)
