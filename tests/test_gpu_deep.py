@@ -33,6 +33,8 @@ DEEP = [
     ("l1_four_layers", dict(l_max=1, n_layers=4, n_tensor=32)),
     ("l2_four_layers_n64", dict(l_max=2, n_layers=4, n_tensor=64)),
     ("l3_three_layers_no_mix", dict(l_max=3, n_layers=3, n_tensor=32, channel_mix=False)),
+    # the largest pattern (both parities in and out, 1191 non-zeros) with 64 channels
+    ("l3_four_layers_n64", dict(l_max=3, n_layers=4, n_tensor=64)),
 ]
 
 
