@@ -537,7 +537,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the energy/force path runs on a single MI355X "
-              "(spatial decomposition across GPUs is not part of this build)", file=sys.stderr)
+              "(spatial decomposition across GPUs is not implemented here)", file=sys.stderr)
         sys.exit(2)
 
     if args.calibration_copy_mib:

@@ -1,4 +1,4 @@
-"""bench.py refuses multi-GPU runs (this build measures one GPU's share)."""
+"""bench.py refuses multi-GPU runs (it measures one GPU's share)."""
 import os
 import subprocess
 import sys
