@@ -42,7 +42,9 @@ enum {
   ALLEGRO_E_CAPACITY = -3,  /* edge capacity exceeded (capacity-limited mode);
                                capacity has been regrown, call again */
   ALLEGRO_E_DEVICE = -4,    /* a HIP runtime call failed */
-  ALLEGRO_E_NONFINITE = -5, /* non-finite energy or forces were produced */
+  ALLEGRO_E_NONFINITE = -5, /* non-finite positions (allegro_neighbors), or a
+                               non-finite atom energy or force was produced
+                               (reported by allegro_check / allegro_md_run) */
   ALLEGRO_E_STATE = -6      /* call order violated (e.g. no neighbour list yet) */
 };
 
@@ -96,7 +98,11 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *   precision        one of the ALLEGRO_PREC_* modes above
  *   edge_chunk       0 = evaluate all edges at once; otherwise the largest
  *                    number of edges whose activations are held at a time
- *                    (whole centre segments; bounds workspace memory)
+ *                    (whole centre segments; bounds workspace memory).  Either
+ *                    way a chunk holds at most AllegroInfo.max_chunk_edges
+ *                    edges (32-bit workspace offsets); larger edge sets are
+ *                    split into chunks automatically, and a single centre with
+ *                    more neighbours than that is rejected (ALLEGRO_E_INVAL)
  *   neighbor_skin    extra radius of the neighbour list (A), so that a list can
  *                    be reused over several MD steps; pairs beyond r_cut carry
  *                    a zero envelope and contribute exactly zero.  0 = the list
@@ -143,6 +149,13 @@ typedef struct {
                                  ((l_max+1)^2, twice that with both parities, 1 for the last) */
   int32_t dim;                /* (l_max+1)^2 strided components */
   int32_t latent;             /* latent width d */
+  int32_t widest_row;         /* widest per-edge (or per-centre) row of the
+                                 evaluation's workspace, in floats */
+  int64_t max_chunk_edges;    /* most edges evaluated at a time: the kernels
+                                 address workspace rows with 32-bit element
+                                 offsets, so a chunk holds at most
+                                 (2^31 - 1) / widest_row edges; a larger
+                                 edge_chunk (or 0) is reduced to this */
 } AllegroInfo;
 
 /*
@@ -153,6 +166,26 @@ typedef struct {
  * Returns ALLEGRO_E_INVAL for unsupported configurations.
  */
 int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info);
+
+/*
+ * allegro_plan_chunks: the split of the centres into evaluation chunks that
+ * allegro_neighbors applies (host only, no GPU needed).  Centres [0, n_centres)
+ * are cut into consecutive runs of whole centre segments (section "Allegro:
+ * Scalable Equivariant Deep Learning": each atom's energy depends only on its
+ * own neighbours, so a run of centres is evaluated exactly as in the whole
+ * system) holding at most min(edge_chunk or unlimited, max_chunk_edges)
+ * edges each (AllegroInfo.max_chunk_edges; 32-bit workspace offsets).
+ *   edges_per_centre  host [n_centres] neighbour count of each centre
+ *   max_bounds        capacity of `bounds`
+ *   bounds            host, receives n_chunks + 1 ascending boundaries,
+ *                     bounds[0] = 0 and bounds[n_chunks] = n_centres (may be
+ *                     NULL to query the count)
+ *   n_chunks          host, receives the number of chunks (may be NULL)
+ * Returns ALLEGRO_E_INVAL when one centre has more edges than a chunk may
+ * hold or `bounds` is too small.
+ */
+int allegro_plan_chunks(const AllegroConfig* cfg, int64_t n_centres, const int32_t* edges_per_centre,
+                        int64_t max_bounds, int64_t* bounds, int64_t* n_chunks);
 
 /*
  * allegro_create: build a model on the current HIP device.
@@ -289,11 +322,24 @@ int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const 
  *   use_graph    1 = capture one step in a HIP graph (captured once per
  *                neighbour list and argument set) and replay it n_steps times
  *   max_disp     host, receives the largest centre displacement since the
- *                neighbour build (synchronises the stream; may be NULL)
+ *                neighbour build (may be NULL)
+ * Synchronises the stream at the end and returns ALLEGRO_E_NONFINITE (as
+ * allegro_check) when a step produced non-finite forces or energies.
  */
 int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos,
                    double* vel, double* forces, const int32_t* species, double* thermo,
                    int32_t init_forces, int32_t use_graph, void* stream, double* max_disp);
+
+/*
+ * allegro_check: synchronise `stream` and report what the device recorded
+ * since the last check (allegro_energy_forces itself does not synchronise).
+ * Returns ALLEGRO_E_NONFINITE when an evaluation produced a non-finite atom
+ * energy or force (e.g. two atoms at the same position: the pair direction is
+ * undefined), else ALLEGRO_OK; the record is cleared either way.  Forces are
+ * F = -dE/dx of a smooth energy (section "Problem overview"), so a non-finite
+ * value means the input left the potential's domain.
+ */
+int allegro_check(AllegroModel* m, void* stream);
 
 /*
  * allegro_copy_edges: copy the current neighbour list to caller buffers.

@@ -6,7 +6,7 @@ exposes the energy as a torch.autograd.Function whose backward is the
 library's hand-written adjoint.
 """
 from .binding import (AllegroConfig, AllegroError, Model, PREC_BF16, PREC_BF16_MIXED, PREC_BF16_SINGLE, PREC_FP32,
-                      config_from, describe, load_library, make_config)
+                      config_from, describe, load_library, make_config, plan_chunks)
 
 __all__ = ["AllegroConfig", "AllegroError", "Model", "PREC_BF16", "PREC_BF16_MIXED", "PREC_BF16_SINGLE", "PREC_FP32",
-           "config_from", "describe", "load_library", "make_config"]
+           "config_from", "describe", "load_library", "make_config", "plan_chunks"]

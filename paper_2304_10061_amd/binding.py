@@ -23,9 +23,9 @@ STATUS = {0: "ALLEGRO_OK", -1: "ALLEGRO_E_INVAL", -2: "ALLEGRO_E_NOMEM", -3: "AL
 PREC_FP32, PREC_BF16, PREC_BF16_SINGLE, PREC_BF16_MIXED = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU tests).
-EXPORTS = ("allegro_describe", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
+EXPORTS = ("allegro_describe", "allegro_plan_chunks", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
            "allegro_system_energies", "allegro_energy_forces",
-           "allegro_autotune", "allegro_set_tiles", "allegro_set_ghosts", "allegro_md_run", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
+           "allegro_autotune", "allegro_set_tiles", "allegro_set_ghosts", "allegro_md_run", "allegro_check", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
            "allegro_workspace_bytes", "allegro_destroy", "allegro_last_error", "allegro_status_string")
 
 
@@ -46,7 +46,8 @@ class AllegroConfig(ctypes.Structure):
 class AllegroInfo(ctypes.Structure):
     _fields_ = [("n_weights", ctypes.c_int64), ("n_paths", ctypes.c_int32 * 4),
                 ("n_nonzero", ctypes.c_int32 * 4), ("width", ctypes.c_int32 * 4), ("dim", ctypes.c_int32),
-                ("latent", ctypes.c_int32)]
+                ("latent", ctypes.c_int32), ("widest_row", ctypes.c_int32),
+                ("max_chunk_edges", ctypes.c_int64)]
 
 
 class AllegroError(RuntimeError):
@@ -73,6 +74,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     lib.allegro_describe.argtypes = [ctypes.POINTER(AllegroConfig), ctypes.POINTER(AllegroInfo)]
     lib.allegro_describe.restype = ctypes.c_int
+    lib.allegro_plan_chunks.argtypes = [ctypes.POINTER(AllegroConfig), i64, vp, i64, vp, ctypes.POINTER(i64)]
+    lib.allegro_plan_chunks.restype = ctypes.c_int
     lib.allegro_create.argtypes = [ctypes.POINTER(AllegroConfig), vp, i64, vp, vp, ctypes.POINTER(vp)]
     lib.allegro_create.restype = ctypes.c_int
     lib.allegro_neighbors.argtypes = [vp, i64, i64, dp, dp, vp, vp, vp, ctypes.POINTER(i64)]
@@ -92,6 +95,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, i32, i32, vp,
                                    ctypes.POINTER(ctypes.c_double)]
     lib.allegro_md_run.restype = ctypes.c_int
+    lib.allegro_check.argtypes = [vp, vp]
+    lib.allegro_check.restype = ctypes.c_int
     lib.allegro_copy_edges.argtypes = [vp, dp, dp, dp, vp]
     lib.allegro_copy_edges.restype = ctypes.c_int
     lib.allegro_num_edges.argtypes = [vp]
@@ -172,6 +177,22 @@ def describe(cfg: AllegroConfig) -> AllegroInfo:
     if st != ALLEGRO_OK:
         raise AllegroError(st, lib.allegro_last_error(None).decode())
     return info
+
+
+def plan_chunks(cfg: AllegroConfig, edges_per_centre) -> np.ndarray:
+    """Chunk boundaries (centre indices) that allegro_neighbors would use."""
+    lib = load_library()
+    cnt = np.ascontiguousarray(edges_per_centre, dtype=np.int32)
+    n = ctypes.c_int64(0)
+    st = lib.allegro_plan_chunks(ctypes.byref(cfg), cnt.size, cnt.ctypes.data, 0, None, ctypes.byref(n))
+    if st != ALLEGRO_OK:
+        raise AllegroError(st, lib.allegro_last_error(None).decode())
+    out = np.zeros(n.value + 1, dtype=np.int64)
+    st = lib.allegro_plan_chunks(ctypes.byref(cfg), cnt.size, cnt.ctypes.data, out.size, out.ctypes.data,
+                                 ctypes.byref(n))
+    if st != ALLEGRO_OK:
+        raise AllegroError(st, lib.allegro_last_error(None).decode())
+    return out
 
 
 def _ptr(t) -> Optional[int]:
@@ -294,6 +315,11 @@ class Model:
                                             ctypes.byref(md) if want_max_disp else None))
         return md.value if want_max_disp else None
 
+    def check(self, stream=None):
+        """Synchronise and raise AllegroError if an evaluation since the last
+        check produced non-finite energies or forces."""
+        self._check(self.lib.allegro_check(self.handle, _stream(stream)))
+
     def num_edges(self) -> int:
         return int(self.lib.allegro_num_edges(self.handle))
 
@@ -342,4 +368,5 @@ class Model:
             out["atom_virial"] = torch.empty((n_total, 9), dtype=torch.float64, device=dev)
         self.energy_forces(pos, species, out["forces"], out["atom_energy"], out["virial"],
                            out.get("atom_virial"), out["energy"])
+        self.check()   # synchronises; raises on non-finite outputs
         return out

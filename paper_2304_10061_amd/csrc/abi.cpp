@@ -207,6 +207,52 @@ Validated validate(const AllegroConfig* c) {
   return v;
 }
 
+// Widest row, in floats, of any array the kernels index by (chunk-local edge
+// or centre) x (row stride) with 32-bit element offsets: the edge record,
+// latent rows, heads and their gradients, tensor features and their adjoints
+// (up to 2 dim n floats per edge with both parities), per-centre environment
+// sums (dim n per centre, and a chunk never has more centres than edges).
+int64_t widest_row(const Validated& v) {
+  int64_t w = std::max<int64_t>(kEB, gy_width(v.lmax));
+  w = std::max<int64_t>(w, v.d);
+  w = std::max<int64_t>(w, 2 * (int64_t)v.LW);
+  w = std::max<int64_t>(w, (int64_t)v.dim * v.n);
+  for (int L = 0; L < v.nl; ++L) w = std::max<int64_t>(w, (int64_t)v.w_out[L] * v.n);
+  for (int wd : v.dims2b) w = std::max<int64_t>(w, wd);
+  for (int wd : v.dimsL) w = std::max<int64_t>(w, wd);
+  return w;
+}
+
+// Largest number of edges one chunk may hold: every edge-row offset of the
+// chunk stays below 2^31 elements (so signed and unsigned 32-bit offset
+// arithmetic alike cannot wrap).
+int64_t max_chunk_edges(const Validated& v) { return (((int64_t)1 << 31) - 1) / widest_row(v); }
+
+// Splits centres [0, n_centres) into consecutive chunks of whole centre
+// segments holding at most `cap` edges each (row_ptr[c] = first edge of centre
+// c).  Returns the chunk boundaries (first entry 0, last n_centres); throws
+// when a single centre has more than `cap` edges.
+std::vector<int64_t> plan_chunks(const int64_t* row_ptr, int64_t n_centres, int64_t cap) {
+  std::vector<int64_t> bounds(1, 0);
+  int64_t c = 0;
+  while (c < n_centres) {
+    REQUIRE(row_ptr[c + 1] - row_ptr[c] <= cap,
+            "centre " + std::to_string(c) + " has more edges than one chunk may hold");
+    int64_t b = c + 1;
+    while (b < n_centres && row_ptr[b + 1] - row_ptr[c] <= cap) ++b;
+    bounds.push_back(b);
+    c = b;
+  }
+  return bounds;
+}
+
+// Edges per chunk for a configuration: edge_chunk (0 = unlimited), capped so
+// that 32-bit offsets cannot wrap.
+int64_t chunk_cap(const Validated& v, int64_t edge_chunk) {
+  const int64_t hard = max_chunk_edges(v);
+  return edge_chunk > 0 ? std::min(edge_chunk, hard) : hard;
+}
+
 // Paths of a layer with the given kinds, as (l1, s1, l2, l_out, s_out) with s = 0
 // for natural and 1 for unnatural parity.
 struct PathId { int l1, s1, l2, lo, so; };
@@ -339,6 +385,7 @@ struct AllegroModel {
   DevBuf ei, ej, es, row_ptr, rrow_ptr, redge, keys;
   DevBuf cell_of, img, cell_count, cell_start, cell_cursor, cell_atoms, count, rcount, rcursor;
   DevBuf bbox, scan_tmp, err_flag;
+  DevBuf status;                          // sticky device status bits (kStatus*)
   int n_sys = 0;                          // batched mode: number of independent systems
   DevBuf sys_off, sys_id, sys_shift;
   std::vector<int32_t> h_row_ptr;
@@ -544,6 +591,9 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   upload(m->shift, sh.data(), sh.size() * sizeof(double));
   m->c_norm = 1.0 / std::sqrt(m->cfg.avg_num_neighbors);
   m->err_flag.ensure(sizeof(int));
+  m->status.ensure(sizeof(int));
+  HIP_OK(launch_fill_i32(m->status.as<int32_t>(), 0, 1, nullptr));
+  HIP_OK(hipDeviceSynchronize());
   // check the MLP kernels fit in LDS for this configuration
   MlpArgs probe;
   probe.d = d; probe.n = n; probe.w = m->twobody.view(); probe.head = m->head0.g; probe.head_bwd = m->head0T.g;
@@ -741,7 +791,12 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   if (herr & 2) throw Fail{ALLEGRO_E_NONFINITE, "non-finite positions"};
   if (herr & 1) throw Fail{ALLEGRO_E_INVAL, "positions lie more than 500 box lengths outside the box"};
   if (herr & 4) throw Fail{ALLEGRO_E_INVAL, "species out of range [0, n_species)"};
+  // each centre's count is below 2^31, so a running sum that passes 2^31
+  // shows as a decrease; the force gather indexes g_e [E][3] with int32
+  for (int64_t q = 0; q < n_local; ++q)
+    REQUIRE(m->h_row_ptr[q + 1] >= m->h_row_ptr[q], "more than 2^31 - 1 edges");
   const int64_t E = m->h_row_ptr[n_local];
+  REQUIRE(E <= ((((int64_t)1 << 31) - 1) / 3), "more than (2^31 - 1) / 3 edges");
   m->E = E;
   const int64_t Ee = std::max<int64_t>(E, 1);
   m->ei.ensure(Ee * 4); m->ej.ensure(Ee * 4); m->es.ensure(Ee * 12); m->keys.ensure(Ee * 8);
@@ -755,17 +810,15 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   HIP_OK(launch_reverse_csr(a, E, s));
 
   // chunks of whole centres and the workspace they need
-  const int64_t cap = m->cfg.edge_chunk > 0 ? m->cfg.edge_chunk : INT64_MAX;
-  m->chunk_c.assign(1, 0);
-  int64_t c = 0;
+  {
+    std::vector<int64_t> rp64(m->h_row_ptr.begin(), m->h_row_ptr.end());
+    m->chunk_c = plan_chunks(rp64.data(), n_local, chunk_cap(m->v, m->cfg.edge_chunk));
+  }
   m->Ec = 0; m->Nc = 0;
-  while (c < n_local) {
-    int64_t b = c + 1;
-    while (b < n_local && m->h_row_ptr[b + 1] - m->h_row_ptr[c] <= cap) ++b;
-    m->Ec = std::max<int64_t>(m->Ec, m->h_row_ptr[b] - m->h_row_ptr[c]);
-    m->Nc = std::max<int64_t>(m->Nc, b - c);
-    m->chunk_c.push_back(b);
-    c = b;
+  for (size_t k = 0; k + 1 < m->chunk_c.size(); ++k) {
+    const int64_t cA = m->chunk_c[k], cB = m->chunk_c[k + 1];
+    m->Ec = std::max<int64_t>(m->Ec, m->h_row_ptr[cB] - m->h_row_ptr[cA]);
+    m->Nc = std::max<int64_t>(m->Nc, cB - cA);
   }
   {
     std::vector<int32_t> crp;
@@ -982,10 +1035,26 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
   fa.rrow_ptr = ptr<int32_t>(m->rrow_ptr); fa.redge = ptr<int32_t>(m->redge); fa.ei = ei; fa.ej = ej; fa.es = es;
   for (int ax = 0; ax < 3; ++ax) fa.L[ax] = m->L[ax];
   fa.g_e = ptr<float>(m->g_e); fa.forces = forces; fa.atom_virial = atom_virial;
-  fa.partial = ptr<double>(m->partial); fa.atom_energy = aE;
+  fa.partial = ptr<double>(m->partial); fa.atom_energy = aE; fa.status = ptr<int>(m->status);
   int nb = 0;
   timed(m, "forces", s, [&] { return launch_forces(fa, &nb, s); });
   if (virial || energy) timed(m, "final_sums", s, [&] { return launch_final_sums(fa.partial, nb, virial, energy, s); });
+}
+
+// Synchronises `s`, reads and clears the sticky device status and turns it
+// into a status code.
+int take_status(AllegroModel* m, hipStream_t s) {
+  int h = 0;
+  HIP_OK(hipMemcpyAsync(&h, m->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (h == 0) return ALLEGRO_OK;
+  HIP_OK(launch_fill_i32(ptr<int32_t>(m->status), 0, 1, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (h & kStatusNonFinite) {
+    m->err = "a previous evaluation produced non-finite energies or forces";
+    return ALLEGRO_E_NONFINITE;
+  }
+  return ALLEGRO_OK;
 }
 
 void release_graph(AllegroModel* m) {
@@ -1075,6 +1144,8 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
     for (double v : part) mx = std::max(mx, v);
     *max_disp = std::sqrt(mx);
   }
+  const int st = take_status(m, s);
+  if (st != ALLEGRO_OK) throw Fail{st, m->err};
 }
 
 const char* const kTuneNames[8] = {"mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd_final", "mlp_bwd_final",
@@ -1218,6 +1289,8 @@ int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info) {
       info->n_weights = v.n_weights;
       info->dim = v.dim;
       info->latent = v.d;
+      info->widest_row = (int32_t)widest_row(v);
+      info->max_chunk_edges = max_chunk_edges(v);
       for (int L = 0; L < kMaxLayers; ++L) {
         info->n_paths[L] = 0;
         info->n_nonzero[L] = 0;
@@ -1232,6 +1305,33 @@ int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info) {
     return ALLEGRO_OK;
   } catch (const Fail& f) {
     return fail(nullptr, f);
+  } catch (...) {
+    return fail(nullptr, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_plan_chunks(const AllegroConfig* cfg, int64_t n_centres, const int32_t* edges_per_centre,
+                        int64_t max_bounds, int64_t* bounds, int64_t* n_chunks) {
+  try {
+    const Validated v = validate(cfg);
+    REQUIRE(n_centres >= 0 && (edges_per_centre || n_centres == 0), "need n_centres >= 0 and edge counts");
+    std::vector<int64_t> rp((size_t)n_centres + 1, 0);
+    for (int64_t c = 0; c < n_centres; ++c) {
+      REQUIRE(edges_per_centre[c] >= 0, "negative edge count");
+      rp[c + 1] = rp[c] + edges_per_centre[c];
+    }
+    const std::vector<int64_t> b = plan_chunks(rp.data(), n_centres, chunk_cap(v, cfg->edge_chunk));
+    const int64_t nch = (int64_t)b.size() - 1;
+    if (n_chunks) *n_chunks = nch;
+    if (bounds) {
+      REQUIRE(max_bounds >= nch + 1, "bounds holds fewer than n_chunks + 1 entries");
+      for (int64_t k = 0; k <= nch; ++k) bounds[k] = b[k];
+    }
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(nullptr, f);
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
   } catch (...) {
     return fail(nullptr, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
   }
@@ -1341,6 +1441,15 @@ int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* spe
     return fail(m, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
   } catch (...) {
     return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_check(AllegroModel* m, void* stream) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    return take_status(m, (hipStream_t)stream);
+  } catch (const Fail& f) {
+    return fail(m, f);
   }
 }
 

@@ -245,6 +245,9 @@ __global__ __launch_bounds__(256) void k_forces(ForceArgs a) {
     if (a.atom_virial)
       for (int q = 0; q < 9; ++q) a.atom_virial[9 * k + q] = av[q];
     if (k < a.n_local) en = a.atom_energy[k];
+    // sticky report of non-finite outputs (read and cleared by the host)
+    if (a.status && !(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]) && isfinite(en)))
+      atomicOr(a.status, kStatusNonFinite);
   }
   for (int q = 0; q < 9; ++q) red[q][threadIdx.x] = av[q];
   red[9][threadIdx.x] = en;

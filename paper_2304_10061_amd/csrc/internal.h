@@ -36,6 +36,10 @@ __host__ __device__ constexpr int eb_y(int c) { return c < 9 ? c : kEB_Y3 + (c -
 // Row stride of the dE/dY buffers.
 __host__ __device__ constexpr int gy_width(int l_max) { return l_max >= 3 ? 16 : 9; }
 
+// Bits of the model's sticky device status word: set by kernels, read and
+// cleared by the host at its next check.
+constexpr int kStatusNonFinite = 1;   // a force or atom energy was not finite
+
 constexpr int kMaxLayers = 4;
 constexpr int kTpwArgs = 83;  // fused-table non-zeros passed by value (larger tables are read from memory)
 
@@ -213,6 +217,7 @@ struct ForceArgs {
   double* atom_virial = nullptr;      // may be null
   double* partial = nullptr;          // [n_blocks][10]  (virial 9 + energy 1)
   const double* atom_energy = nullptr;
+  int* status = nullptr;              // sticky device status bits (kStatus*), or null
 };
 hipError_t launch_forces(const ForceArgs& a, int* n_blocks, hipStream_t s);
 hipError_t launch_final_sums(const double* partial, int n_blocks, double* virial, double* energy,

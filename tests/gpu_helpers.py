@@ -5,6 +5,7 @@ import torch
 
 import paper_2304_10061_amd as P
 import workloads as W
+from oracle import model as OM
 
 
 def device():
@@ -39,3 +40,24 @@ def gpu_edges(model, sysm):
     ci, nj, sh = model.copy_edges()
     torch.cuda.synchronize()
     return ci.cpu().numpy().astype(np.int64), nj.cpu().numpy().astype(np.int64), sh.cpu().numpy().astype(np.int64)
+
+
+def sampled_reference(mc, s, w, nbr, rng, n_centres=24, n_force_atoms=3):
+    """Oracle energies of `n_centres` random centres and the forces on the
+    first `n_force_atoms` of them (every edge touching those atoms is
+    evaluated: their own segments and the segments of the centres that have
+    them as neighbours)."""
+    i, j, _ = nbr
+    cents = np.sort(rng.choice(s.n_local, size=n_centres, replace=False))
+    p = OM.Params(mc, w)
+    e_raw, _ = OM.evaluate_centres(mc, w, s, cents, nbr, params=p)
+    atoms = cents[:n_force_atoms]
+    need = np.unique(np.concatenate([atoms, i[np.isin(j, atoms)]]))
+    _, g = OM.evaluate_centres(mc, w, s, need, nbr, params=p)
+    F = np.zeros((len(atoms), 3))
+    for k, a in enumerate(atoms):
+        for e in np.nonzero(i == a)[0]:
+            F[k] += g[int(e)]
+        for e in np.nonzero(j == a)[0]:
+            F[k] -= g[int(e)]
+    return cents, e_raw, atoms, F

@@ -19,7 +19,8 @@ from oracle import model as OM
 from oracle.neighbors import neighbor_list
 
 from gpu_helpers import gpu_eval, gpu_model
-from test_gpu_parity import _check_bf16, _check_fp32, _report, _sampled_reference
+from gpu_helpers import sampled_reference as _sampled_reference
+from test_gpu_parity import _check_bf16, _check_fp32, _report
 
 pytestmark = pytest.mark.gpu
 

@@ -240,51 +240,8 @@ def test_empty_and_isolated():
     assert got["energy"][0] == 0.0
 
 
-# ----------------------------------------------------------------------------- full-size protein box
-
-@pytest.fixture(scope="module")
-def cfg3():
-    mc, s, w = W.workload(3)
-    nbr = neighbor_list(s.pos, s.cell, s.pbc, mc.r_cut, method="kdtree")
-    return mc, s, w, nbr
-
-
-def _sampled_reference(mc, s, w, nbr, rng):
-    i, j, _ = nbr
-    cents = np.sort(rng.choice(s.n_local, size=24, replace=False))
-    p = OM.Params(mc, w)
-    e_raw, _ = OM.evaluate_centres(mc, w, s, cents, nbr, params=p)
-    atoms = cents[:3]
-    need = np.unique(np.concatenate([atoms, i[np.isin(j, atoms)]]))
-    _, g = OM.evaluate_centres(mc, w, s, need, nbr, params=p)
-    F = np.zeros((len(atoms), 3))
-    for k, a in enumerate(atoms):
-        for e in np.nonzero(i == a)[0]:
-            F[k] += g[int(e)]
-        for e in np.nonzero(j == a)[0]:
-            F[k] -= g[int(e)]
-    return cents, e_raw, atoms, F
-
-
-@pytest.mark.parametrize("prec", [FP32, BF16, BF16M], ids=["fp32", "bf16", "bf16_mixed"])
-def test_protein_box_sampled(cfg3, prec):
-    mc, s, w, nbr = cfg3
-    got = gpu_eval(gpu_model(mc, w, prec), s, want_atom_virial=False)
-    cents, e_ref, atoms, F_ref = _sampled_reference(mc, s, w, nbr, np.random.default_rng(3))
-    dEi = got["atom_energy"][cents] - e_ref
-    dF = got["forces"][atoms] - F_ref
-    frms = float(np.sqrt((F_ref ** 2).mean()))
-    _report(f"cfg3_{_PNAME.get(prec, prec)}", mean_dEi=float(abs(dEi.mean())),
-            max_dEi=float(np.abs(dEi).max()), max_dF=float(np.abs(dF).max()), Frms=frms,
-            net_force=float(np.abs(got["forces"].sum(0)).max()))
-    if prec == FP32:
-        assert abs(dEi.mean()) <= 1e-6 and np.abs(dEi).max() <= 1e-5
-        assert np.abs(dF).max() <= 1e-4
-    else:
-        assert abs(dEi.mean()) <= 1e-3
-        assert np.sqrt((dF ** 2).mean()) <= 0.01 * frms
-    # periodic box: zero net force up to FP32 accumulation
-    assert np.abs(got["forces"].sum(0)).max() < 1e-6 * s.n_local
+# The full-size protein box (whole-box fixture, every tile shape) is covered
+# by test_gpu_protein_box.py.
 
 
 # ----------------------------------------------------------------------------- interface behaviour
@@ -314,6 +271,45 @@ def test_error_paths():
     # the model stays usable after errors
     got = gpu_eval(m, s)
     assert np.isfinite(got["energy"][0])
+
+
+def test_nonfinite_outputs_reported():
+    """Two atoms at the same position: the pair direction (and the radial
+    basis sin(k d)/d) is undefined, the kernels produce NaN without faulting,
+    and allegro_check reports ALLEGRO_E_NONFINITE; the record is then cleared
+    and the model stays usable."""
+    mc = W.model_config(2)
+    w = W.make_weights(mc, np.random.default_rng(1))
+    m = gpu_model(mc, w, FP32)
+    pos = np.array([[0.0, 0.0, 0.0], [1.2, 0.3, 0.1], [1.2, 0.3, 0.1], [2.5, 0.0, 0.0]])
+    s = W.System(pos=pos, species=np.array([1, 0, 0, 1], np.int32), cell=np.zeros(3),
+                 pbc=np.zeros(3, np.int32), n_local=4)
+    with pytest.raises(P.AllegroError) as ex:
+        gpu_eval(m, s)
+    assert ex.value.status == -5
+    m.check()                                  # cleared by the report
+    ok = W.System(pos=pos[[0, 1, 3]], species=np.array([1, 0, 1], np.int32), cell=np.zeros(3),
+                  pbc=np.zeros(3, np.int32), n_local=3)
+    ref = OM.evaluate(mc, w, ok)
+    got = gpu_eval(m, ok)
+    _check_fp32("after_nonfinite", got, ref, 3)
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16M], ids=["fp32", "bf16_mixed"])
+def test_autotune_water_box(cfg2, prec):
+    """allegro_autotune picks per-kernel tile shapes; the evaluation at those
+    shapes matches the oracle."""
+    mc, s, w, sc, sh, ref = cfg2
+    m = gpu_model(mc, w, prec, sc, sh)
+    pos, sp = to_dev(s)
+    m.neighbors(pos, sp, s.cell, s.pbc, s.n_local)
+    picks = m.autotune(pos, sp)
+    _report(f"cfg2_autotune_{_PNAME[prec]}", **{k: int(v) for k, v in picks.items()})
+    got = gpu_eval(m, s)
+    if prec == FP32:
+        _check_fp32("cfg2_autotuned", got, ref, s.n_local)
+    else:
+        _check_bf16("cfg2_autotuned", got, ref, s.n_local)
 
 
 def test_autograd_function():

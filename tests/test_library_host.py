@@ -100,3 +100,73 @@ def test_describe_accepts_pair_cutoffs():
     assert a.n_weights == b.n_weights
     with pytest.raises(ValueError):
         P.make_config(r_cut_pair=((3.0, 4.0),), **kw)
+
+
+# ----------------------------------------------------------------------------- 32-bit workspace offsets
+
+def _deep4_lmax3_n64():
+    return W.ModelConfig(n_species=2, r_cut=4.0, l_max=3, n_layers=4, n_tensor=64,
+                         twobody_dims=(128, 128), latent_dims=(128, 128), edge_dims=(128,))
+
+
+@pytest.mark.parametrize("name,mc,widest", [
+    ("protein_box_model", W.model_config(3), 9 * 64),            # V of the first layer: dim n floats per edge
+    ("subdomain_model", W.model_config(4), 3 * 3 * 32),          # [a0 | w^1] head: 2 (l_max+1) n = dim n
+    ("deep4_lmax3_n64", _deep4_lmax3_n64(), 2 * 16 * 64),        # both-parity features: 2 dim n
+])
+def test_chunk_cap_keeps_offsets_below_2_31(name, mc, widest):
+    info = P.describe(P.config_from(mc))
+    assert info.widest_row == widest
+    assert info.max_chunk_edges > 0
+    assert info.max_chunk_edges * info.widest_row < 2 ** 31
+    assert (info.max_chunk_edges + 1) * info.widest_row >= 2 ** 31 - 1
+
+
+def _check_plan(bounds, counts, cap):
+    assert bounds[0] == 0 and bounds[-1] == len(counts)
+    assert np.all(np.diff(bounds) > 0)
+    rp = np.concatenate([[0], np.cumsum(counts, dtype=np.int64)])
+    per = rp[bounds[1:]] - rp[bounds[:-1]]
+    assert per.max() <= cap
+    # greedy: no chunk could have taken the next centre as well
+    nxt = rp[np.minimum(bounds[1:-1] + 1, len(counts))] - rp[bounds[:-2]]
+    assert np.all(nxt > cap)
+    return per
+
+
+def test_plan_chunks_one_gpu_subdomain_share():
+    """The 1M-atom subdomain with its ghost shell: about 27 neighbours per
+    centre, ~32M edges, more than one chunk may hold at 288 floats per edge
+    row -- the list is split into whole-centre chunks automatically."""
+    mc = W.model_config(4)
+    rng = np.random.default_rng(0)
+    counts = rng.poisson(31.7, size=1_000_000).astype(np.int32)
+    cfg = P.config_from(mc, edge_chunk=0)
+    info = P.describe(cfg)
+    b = P.plan_chunks(cfg, counts)
+    per = _check_plan(b, counts, info.max_chunk_edges)
+    assert len(b) - 1 >= int(np.ceil(counts.sum() / info.max_chunk_edges))
+    assert per.max() * info.widest_row < 2 ** 31
+    # an explicit bound below the cap is kept, one above it is reduced
+    small = P.plan_chunks(P.config_from(mc, edge_chunk=4_000_000), counts)
+    _check_plan(small, counts, 4_000_000)
+    big = P.plan_chunks(P.config_from(mc, edge_chunk=10 ** 12), counts)
+    assert np.array_equal(big, b)
+
+
+def test_plan_chunks_deep_model_and_limits():
+    mc = _deep4_lmax3_n64()
+    cfg = P.config_from(mc)
+    info = P.describe(cfg)
+    counts = np.full(400_000, 60, np.int32)            # 24M edges at 2048 floats per row
+    b = P.plan_chunks(cfg, counts)
+    per = _check_plan(b, counts, info.max_chunk_edges)
+    assert per.max() * info.widest_row < 2 ** 31
+    # a centre with more neighbours than a chunk may hold is rejected
+    bad = counts.copy()
+    bad[7] = info.max_chunk_edges + 1
+    with pytest.raises(P.AllegroError) as ex:
+        P.plan_chunks(cfg, bad)
+    assert ex.value.status == -1
+    # empty input: a single boundary
+    assert list(P.plan_chunks(cfg, np.zeros(0, np.int32))) == [0]
