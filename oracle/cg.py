@@ -71,14 +71,6 @@ def gaunt(l1: int, l2: int, l3: int) -> np.ndarray:
     return np.einsum("q,qa,qb,qc->abc", w, s(l1), s(l2), s(l3)) / (4.0 * math.pi)
 
 
-def coupling(l1: int, l2: int, l3: int) -> np.ndarray:
-    """Gaunt tensor rescaled to unit Frobenius norm (zero tensor if it vanishes)."""
-    g = gaunt(l1, l2, l3)
-    g[np.abs(g) < 1e-13] = 0.0
-    nrm = np.linalg.norm(g)
-    return g / nrm if nrm > 0 else g
-
-
 def _triangle(l1, l2, lo):
     return abs(l1 - l2) <= lo <= l1 + l2
 

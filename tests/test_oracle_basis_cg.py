@@ -234,3 +234,46 @@ def test_path_fusion_equals_per_path_sum():
         out[lo * lo:(lo + 1) ** 2] += al[l1, l2, lo] / math.sqrt(per_out[lo]) * np.einsum(
             "abc,a,b->c", C, x[l1 * l1:(l1 + 1) ** 2], y[l2 * l2:(l2 + 1) ** 2])
     assert np.allclose(fused, out, atol=1e-13)
+
+
+# Number of kept paths into each output irrep (l_out, p_out), counted by hand
+# from the selection rules (triangle, p_out = p1 p2, l_out <= l_max, pruning
+# towards the final scalar), independently of the oracle's enumeration:
+#   l_max 1, one layer: 0e <- (0,0), (1,1).
+#   l_max 2, two layers: layer 1 (natural inputs, natural outputs) 0e <- (0,0),
+#     (1,1), (2,2); 1o <- (0,1), (1,0), (1,2), (2,1); 2e <- (0,2), (2,0), (1,1),
+#     (2,2); final 0e <- (0,0), (1,1), (2,2).
+#   l_max 2, three layers: layer 1 also feeds the unnatural 1e <- (1,1), (2,2)
+#     and 2o <- (1,2), (2,1); layer 2 adds to its natural outputs 1o <- (1e,1),
+#     (2o,2) and 2e <- (1e,2), (2o,1).
+HAND_PATHS_PER_OUTPUT = {
+    (1, 1): [{(0, 1): 2}],
+    (2, 2): [{(0, 1): 3, (1, -1): 4, (2, 1): 4}, {(0, 1): 3}],
+    (2, 3): [{(0, 1): 3, (1, -1): 4, (2, 1): 4, (1, 1): 2, (2, -1): 2},
+             {(0, 1): 3, (1, -1): 6, (2, 1): 6}, {(0, 1): 3}],
+}
+
+
+@pytest.mark.parametrize("model", sorted(HAND_PATHS_PER_OUTPUT), ids=lambda m: f"lmax{m[0]}_layers{m[1]}")
+def test_path_weight_scale_by_hand_counts(model):
+    """Reading of the path weights: alpha_p = raw_p / sqrt(P_out), P_out the
+    number of kept paths into p's output irrep.  With a single unit raw weight
+    the fused table is that path's unit-norm coupling divided by sqrt(P_out),
+    so its Frobenius norm must be 1/sqrt of the hand-counted P_out (a wrong
+    count in the oracle's fusion changes it)."""
+    l_max, n_layers = model
+    layers = cg.layer_paths(l_max, n_layers)
+    widths = cg.layer_widths(l_max, n_layers)
+    deep = cg.has_unnatural(l_max, n_layers)
+    for L, paths in enumerate(layers):
+        hand = HAND_PATHS_PER_OUTPUT[model][L]
+        assert sum(hand.values()) == len(paths)
+        final = L == len(layers) - 1
+        for (l1, p1, l2, lo, po) in paths:
+            raw = np.zeros((2, l_max + 1, l_max + 1, l_max + 1) if deep else (l_max + 1,) * 3)
+            if deep:
+                raw[0 if p1 == cg.natural(l1) else 1, l1, l2, lo] = 1.0
+            else:
+                raw[l1, l2, lo] = 1.0
+            W = cg.fused_table(l_max, paths, raw, final, n_in=widths[L][0], n_out=widths[L][1])
+            assert abs(np.linalg.norm(W) - 1.0 / math.sqrt(hand[(lo, po)])) < 1e-12, (L, l1, p1, l2, lo, po)
