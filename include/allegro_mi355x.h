@@ -273,6 +273,33 @@ int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* spe
                           double* atom_energy, double* forces, double* virial,
                           double* atom_virial, double* energy, void* stream);
 
+/* Size of the static workspace of allegro_energy_forces_noalloc (bytes, one
+ * array per GPU the library runs on, held until the process ends). */
+#define ALLEGRO_NOALLOC_SCRATCH_BYTES (256u << 20)
+
+/*
+ * allegro_energy_forces_noalloc: allegro_energy_forces for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results; its
+ * per-evaluation workspace (activations, gradients, per-edge dE/dr, partial
+ * sums) lives in a static device array of ALLEGRO_NOALLOC_SCRATCH_BYTES per GPU
+ * instead of the model's workspace, and it calls no allocator of any kind and
+ * records no per-kernel timing.  The neighbour list must come from an earlier
+ * allegro_neighbors call (which allocates) on the current device.
+ *   Returns ALLEGRO_E_INVAL, with the required size in allegro_last_error,
+ *   when the list's largest chunk needs more workspace than the static array
+ *   holds (build the list with a smaller edge_chunk: whole centre segments are
+ *   evaluated a chunk at a time, so any system fits with a small enough
+ *   chunk); ALLEGRO_E_STATE without a neighbour list.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (no kernel expects it cleared): calls that overlap in time on one
+ * GPU (two streams, two threads, two models) race and must be serialised by
+ * the caller.  Does not synchronise.
+ */
+int allegro_energy_forces_noalloc(AllegroModel* m, const double* pos, const int32_t* species,
+                                  double* atom_energy, double* forces, double* virial,
+                                  double* atom_virial, double* energy, void* stream);
+
 /*
  * allegro_autotune: time the candidate edge-tile shapes of the edge-batched
  * kernels (MLP chains: 128, 64 or 32 edges per tile in BF16, 32 or 16 in

@@ -21,10 +21,11 @@ ALLEGRO_OK = 0
 STATUS = {0: "ALLEGRO_OK", -1: "ALLEGRO_E_INVAL", -2: "ALLEGRO_E_NOMEM", -3: "ALLEGRO_E_CAPACITY",
           -4: "ALLEGRO_E_DEVICE", -5: "ALLEGRO_E_NONFINITE", -6: "ALLEGRO_E_STATE"}
 PREC_FP32, PREC_BF16, PREC_BF16_SINGLE, PREC_BF16_MIXED = 0, 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 256 << 20   # ALLEGRO_NOALLOC_SCRATCH_BYTES
 
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ("allegro_describe", "allegro_plan_chunks", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
-           "allegro_system_energies", "allegro_energy_forces",
+           "allegro_system_energies", "allegro_energy_forces", "allegro_energy_forces_noalloc",
            "allegro_autotune", "allegro_set_tiles", "allegro_set_ghosts", "allegro_md_run", "allegro_check", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
            "allegro_workspace_bytes", "allegro_destroy", "allegro_last_error", "allegro_status_string")
 
@@ -86,6 +87,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_system_energies.restype = ctypes.c_int
     lib.allegro_energy_forces.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
     lib.allegro_energy_forces.restype = ctypes.c_int
+    lib.allegro_energy_forces_noalloc.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, vp]
+    lib.allegro_energy_forces_noalloc.restype = ctypes.c_int
     lib.allegro_autotune.argtypes = [vp, dp, dp, vp, vp]
     lib.allegro_autotune.restype = ctypes.c_int
     lib.allegro_set_tiles.argtypes = [vp, vp]
@@ -279,6 +282,13 @@ class Model:
         self._check(self.lib.allegro_energy_forces(self.handle, _ptr(pos), _ptr(species), _ptr(atom_energy),
                                                    _ptr(forces), _ptr(virial), _ptr(atom_virial),
                                                    _ptr(energy), _stream(stream)))
+
+    def energy_forces_noalloc(self, pos, species, forces, atom_energy=None, virial=None, atom_virial=None,
+                              energy=None, stream=None):
+        """energy_forces on the library's static per-GPU workspace (allocates nothing)."""
+        self._check(self.lib.allegro_energy_forces_noalloc(self.handle, _ptr(pos), _ptr(species),
+                                                           _ptr(atom_energy), _ptr(forces), _ptr(virial),
+                                                           _ptr(atom_virial), _ptr(energy), _stream(stream)))
 
     TILE_KINDS = ("mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd_final", "mlp_bwd_final", "mlp_bwd_latent",
                   "mlp_bwd_twobody", "tp_mix", "mix_adjoint")

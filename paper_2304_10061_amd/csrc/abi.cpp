@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,9 +22,20 @@
 
 using namespace allegro;
 
+// Workspace of allegro_energy_forces_noalloc: one array per GPU, created with
+// the code object and held until the process ends.  Host code never uses the
+// array's name as an address (on the host it names a stand-in): each device's
+// address is looked up once, by allegro_create with that device current, and
+// kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[ALLEGRO_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
 
 struct Fail {
   int code;
@@ -349,6 +361,70 @@ struct Mlp {
 
 }  // namespace
 
+// Per-evaluation workspace: every array allegro_energy_forces writes and
+// reads back within one call (activations of the current chunk, gradients,
+// per-edge dE/dr for the force gather, per-atom energies when the caller
+// passes none, partial sums).  Nothing in it carries over between calls, and
+// no kernel relies on it starting at zero.  ws_layout carves it out of one
+// block starting at `base` (256-byte aligned pieces) and returns its size;
+// with base = 0 it only measures.
+struct Ws {
+  float *eb = nullptr, *x[kMaxLayers] = {}, *head0o = nullptr, *wenv[kMaxLayers] = {}, *V[kMaxLayers] = {},
+        *gam[kMaxLayers] = {}, *eij = nullptr, *gxa = nullptr, *gxb = nullptr, *gTf = nullptr, *gs = nullptr,
+        *ghead0 = nullptr, *gw2 = nullptr, *gT[2] = {}, *gY = nullptr, *gu = nullptr, *gR = nullptr,
+        *ggam = nullptr, *epair = nullptr, *g_e = nullptr;
+  void* zscr = nullptr;      // hidden pre-activations of the 128-row backward MLP kernels
+  double *atom_e = nullptr, *partial = nullptr;
+};
+
+// Ec / Nc: most edges / centres of one chunk; E: all edges; n_local, n_total:
+// atoms of the list.
+size_t ws_layout(const Validated& v, int64_t Ec, int64_t Nc, int64_t E, int64_t n_local, int64_t n_total,
+                 bool zbl, bool tall, uintptr_t base, Ws* w) {
+  Ec = std::max<int64_t>(Ec, 1); Nc = std::max<int64_t>(Nc, 1); E = std::max<int64_t>(E, 1);
+  const int64_t nt = std::max<int64_t>(n_total, 1), nl = std::max<int64_t>(n_local, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return base ? (void*)(base + at) : nullptr;
+  };
+  auto fl = [&](int64_t count) { return (float*)take((size_t)count * sizeof(float)); };
+  Ws t;
+  t.eb = fl(Ec * kEB);
+  for (int L = 0; L < v.nl; ++L) t.x[L] = fl(Ec * v.d);
+  t.head0o = fl(Ec * 2 * v.LW);
+  if (v.nl >= 2) {
+    int wmax = 0;
+    for (int L = 0; L + 1 < v.nl; ++L) {
+      t.wenv[L + 1] = fl(Ec * v.LW);
+      t.V[L] = fl(Ec * v.w_out[L] * v.n);
+      wmax = std::max(wmax, v.w_out[L]);
+    }
+    t.gw2 = fl(Ec * v.LW);
+    t.gT[0] = fl(Ec * wmax * v.n);
+    if (v.nl >= 3) t.gT[1] = fl(Ec * wmax * v.n);
+    t.gxb = fl(Ec * v.d);
+    t.gs = fl(Ec * v.n);
+  }
+  for (int L = 0; L < v.nl; ++L) t.gam[L] = fl(Nc * v.dim * v.n);
+  t.ggam = fl(Nc * v.dim * v.n);
+  t.eij = fl(Ec);
+  t.gxa = fl(Ec * v.d);
+  t.gTf = fl(Ec * v.n);
+  t.ghead0 = fl(Ec * 2 * v.LW);
+  t.gY = fl(Ec * gy_width(v.lmax));
+  t.gu = fl(Ec);
+  t.gR = fl(Ec * v.nb);
+  if (zbl) t.epair = fl(Ec);
+  if (tall) t.zscr = take(mlp_tall_scratch_bytes(Ec, v.d));
+  t.g_e = fl(E * 3);
+  t.atom_e = (double*)take((size_t)nl * sizeof(double));
+  t.partial = (double*)take((size_t)((nt + 255) / 256) * 10 * sizeof(double));
+  if (w) *w = t;
+  return off;
+}
+
 struct AllegroModel {
   AllegroConfig cfg{};
   Validated v{};
@@ -370,7 +446,7 @@ struct AllegroModel {
   // ZBL term: atomic numbers (empty = none), their device table [Z | Z^0.23]
   // and the per-edge pair shares of the current chunk
   std::vector<int> znum;
-  DevBuf zbl_tab, epair;
+  DevBuf zbl_tab;
   DevBuf mixF[kMaxLayers], mixB[kMaxLayers];   // packed FP32 mixing matrices per layer and irrep slot
   int mix_stride = 0;
   DevBuf tpw[kMaxLayers];                 // fused coupling non-zeros per layer
@@ -416,15 +492,14 @@ struct AllegroModel {
   std::vector<KTime> ktimes;
   std::vector<std::pair<size_t, std::pair<hipEvent_t, hipEvent_t>>> pending;
 
-  // workspace
+  // workspace of the current neighbour list (ws_layout) and its pieces:
   // x[L]: input of layer L; wenv[L] (L >= 1): its environment weights; V[L]:
   // output features of non-final layer L; gT[2]: dE/dT of consecutive
-  // non-final layers during the adjoint
-  DevBuf eb, x[kMaxLayers], head0o, wenv[kMaxLayers], V[kMaxLayers], gam[kMaxLayers], eij, gxa, gxb, gTf, gs,
-      ghead0, gw2, gT[2], gY, gu, gR;
-  DevBuf ggam;   // dE/dGamma of the layer being differentiated [centres][dim][n]
-  DevBuf zscr;   // hidden pre-activations of the 128-row backward MLP kernels
-  DevBuf g_e, atom_e, partial;
+  // non-final layers during the adjoint; ggam: dE/dGamma of the layer being
+  // differentiated [centres][dim][n]
+  DevBuf arena;
+  size_t ws_bytes = 0;
+  Ws ws;
 };
 
 namespace {
@@ -459,6 +534,16 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
                                         std::to_string(v.n_weights));
   for (int64_t k = 0; k < n_weights; ++k) REQUIRE(std::isfinite(w[k]), "weights contain non-finite values");
   HIP_OK(hipGetDevice(&m->device));
+  {
+    // the static workspace of allegro_energy_forces_noalloc on this device
+    REQUIRE(m->device >= 0 && m->device < kMaxDevices, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[m->device]) {
+      void* p = nullptr;
+      HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[m->device] = p;
+    }
+  }
   const int n = v.n, d = v.d, LW = v.LW, L1 = v.lmax + 1;
   if (!m->rc_pair.empty()) {
     std::vector<float> rf(m->rc_pair.size());
@@ -831,39 +916,11 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
     if (crp.empty()) crp.push_back(0);
     upload(m->chunk_rp, crp.data(), crp.size() * sizeof(int32_t));
   }
-  const Validated& v = m->v;
-  const int64_t Ec = std::max<int64_t>(m->Ec, 1), Nc = std::max<int64_t>(m->Nc, 1);
-  const size_t f = sizeof(float);
-  m->eb.ensure(Ec * kEB * f);
-  for (int L = 0; L < v.nl; ++L) m->x[L].ensure(Ec * v.d * f);
-  m->head0o.ensure(Ec * 2 * v.LW * f);
-  if (v.nl >= 2) {
-    int wmax = 0;
-    for (int L = 0; L + 1 < v.nl; ++L) {
-      m->wenv[L + 1].ensure(Ec * v.LW * f);
-      m->V[L].ensure(Ec * v.w_out[L] * v.n * f);
-      wmax = std::max(wmax, v.w_out[L]);
-    }
-    m->gw2.ensure(Ec * v.LW * f);
-    m->gT[0].ensure(Ec * wmax * v.n * f);
-    if (v.nl >= 3) m->gT[1].ensure(Ec * wmax * v.n * f);
-    m->gxb.ensure(Ec * v.d * f);
-    m->gs.ensure(Ec * v.n * f);
-  }
-  for (int L = 0; L < v.nl; ++L) m->gam[L].ensure(Nc * v.dim * v.n * f);
-  m->ggam.ensure(Nc * v.dim * v.n * f);
-  m->eij.ensure(Ec * f);
-  m->gxa.ensure(Ec * v.d * f);
-  m->gTf.ensure(Ec * v.n * f);
-  m->ghead0.ensure(Ec * 2 * v.LW * f);
-  m->gY.ensure(Ec * gy_width(v.lmax) * f);
-  m->gu.ensure(Ec * f);
-  m->gR.ensure(Ec * v.nb * f);
-  if (!m->znum.empty()) m->epair.ensure(Ec * f);
-  if (m->prec != ALLEGRO_PREC_FP32) m->zscr.ensure(mlp_tall_scratch_bytes(Ec, v.d));
-  m->g_e.ensure(Ee * 3 * f);
-  m->atom_e.ensure(std::max<int64_t>(n_local, 1) * sizeof(double));
-  m->partial.ensure(((nt + 255) / 256) * 10 * sizeof(double));
+  m->ws_bytes = ws_layout(m->v, m->Ec, m->Nc, E, n_local, n_total, !m->znum.empty(),
+                          m->prec != ALLEGRO_PREC_FP32, 0, nullptr);
+  m->arena.ensure(m->ws_bytes);
+  ws_layout(m->v, m->Ec, m->Nc, E, n_local, n_total, !m->znum.empty(), m->prec != ALLEGRO_PREC_FP32,
+            (uintptr_t)m->arena.p, &m->ws);
   m->pos_ref.ensure(std::max<int64_t>(n_local, 1) * 3 * sizeof(double));
   if (n_local > 0)
     HIP_OK(hipMemcpyAsync(m->pos_ref.p, pos, n_local * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -871,13 +928,14 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   if (n_edges) *n_edges = E;
 }
 
-void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* species, double* atom_energy,
-                        double* forces, double* virial, double* atom_virial, double* energy, hipStream_t s) {
+void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const int32_t* species,
+                        double* atom_energy, double* forces, double* virial, double* atom_virial, double* energy,
+                        hipStream_t s) {
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE((pos && species && forces) || m->n_total == 0, "pos, species and forces must not be NULL");
   const Validated& v = m->v;
   const int d = v.d, n = v.n, LW = v.LW;
-  double* aE = atom_energy ? atom_energy : ptr<double>(m->atom_e);
+  double* aE = atom_energy ? atom_energy : w.atom_e;
   const int32_t* ei = ptr<int32_t>(m->ei);
   const int32_t* ej = ptr<int32_t>(m->ej);
   const int32_t* es = ptr<int32_t>(m->es);
@@ -893,36 +951,36 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     for (int ax = 0; ax < 3; ++ax) ea.L[ax] = m->L[ax];
     ea.r_cut = m->cfg.r_cut; ea.p = v.p; ea.n_bessel = v.nb; ea.l_max = v.lmax;
     ea.rc_pair = m->rc_pair.empty() ? nullptr : ptr<float>(m->rc_pair_f); ea.n_species = v.S;
-    if (!m->znum.empty()) { ea.zbl = ptr<float>(m->zbl_tab); ea.e_pair = ptr<float>(m->epair); }
-    ea.eb = ptr<float>(m->eb);
+    if (!m->znum.empty()) { ea.zbl = ptr<float>(m->zbl_tab); ea.e_pair = w.epair; }
+    ea.eb = w.eb;
     timed(m, "edge_basis", s, [&] { return launch_edge_basis(ea, s); });
 
     MlpArgs base;
     base.E = E; base.d = d; base.n = n; base.l_max = v.lmax; base.n_species = v.S; base.n_bessel = v.nb;
-    base.eb = ptr<float>(m->eb); base.ei = ei + eA; base.ej = ej + eA; base.species = species;
+    base.eb = w.eb; base.ei = ei + eA; base.ej = ej + eA; base.species = species;
     base.centre_base = (int)cA;
 
     MlpArgs m0 = base;
     m0.kind = kTwoBody; m0.w = m->twobody.view(); m0.head = m->head0.g; m0.head_bwd = m->head0T.g;
-    m0.x_out = ptr<float>(m->x[0]); m0.head_out = ptr<float>(m->head0o);
+    m0.x_out = w.x[0]; m0.head_out = w.head0o;
     m0.tm = m->tm_choice[0];
     timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, m->prec_two, s); });
 
     TensorArgs tb;
     tb.E = E; tb.n_centres = nc; tb.n = n; tb.l_max = v.lmax; tb.row_ptr = drp; tb.ei = ei + eA;
-    tb.centre_base = (int)cA; tb.eb = ptr<float>(m->eb); tb.c_norm = (float)m->c_norm;
+    tb.centre_base = (int)cA; tb.eb = w.eb; tb.c_norm = (float)m->c_norm;
     tb.channel_mix = m->cfg.channel_mix ? 1 : 0; tb.mix_scale = (float)(1.0 / std::sqrt((double)n));
     tb.mix_stride = m->mix_stride;
 
     TensorArgs t1 = tb;
-    t1.w_env = ptr<float>(m->head0o) + LW; t1.ld_w = 2 * LW; t1.gam = ptr<float>(m->gam[0]);
+    t1.w_env = w.head0o + LW; t1.ld_w = 2 * LW; t1.gam = w.gam[0];
     timed(m, "env", s, [&] { return launch_env(t1, s); });
 
-    const VSrc v_a0{ptr<float>(m->head0o), 2 * LW, 1};
+    const VSrc v_a0{w.head0o, 2 * LW, 1};
     MlpArgs mf = base;
     mf.kind = kLatentFinal; mf.we = ptr<float>(m->we); mf.g_const = ptr<float>(m->gconst);
     for (int k = 0; k < 16; ++k) mf.tp_w[k] = m->tp_final[k];
-    mf.eij = ptr<float>(m->eij);
+    mf.eij = w.eij;
     // non-final layers: tensor product + mixing, then the latent MLP that
     // produces the next layer's scalars and environment weights
     MlpArgs ml[kMaxLayers];
@@ -930,112 +988,112 @@ void energy_forces_impl(AllegroModel* m, const double* pos, const int32_t* speci
     for (int L = 0; L + 1 < v.nl; ++L) {
       TensorArgs tl = tb;
       tl.in_kind = v.in_kind[L]; tl.out_kind = v.out_kind[L];
-      tl.v = vin; tl.gam = ptr<float>(m->gam[L]); tl.tile = m->tt_choice[0];
+      tl.v = vin; tl.gam = w.gam[L]; tl.tile = m->tt_choice[0];
       tl.tpw = ptr<float>(m->tpw[L]); set_tpw(tl, m->tpw_host[L]); tl.mixB = m->mixF[L].p;
-      tl.v_out = ptr<float>(m->V[L]);
+      tl.v_out = w.V[L];
       timed(m, "tp_mix", s, [&] { return launch_tp_mix(tl, false, s); });
       MlpArgs& mL = ml[L];
       mL = base;
       mL.kind = kLatent; mL.w = m->latent[L].view(); mL.head = m->envH[L].g; mL.head_bwd = m->envHT[L].g;
-      mL.x_prev = ptr<float>(m->x[L]); mL.s_in = ptr<float>(m->V[L]); mL.s_ld = v.w_out[L] * n;
-      mL.x_out = ptr<float>(m->x[L + 1]); mL.head_out = ptr<float>(m->wenv[L + 1]);
+      mL.x_prev = w.x[L]; mL.s_in = w.V[L]; mL.s_ld = v.w_out[L] * n;
+      mL.x_out = w.x[L + 1]; mL.head_out = w.wenv[L + 1];
       mL.tm = m->tm_choice[1];
       timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(mL, m->prec_lat, s); });
       TensorArgs te = tb;
-      te.w_env = ptr<float>(m->wenv[L + 1]); te.ld_w = LW; te.gam = ptr<float>(m->gam[L + 1]);
+      te.w_env = w.wenv[L + 1]; te.ld_w = LW; te.gam = w.gam[L + 1];
       timed(m, "env", s, [&] { return launch_env(te, s); });
-      vin = VSrc{ptr<float>(m->V[L]), v.w_out[L] * n, 0};
+      vin = VSrc{w.V[L], v.w_out[L] * n, 0};
     }
-    mf.w = m->latent[v.nl - 1].view(); mf.x_prev = ptr<float>(m->x[v.nl - 1]); mf.tp_v = vin;
-    mf.tp_gam = ptr<float>(m->gam[v.nl - 1]);
+    mf.w = m->latent[v.nl - 1].view(); mf.x_prev = w.x[v.nl - 1]; mf.tp_v = vin;
+    mf.tp_gam = w.gam[v.nl - 1];
     mf.tm = m->tm_choice[2];
-    mf.tp_out = ptr<float>(m->gTf);   // the final scalars, read back by the backward pass
+    mf.tp_out = w.gTf;   // the final scalars, read back by the backward pass
     timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, m->prec_lat, s); });
 
     ReduceArgs ra;
-    ra.n_centres = nc; ra.centre_base = (int)cA; ra.row_ptr = drp; ra.eij = ptr<float>(m->eij);
-    ra.e_pair = m->znum.empty() ? nullptr : ptr<float>(m->epair);
+    ra.n_centres = nc; ra.centre_base = (int)cA; ra.row_ptr = drp; ra.eij = w.eij;
+    ra.e_pair = m->znum.empty() ? nullptr : w.epair;
     ra.species = species; ra.n_species = v.S;
     ra.scale = ptr<double>(m->scale); ra.shift = ptr<double>(m->shift); ra.atom_energy = aE;
     timed(m, "atom_energy", s, [&] { return launch_atom_energy(ra, s); });
 
     // ---- adjoint ----
     // the backward reads each row's stored scalars before overwriting them with dE/ds
-    mf.tp_out = nullptr; mf.s_in = ptr<float>(m->gTf); mf.s_ld = n;
-    mf.g_xprev = ptr<float>(m->gxa); mf.g_s = ptr<float>(m->gTf); mf.g_u = ptr<float>(m->gu); mf.gu_accum = 0;
-    mf.g_store = mf.g_xprev; mf.act_scratch = m->zscr.p;
+    mf.tp_out = nullptr; mf.s_in = w.gTf; mf.s_ld = n;
+    mf.g_xprev = w.gxa; mf.g_s = w.gTf; mf.g_u = w.gu; mf.gu_accum = 0;
+    mf.g_store = mf.g_xprev; mf.act_scratch = w.zscr;
     mf.tm = m->tm_choice[3];
     timed(m, "mlp_bwd_final", s, [&] { return launch_mlp_bwd(mf, m->prec_lat, s); });
 
     TensorArgs tf = tb;
-    tf.g_t = ptr<float>(m->gTf); tf.g_Y = ptr<float>(m->gY); tf.gy_accum = 0; tf.g_gam = ptr<float>(m->ggam);
+    tf.g_t = w.gTf; tf.g_Y = w.gY; tf.gy_accum = 0; tf.g_gam = w.ggam;
     tf.tpw = ptr<float>(m->tpw[v.nl - 1]);
     set_tpw(tf, m->tpw_host[v.nl - 1]);
-    tf.v = vin; tf.gam = ptr<float>(m->gam[v.nl - 1]);
+    tf.v = vin; tf.gam = w.gam[v.nl - 1];
     if (v.nl >= 2) {
-      tf.w_env = ptr<float>(m->wenv[v.nl - 1]); tf.ld_w = LW; tf.g_w = ptr<float>(m->gw2); tf.ld_gw = LW;
+      tf.w_env = w.wenv[v.nl - 1]; tf.ld_w = LW; tf.g_w = w.gw2; tf.ld_gw = LW;
     } else {
-      tf.w_env = ptr<float>(m->head0o) + LW; tf.ld_w = 2 * LW;
-      tf.g_w = ptr<float>(m->ghead0) + LW; tf.ld_gw = 2 * LW; tf.g_a0 = ptr<float>(m->ghead0);
+      tf.w_env = w.head0o + LW; tf.ld_w = 2 * LW;
+      tf.g_w = w.ghead0 + LW; tf.ld_gw = 2 * LW; tf.g_a0 = w.ghead0;
     }
     timed(m, "tp_env_adjoint_final", s, [&] { return launch_tp_env_adjoint(tf, true, s); });
 
     // non-final layers, last to first: latent-MLP adjoint (dE/dx of the layer's
     // input, dE/ds of its scalars), mixing adjoint (dE/dT from the next layer),
     // tensor-product / environment adjoint (dE/dw of its environment weights)
-    float* gx_cur = ptr<float>(m->gxa);     // dE/dx of the input of layer L+1
-    float* gx_other = ptr<float>(m->gxb);
-    const float* gt_next = ptr<float>(m->gTf);
+    float* gx_cur = w.gxa;     // dE/dx of the input of layer L+1
+    float* gx_other = w.gxb;
+    const float* gt_next = w.gTf;
     int slot = 0;
     for (int L = v.nl - 2; L >= 0; --L) {
       MlpArgs& mL = ml[L];
-      mL.g_head = ptr<float>(m->gw2); mL.g_x = gx_cur; mL.g_xprev = gx_other;
-      mL.g_s = ptr<float>(m->gs); mL.g_u = ptr<float>(m->gu); mL.gu_accum = 1;
-      mL.g_store = mL.g_xprev; mL.act_scratch = m->zscr.p;
+      mL.g_head = w.gw2; mL.g_x = gx_cur; mL.g_xprev = gx_other;
+      mL.g_s = w.gs; mL.g_u = w.gu; mL.gu_accum = 1;
+      mL.g_store = mL.g_xprev; mL.act_scratch = w.zscr;
       mL.tm = m->tm_choice[4];
       timed(m, "mlp_bwd_latent", s, [&] { return launch_mlp_bwd(mL, m->prec_lat, s); });
       std::swap(gx_cur, gx_other);
       TensorArgs tm = tb;
       tm.next_in = v.in_kind[L + 1]; tm.next_out = v.out_kind[L + 1];
-      tm.g_tnext = gt_next; tm.gam_next = ptr<float>(m->gam[L + 1]);
+      tm.g_tnext = gt_next; tm.gam_next = w.gam[L + 1];
       for (int k = 0; k < 16; ++k) tm.tp_wnext[k] = m->tp_final[k];
       tm.tpw = ptr<float>(m->tpw[L + 1]); set_tpw(tm, m->tpw_host[L + 1]);
-      tm.g_s = ptr<float>(m->gs); tm.tile = m->tt_choice[1]; tm.mixB = m->mixB[L].p;
-      tm.g_tout = ptr<float>(m->gT[slot]);
+      tm.g_s = w.gs; tm.tile = m->tt_choice[1]; tm.mixB = m->mixB[L].p;
+      tm.g_tout = w.gT[slot];
       timed(m, "mix_adjoint", s, [&] { return launch_mix_adjoint(tm, s); });
       TensorArgs tl = tb;
       tl.in_kind = v.in_kind[L]; tl.out_kind = v.out_kind[L];
-      tl.g_t = ptr<float>(m->gT[slot]); tl.tpw = ptr<float>(m->tpw[L]); set_tpw(tl, m->tpw_host[L]);
-      tl.g_Y = ptr<float>(m->gY); tl.gy_accum = 1; tl.g_gam = ptr<float>(m->ggam);
-      tl.gam = ptr<float>(m->gam[L]);
+      tl.g_t = w.gT[slot]; tl.tpw = ptr<float>(m->tpw[L]); set_tpw(tl, m->tpw_host[L]);
+      tl.g_Y = w.gY; tl.gy_accum = 1; tl.g_gam = w.ggam;
+      tl.gam = w.gam[L];
       if (L == 0) {
-        tl.v = v_a0; tl.w_env = ptr<float>(m->head0o) + LW; tl.ld_w = 2 * LW;
-        tl.g_w = ptr<float>(m->ghead0) + LW; tl.ld_gw = 2 * LW; tl.g_a0 = ptr<float>(m->ghead0);
+        tl.v = v_a0; tl.w_env = w.head0o + LW; tl.ld_w = 2 * LW;
+        tl.g_w = w.ghead0 + LW; tl.ld_gw = 2 * LW; tl.g_a0 = w.ghead0;
       } else {
-        tl.v = VSrc{ptr<float>(m->V[L - 1]), v.w_out[L - 1] * n, 0};
-        tl.w_env = ptr<float>(m->wenv[L]); tl.ld_w = LW; tl.g_w = ptr<float>(m->gw2); tl.ld_gw = LW;
+        tl.v = VSrc{w.V[L - 1], v.w_out[L - 1] * n, 0};
+        tl.w_env = w.wenv[L]; tl.ld_w = LW; tl.g_w = w.gw2; tl.ld_gw = LW;
       }
       timed(m, "tp_env_adjoint", s, [&] { return launch_tp_env_adjoint(tl, false, s); });
-      gt_next = ptr<float>(m->gT[slot]);
+      gt_next = w.gT[slot];
       slot ^= 1;
     }
     float* gx_two = gx_cur;
-    m0.g_head = ptr<float>(m->ghead0); m0.g_x = gx_two; m0.g_u = ptr<float>(m->gu); m0.gu_accum = 1;
-    m0.g_R = ptr<float>(m->gR);
-    m0.g_store = gx_two; m0.act_scratch = m->zscr.p;   // the two-body backward reuses its g_x rows
+    m0.g_head = w.ghead0; m0.g_x = gx_two; m0.g_u = w.gu; m0.gu_accum = 1;
+    m0.g_R = w.gR;
+    m0.g_store = gx_two; m0.act_scratch = w.zscr;   // the two-body backward reuses its g_x rows
     m0.tm = m->tm_choice[5];
     timed(m, "mlp_bwd_twobody", s, [&] { return launch_mlp_bwd(m0, m->prec_two, s); });
 
-    ea.g_Y = ptr<float>(m->gY); ea.g_R = ptr<float>(m->gR); ea.g_u = ptr<float>(m->gu);
-    ea.g_e = ptr<float>(m->g_e) + 3 * eA;
+    ea.g_Y = w.gY; ea.g_R = w.gR; ea.g_u = w.gu;
+    ea.g_e = w.g_e + 3 * eA;
     timed(m, "edge_adjoint", s, [&] { return launch_edge_adjoint(ea, s); });
   }
   ForceArgs fa;
   fa.n_total = m->n_total; fa.n_local = m->n_local; fa.pos = pos; fa.row_ptr = ptr<int32_t>(m->row_ptr);
   fa.rrow_ptr = ptr<int32_t>(m->rrow_ptr); fa.redge = ptr<int32_t>(m->redge); fa.ei = ei; fa.ej = ej; fa.es = es;
   for (int ax = 0; ax < 3; ++ax) fa.L[ax] = m->L[ax];
-  fa.g_e = ptr<float>(m->g_e); fa.forces = forces; fa.atom_virial = atom_virial;
-  fa.partial = ptr<double>(m->partial); fa.atom_energy = aE; fa.status = ptr<int>(m->status);
+  fa.g_e = w.g_e; fa.forces = forces; fa.atom_virial = atom_virial;
+  fa.partial = w.partial; fa.atom_energy = aE; fa.status = ptr<int>(m->status);
   int nb = 0;
   timed(m, "forces", s, [&] { return launch_forces(fa, &nb, s); });
   if (virial || energy) timed(m, "final_sums", s, [&] { return launch_final_sums(fa.partial, nb, virial, energy, s); });
@@ -1071,7 +1129,7 @@ void md_step(AllegroModel* m, double dt, const double* masses, double* pos, doub
   HIP_OK(launch_kick_drift(nl, dt, masses, pos, vel, forces, s));
   if (m->n_ghost > 0)
     HIP_OK(launch_ghost_refresh(m->n_ghost, nl, ptr<int32_t>(m->g_owner), ptr<double>(m->g_offset), pos, s));
-  energy_forces_impl(m, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
+  energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
   if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
   HIP_OK(launch_kick(nl, dt, masses, vel, forces, s));
   if (thermo)
@@ -1096,7 +1154,7 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
   const bool was_timing = m->timing;
   m->timing = false;
   if (init_forces) {
-    energy_forces_impl(m, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
+    energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
     if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
   }
   HIP_OK(launch_fill_i32(ptr<int32_t>(m->md_counter), 0, 1, s));
@@ -1171,13 +1229,13 @@ void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, h
     for (int k = 0; k < 2; ++k) m->tt_choice[k] = cand_tt[c < 2 ? c : 1];
     // warm-up, then two timed evaluations
     m->timing = false;
-    energy_forces_impl(m, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
+    energy_forces_impl(m, m->ws, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
                        ptr<double>(m->md_epot), s);
     collect_times(m);
     m->ktimes.clear();
     m->timing = true;
     for (int r = 0; r < 2; ++r)
-      energy_forces_impl(m, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
+      energy_forces_impl(m, m->ws, pos, species, nullptr, ptr<double>(m->tune_forces), nullptr, nullptr,
                          ptr<double>(m->md_epot), s);
     collect_times(m);
     for (int k = 0; k < 8; ++k)
@@ -1433,12 +1491,50 @@ int allegro_energy_forces(AllegroModel* m, const double* pos, const int32_t* spe
                           double* forces, double* virial, double* atom_virial, double* energy, void* stream) {
   if (!m) return ALLEGRO_E_INVAL;
   try {
-    energy_forces_impl(m, pos, species, atom_energy, forces, virial, atom_virial, energy, (hipStream_t)stream);
+    energy_forces_impl(m, m->ws, pos, species, atom_energy, forces, virial, atom_virial, energy, (hipStream_t)stream);
     return ALLEGRO_OK;
   } catch (const Fail& f) {
     return fail(m, f);
   } catch (const std::bad_alloc&) {
     return fail(m, Fail{ALLEGRO_E_NOMEM, "host allocation failed"});
+  } catch (...) {
+    return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
+  }
+}
+
+int allegro_energy_forces_noalloc(AllegroModel* m, const double* pos, const int32_t* species,
+                                  double* atom_energy, double* forces, double* virial, double* atom_virial,
+                                  double* energy, void* stream) {
+  if (!m) return ALLEGRO_E_INVAL;
+  try {
+    if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    REQUIRE(dev == m->device, "the current device is not the model's device");
+    const bool zbl = !m->znum.empty(), tall = m->prec != ALLEGRO_PREC_FP32;
+    const size_t need = ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, 0, nullptr);
+    REQUIRE(need <= (size_t)ALLEGRO_NOALLOC_SCRATCH_BYTES,
+            "the neighbour list needs " + std::to_string(need) + " bytes of workspace, the static workspace holds " +
+                std::to_string((size_t)ALLEGRO_NOALLOC_SCRATCH_BYTES) +
+                "; build the list with a smaller edge_chunk");
+    void* base = g_scratch_ptr[dev];
+    if (!base) throw Fail{ALLEGRO_E_STATE, "static workspace address not resolved on this device"};
+    Ws w;
+    ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, (uintptr_t)base, &w);
+    // no per-kernel timing here: recording it creates events
+    const bool timing = m->timing;
+    m->timing = false;
+    try {
+      energy_forces_impl(m, w, pos, species, atom_energy, forces, virial, atom_virial, energy,
+                         (hipStream_t)stream);
+    } catch (...) {
+      m->timing = timing;
+      throw;
+    }
+    m->timing = timing;
+    return ALLEGRO_OK;
+  } catch (const Fail& f) {
+    return fail(m, f);
   } catch (...) {
     return fail(m, Fail{ALLEGRO_E_INVAL, "unexpected exception"});
   }
@@ -1508,11 +1604,7 @@ int64_t allegro_workspace_bytes(const AllegroModel* m) {
   if (!m) return -1;
   const DevBuf* bufs[] = {&m->ei, &m->ej, &m->es, &m->row_ptr, &m->rrow_ptr, &m->redge, &m->keys, &m->cell_of,
                           &m->img, &m->cell_count, &m->cell_start, &m->cell_cursor, &m->cell_atoms, &m->count,
-                          &m->rcount, &m->rcursor, &m->bbox, &m->scan_tmp, &m->eb, &m->x[0], &m->x[1],
-                          &m->x[2], &m->x[3], &m->head0o, &m->wenv[1], &m->wenv[2], &m->wenv[3], &m->V[0],
-                          &m->V[1], &m->V[2], &m->gam[0], &m->gam[1], &m->gam[2], &m->gam[3], &m->eij,
-                          &m->gxa, &m->gxb, &m->gTf, &m->gs, &m->ghead0, &m->gw2, &m->gT[0], &m->gT[1], &m->gY,
-                          &m->gu, &m->gR, &m->g_e, &m->atom_e, &m->partial, &m->chunk_rp};
+                          &m->rcount, &m->rcursor, &m->bbox, &m->scan_tmp, &m->arena, &m->chunk_rp};
   int64_t s = 0;
   for (const DevBuf* b : bufs) s += (int64_t)b->bytes;
   return s;

@@ -170,3 +170,11 @@ def test_plan_chunks_deep_model_and_limits():
     assert ex.value.status == -1
     # empty input: a single boundary
     assert list(P.plan_chunks(cfg, np.zeros(0, np.int32))) == [0]
+
+
+def test_noalloc_scratch_size_matches_header():
+    """The binding's copy of the static workspace size equals the header's."""
+    txt = open(os.path.join(ROOT, "include", "allegro_mi355x.h")).read()
+    m = re.search(r"#define ALLEGRO_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m is not None
+    assert int(m.group(1)) << int(m.group(2)) == binding.NOALLOC_SCRATCH_BYTES
