@@ -28,7 +28,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-unused-result"]
 
 SOURCES = ["abi.cpp", "neighbors.hip", "edge.hip", "mlp.hip", "mlp_fp32.hip", "mlp_bf16.hip", "mlp_bf16s.hip",
-           "tensor.hip", "md.hip"]
+           "mlp_rr1f.hip", "mlp_rr1b.hip", "mlp_rr2f.hip", "mlp_rr2b.hip", "tensor.hip", "md.hip"]
 
 
 def _hipcc() -> str:

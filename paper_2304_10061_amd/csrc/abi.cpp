@@ -123,6 +123,37 @@ std::vector<double> transpose(const std::vector<double>& W, int K, int N) {
   return T;
 }
 
+// Packs M (Kin x Nout, row-major: out = in @ M) as A fragments of the
+// register-resident kernels (layout in internal.h, RRW).  split: BF16 pairs
+// (hi fragment, then lo = M - hi) instead of single-rounded BF16.
+void pack_rr(const double* M, int Kin, int Nout, bool split, std::vector<char>& out) {
+  const int KS = (Kin + 15) / 16, MB = (Nout + 31) / 32, NBP = rr_nbp(MB), NP = MB / NBP, S = split ? 2 : 1;
+  const size_t base = out.size();
+  out.resize(base + (size_t)NP * KS * NBP * S * 1024, 0);
+  for (int p = 0; p < NP; ++p)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int b = 0; b < NBP; ++b)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int j = 0; j < 8; ++j) {
+            const int m = 32 * (p * NBP + b) + lane % 32, gq = lane / 32;
+            const int f = 16 * ks + (j < 4 ? 4 * gq + j : 8 + 4 * gq + (j - 4));
+            const double w = (m < Nout && f < Kin) ? M[(size_t)f * Nout + m] : 0.0;
+            const __bf16 hi = (__bf16)(float)w;
+            const size_t frag = ((size_t)(p * KS + ks) * NBP + b) * S;
+            std::memcpy(out.data() + base + ((frag * 64 + lane) * 8 + j) * 2, &hi, 2);
+            if (split) {
+              const __bf16 lo = (__bf16)(float)(w - (double)(float)hi);
+              std::memcpy(out.data() + base + (((frag + 1) * 64 + lane) * 8 + j) * 2, &lo, 2);
+            }
+          }
+}
+
+// The same for a head transpose, in K chunks of 192 rows (the backward kernels
+// take the head gradient 12 K steps at a time).
+void pack_rr_chunked(const std::vector<double>& M, int Kin, int Nout, bool split, std::vector<char>& out) {
+  for (int r0 = 0; r0 < Kin; r0 += 192) pack_rr(M.data() + (size_t)r0 * Nout, std::min(192, Kin - r0), Nout, split, out);
+}
+
 struct PackedMat {
   DevBuf buf;
   GemmB g;
@@ -350,6 +381,7 @@ int count_nonzeros(int lmax, int in, int out) {
 
 struct Mlp {
   PackedMat fwd[kMaxMlpLayers], bwd[kMaxMlpLayers];
+  DevBuf rr_fwd[kMaxMlpLayers], rr_bwd[kMaxMlpLayers];   // register-resident kernels' packing
   int nl = 0;
   MlpW view() const {
     MlpW w;
@@ -380,7 +412,7 @@ struct Ws {
 // Ec / Nc: most edges / centres of one chunk; E: all edges; n_local, n_total:
 // atoms of the list.
 size_t ws_layout(const Validated& v, int64_t Ec, int64_t Nc, int64_t E, int64_t n_local, int64_t n_total,
-                 bool zbl, bool tall, uintptr_t base, Ws* w) {
+                 bool zbl, bool tall, bool rr, uintptr_t base, Ws* w) {
   Ec = std::max<int64_t>(Ec, 1); Nc = std::max<int64_t>(Nc, 1); E = std::max<int64_t>(E, 1);
   const int64_t nt = std::max<int64_t>(n_total, 1), nl = std::max<int64_t>(n_local, 1);
   size_t off = 0;
@@ -417,7 +449,9 @@ size_t ws_layout(const Validated& v, int64_t Ec, int64_t Nc, int64_t E, int64_t 
   t.gu = fl(Ec);
   t.gR = fl(Ec * v.nb);
   if (zbl) t.epair = fl(Ec);
-  if (tall) t.zscr = take(mlp_tall_scratch_bytes(Ec, v.d));
+  if (tall || rr)
+    t.zscr = take(std::max(tall ? mlp_tall_scratch_bytes(Ec, v.d) : (size_t)0,
+                           rr ? mlp_rr_scratch_bytes(Ec, v.d, (int)v.dims2b.size()) : (size_t)0));
   t.g_e = fl(E * 3);
   t.atom_e = (double*)take((size_t)nl * sizeof(double));
   t.partial = (double*)take((size_t)((nt + 255) / 256) * 10 * sizeof(double));
@@ -437,6 +471,8 @@ struct AllegroModel {
   int device = 0;
 
   Mlp twobody, latent[kMaxLayers];
+  int rr_cfg = 0;                         // register-resident kernels (rr_config), 0 = none
+  DevBuf rr_head0, rr_head0T, rr_envH[kMaxLayers], rr_envHT[kMaxLayers], rr_fold_v;
   PackedMat head0, head0T;                // [embed0 | env of layer 1] after the two-body MLP
   PackedMat envH[kMaxLayers], envHT[kMaxLayers];   // env of layer L+1 after latent MLP L
   // ordered species-pair cutoffs (empty = r_cut for every pair): the host
@@ -453,6 +489,7 @@ struct AllegroModel {
   std::vector<float> tpw_host[kMaxLayers];
   float tp_final[16] = {0};               // final-layer diagonal weights
   DevBuf we, gconst, scale, shift;
+  float sigma_f[16] = {0};                // species scales sigma_Z (FP32 copy)
   double c_norm = 1.0;
 
   // neighbour list
@@ -518,13 +555,45 @@ std::vector<double> slice(const float* w, int64_t& off, int64_t count) {
 
 // prec_first applies to the first layer, prec_rest to the others.
 void build_mlp(Mlp& mlp, const std::vector<std::vector<double>>& Ws, const std::vector<int>& dims, int prec_first,
-               int prec_rest) {
+               int prec_rest, bool rr) {
   mlp.nl = (int)Ws.size();
   for (int k = 0; k < mlp.nl; ++k) {
     const int prec = k == 0 ? prec_first : prec_rest;
+    const std::vector<double> T = transpose(Ws[k], dims[k], dims[k + 1]);
     make_packed(mlp.fwd[k], Ws[k], dims[k], dims[k + 1], prec);
-    make_packed(mlp.bwd[k], transpose(Ws[k], dims[k], dims[k + 1]), dims[k + 1], dims[k], prec);
+    make_packed(mlp.bwd[k], T, dims[k + 1], dims[k], prec);
+    if (rr) {
+      std::vector<char> f, b;
+      pack_rr(Ws[k].data(), dims[k], dims[k + 1], prec == 1, f);
+      pack_rr(T.data(), dims[k + 1], dims[k], prec == 1, b);
+      upload(mlp.rr_fwd[k], f.data(), f.size());
+      upload(mlp.rr_bwd[k], b.data(), b.size());
+    }
   }
+}
+
+RRW rr_view(const Mlp& mlp, int cfg, const DevBuf* head, const DevBuf* head_bwd) {
+  RRW r;
+  if (!cfg) return r;
+  r.cfg = cfg;
+  for (int k = 0; k < mlp.nl; ++k) { r.fwd[k] = mlp.rr_fwd[k].p; r.bwd[k] = mlp.rr_bwd[k].p; }
+  r.head = head ? head->p : nullptr;
+  r.head_bwd = head_bwd ? head_bwd->p : nullptr;
+  return r;
+}
+
+// Configurations the register-resident kernels are compiled for (0 = none):
+// 1 = latent width 256, 64 tensor channels, l_max 2, three-layer two-body and
+// latent MLPs of width 256; 2 = 128, 32, l_max 2, two-layer MLPs of width 128.
+// Both need the two-body input (2 species + radial functions) within 16.
+int rr_config(const Validated& v, int prec) {
+  if (prec == ALLEGRO_PREC_FP32 || v.lmax != 2 || 2 * v.S + v.nb > 16) return 0;
+  for (int w : v.dims2b) if (w != v.d) return 0;
+  for (int w : v.dimsL) if (w != v.d) return 0;
+  const int nl2 = (int)v.dims2b.size(), nlL = (int)v.dimsL.size();
+  if (v.d == 256 && v.n == 64 && nl2 == 3 && nlL == 3) return 1;
+  if (v.d == 128 && v.n == 32 && nl2 == 2 && nlL == 2) return 2;
+  return 0;
 }
 
 void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const double* scale, const double* shift) {
@@ -572,7 +641,9 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     Ws.push_back(slice(w, off, (int64_t)dims.back() * wd));
     dims.push_back(wd);
   }
-  build_mlp(m->twobody, Ws, dims, m->prec_two, m->prec_two);
+  m->rr_cfg = rr_config(v, m->prec);
+  const bool rr = m->rr_cfg != 0;
+  build_mlp(m->twobody, Ws, dims, m->prec_two, m->prec_two, rr);
   const std::vector<double> embed0 = slice(w, off, (int64_t)d * LW);
   std::vector<double> env[kMaxLayers], alpha[kMaxLayers], mix[kMaxLayers];
   std::vector<std::vector<double>> mlpW[kMaxLayers];
@@ -610,7 +681,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
   }
   std::vector<int> ldims{d + n};
   for (int wd : v.dimsL) ldims.push_back(wd);
-  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, m->prec_lat_first, m->prec_lat_rest);
+  for (int L = 0; L < v.nl; ++L) build_mlp(m->latent[L], mlpW[L], ldims, m->prec_lat_first, m->prec_lat_rest, rr);
 
   // heads: [embed0 | env of layer 1] after the two-body MLP, env of layer L+1
   // after latent MLP L
@@ -626,6 +697,20 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     for (int L = 0; L + 1 < v.nl; ++L) {
       make_packed(m->envH[L], env[L + 1], d, LW, m->prec_lat_rest);
       make_packed(m->envHT[L], transpose(env[L + 1], d, LW), LW, d, m->prec_lat_rest);
+    }
+    if (rr) {
+      std::vector<char> f, b;
+      pack_rr(H.data(), d, 2 * LW, m->prec_two == 1, f);
+      pack_rr_chunked(transpose(H, d, 2 * LW), 2 * LW, d, m->prec_two == 1, b);
+      upload(m->rr_head0, f.data(), f.size());
+      upload(m->rr_head0T, b.data(), b.size());
+      for (int L = 0; L + 1 < v.nl; ++L) {
+        f.clear(); b.clear();
+        pack_rr(env[L + 1].data(), d, LW, m->prec_lat_rest == 1, f);
+        pack_rr_chunked(transpose(env[L + 1], d, LW), LW, d, m->prec_lat_rest == 1, b);
+        upload(m->rr_envH[L], f.data(), f.size());
+        upload(m->rr_envHT[L], b.data(), b.size());
+      }
     }
   }
   // channel mixing matrices of non-final layers (FP32): forward W[u][v] = M[v][u],
@@ -662,6 +747,18 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     for (int k = 0; k < v.h; ++k) wev[r] += We0[(size_t)r * v.h + k] * We1[k];
   std::vector<float> wef(wev.begin(), wev.end());
   upload(m->we, wef.data(), wef.size() * sizeof(float));
+  if (rr) {
+    // the final latent MLP's last matrix folded with the edge-energy vector:
+    // v = W_last w_e (the register-resident final-layer kernels use a . v)
+    const std::vector<double>& Wl = mlpW[v.nl - 1].back();
+    std::vector<float> fv(d);
+    for (int r = 0; r < d; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < d; ++c) acc += Wl[(size_t)r * d + c] * wev[c];
+      fv[r] = (float)acc;
+    }
+    upload(m->rr_fold_v, fv.data(), fv.size() * sizeof(float));
+  }
   std::vector<double> sc(v.S, 1.0), sh(v.S, 0.0);
   for (int s = 0; s < v.S; ++s) {
     if (scale) sc[s] = scale[s];
@@ -673,6 +770,7 @@ void create_impl(AllegroModel* m, const float* w, int64_t n_weights, const doubl
     for (int r = 0; r < d; ++r) gc[(size_t)s * d + r] = (float)(sc[s] * wev[r]);
   upload(m->gconst, gc.data(), gc.size() * sizeof(float));
   upload(m->scale, sc.data(), sc.size() * sizeof(double));
+  for (int k = 0; k < v.S && k < 16; ++k) m->sigma_f[k] = (float)sc[k];
   upload(m->shift, sh.data(), sh.size() * sizeof(double));
   m->c_norm = 1.0 / std::sqrt(m->cfg.avg_num_neighbors);
   m->err_flag.ensure(sizeof(int));
@@ -917,10 +1015,10 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
     upload(m->chunk_rp, crp.data(), crp.size() * sizeof(int32_t));
   }
   m->ws_bytes = ws_layout(m->v, m->Ec, m->Nc, E, n_local, n_total, !m->znum.empty(),
-                          m->prec != ALLEGRO_PREC_FP32, 0, nullptr);
+                          m->prec != ALLEGRO_PREC_FP32, m->rr_cfg != 0, 0, nullptr);
   m->arena.ensure(m->ws_bytes);
   ws_layout(m->v, m->Ec, m->Nc, E, n_local, n_total, !m->znum.empty(), m->prec != ALLEGRO_PREC_FP32,
-            (uintptr_t)m->arena.p, &m->ws);
+            m->rr_cfg != 0, (uintptr_t)m->arena.p, &m->ws);
   m->pos_ref.ensure(std::max<int64_t>(n_local, 1) * 3 * sizeof(double));
   if (n_local > 0)
     HIP_OK(hipMemcpyAsync(m->pos_ref.p, pos, n_local * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -962,6 +1060,7 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
 
     MlpArgs m0 = base;
     m0.kind = kTwoBody; m0.w = m->twobody.view(); m0.head = m->head0.g; m0.head_bwd = m->head0T.g;
+    m0.rr = rr_view(m->twobody, m->rr_cfg, &m->rr_head0, &m->rr_head0T);
     m0.x_out = w.x[0]; m0.head_out = w.head0o;
     m0.tm = m->tm_choice[0];
     timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, m->prec_two, s); });
@@ -979,6 +1078,9 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
     const VSrc v_a0{w.head0o, 2 * LW, 1};
     MlpArgs mf = base;
     mf.kind = kLatentFinal; mf.we = ptr<float>(m->we); mf.g_const = ptr<float>(m->gconst);
+    mf.rr = rr_view(m->latent[v.nl - 1], m->rr_cfg, nullptr, nullptr);
+    mf.fold_v = m->rr_cfg ? ptr<float>(m->rr_fold_v) : nullptr;
+    for (int k = 0; k < v.S && k < 16; ++k) mf.sigma[k] = m->sigma_f[k];
     for (int k = 0; k < 16; ++k) mf.tp_w[k] = m->tp_final[k];
     mf.eij = w.eij;
     // non-final layers: tensor product + mixing, then the latent MLP that
@@ -995,6 +1097,7 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
       MlpArgs& mL = ml[L];
       mL = base;
       mL.kind = kLatent; mL.w = m->latent[L].view(); mL.head = m->envH[L].g; mL.head_bwd = m->envHT[L].g;
+      mL.rr = rr_view(m->latent[L], m->rr_cfg, &m->rr_envH[L], &m->rr_envHT[L]);
       mL.x_prev = w.x[L]; mL.s_in = w.V[L]; mL.s_ld = v.w_out[L] * n;
       mL.x_out = w.x[L + 1]; mL.head_out = w.wenv[L + 1];
       mL.tm = m->tm_choice[1];
@@ -1214,9 +1317,13 @@ const char* const kTuneNames[8] = {"mlp_fwd_twobody", "mlp_fwd_latent", "mlp_fwd
 void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, hipStream_t s, int32_t* choices) {
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE((pos && species) || m->n_total == 0, "pos and species must not be NULL");
-  // MLP tile rows: BF16 {128 (tall tiles), 64, 32}, FP32 {32, 16}; tensor tiles {32, 16}
-  const int ntm = m->prec ? 3 : 2;
-  const int cand_tm[3] = {m->prec ? 128 : 32, m->prec ? 64 : 16, 32};
+  // MLP tile rows: BF16 {256 (register-resident kernels, where compiled),
+  // 128 (tall tiles), 64, 32}, FP32 {32, 16}; tensor tiles {32, 16} (tried
+  // with the first two MLP candidates)
+  int cand_tm[4], ntm = 0;
+  if (m->prec && m->rr_cfg) cand_tm[ntm++] = kRRTile;
+  if (m->prec) { cand_tm[ntm++] = 128; cand_tm[ntm++] = 64; cand_tm[ntm++] = 32; }
+  else { cand_tm[ntm++] = 32; cand_tm[ntm++] = 16; }
   const int cand_tt[2] = {32, 16};
   m->tune_forces.ensure(std::max<int64_t>(m->n_total, 1) * 3 * sizeof(double));
   m->md_epot.ensure(sizeof(double));
@@ -1264,7 +1371,8 @@ int allegro_set_tiles(AllegroModel* m, const int32_t* tiles) {
     REQUIRE(tiles != nullptr, "tiles is NULL");
     for (int k = 0; k < 6; ++k) {
       const int t = tiles[k];
-      const bool ok = t == 0 || (m->prec ? (t == 128 || t == 64 || t == 32) : (t == 32 || t == 16));
+      const bool ok = t == 0 || (m->prec ? (t == 128 || t == 64 || t == 32 || (t == kRRTile && m->rr_cfg))
+                                         : (t == 32 || t == 16));
       REQUIRE(ok, std::string("tile rows ") + std::to_string(t) + " not available for " + kTuneNames[k]);
     }
     for (int k = 6; k < 8; ++k)
@@ -1511,8 +1619,8 @@ int allegro_energy_forces_noalloc(AllegroModel* m, const double* pos, const int3
     int dev = -1;
     HIP_OK(hipGetDevice(&dev));
     REQUIRE(dev == m->device, "the current device is not the model's device");
-    const bool zbl = !m->znum.empty(), tall = m->prec != ALLEGRO_PREC_FP32;
-    const size_t need = ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, 0, nullptr);
+    const bool zbl = !m->znum.empty(), tall = m->prec != ALLEGRO_PREC_FP32, rr = m->rr_cfg != 0;
+    const size_t need = ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, rr, 0, nullptr);
     REQUIRE(need <= (size_t)ALLEGRO_NOALLOC_SCRATCH_BYTES,
             "the neighbour list needs " + std::to_string(need) + " bytes of workspace, the static workspace holds " +
                 std::to_string((size_t)ALLEGRO_NOALLOC_SCRATCH_BYTES) +
@@ -1520,7 +1628,7 @@ int allegro_energy_forces_noalloc(AllegroModel* m, const double* pos, const int3
     void* base = g_scratch_ptr[dev];
     if (!base) throw Fail{ALLEGRO_E_STATE, "static workspace address not resolved on this device"};
     Ws w;
-    ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, (uintptr_t)base, &w);
+    ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, rr, (uintptr_t)base, &w);
     // no per-kernel timing here: recording it creates events
     const bool timing = m->timing;
     m->timing = false;

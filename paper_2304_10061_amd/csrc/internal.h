@@ -60,6 +60,22 @@ struct MlpW {
   GemmB bwd[kMaxMlpLayers];   // packed W^T (for input gradients)
 };
 
+// Weights of the register-resident BF16 chain kernels (mlp_rr.h): each GEMM
+// out = in @ M packed as A fragments of the 32x32x16 instruction,
+// [pass][K step][block of the pass][hi, lo][64 lanes][8]; lane l of fragment
+// (block mb, K step s) holds M[f][32 mb + l % 32] for input features
+// f = 16 s + 4 (l / 32) + j (j < 4) and 16 s + 8 + 4 (l / 32) + (j - 4) (j >= 4).
+// A pass covers rr_nbp(MB) consecutive blocks of 32 output features.
+__host__ __device__ constexpr int rr_nbp(int mb) { return mb % 2 == 0 ? 2 : 1; }
+constexpr int kRRTile = 256;   // tile value selecting these kernels (edges per block)
+struct RRW {
+  int cfg = 0;                 // 0: not packed; 1: d 256, n 64, 3-layer MLPs; 2: d 128, n 32, 2-layer MLPs
+  const void* fwd[kMaxMlpLayers] = {};
+  const void* bwd[kMaxMlpLayers] = {};   // packed W^T
+  const void* head = nullptr;
+  const void* head_bwd = nullptr;
+};
+
 enum MlpKind { kTwoBody = 0, kLatent = 1, kLatentFinal = 2 };
 
 // Where a tensor-product input V[e][a][u] comes from.
@@ -111,6 +127,9 @@ struct MlpArgs {
   // tall-tile backward only
   float* g_store = nullptr;       // [E][d] receives dE/dx_out (g_xprev, or g_x itself for two-body)
   void* act_scratch = nullptr;    // hidden pre-activations of the recomputation (fragment order)
+  RRW rr;                         // register-resident kernels' weights (rr.cfg = 0: unavailable)
+  const float* fold_v = nullptr;  // final layer, register-resident kernels: v = W_last w_e [d]
+  float sigma[16] = {0};          // species scales sigma_Z (final layer, register-resident backward)
 };
 
 struct EdgeArgs {
@@ -183,6 +202,8 @@ hipError_t launch_mlp_bwd(const MlpArgs& a, int prec, hipStream_t s);
 size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd);
 bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm);
 size_t mlp_tall_scratch_bytes(int64_t E, int d);   // scratch of the 128-row backward kernels
+size_t mlp_rr_scratch_bytes(int64_t E, int d, int nl);   // scratch of the register-resident backward kernels
+hipError_t launch_mlp_rr(const MlpArgs& a, bool bwd, hipStream_t s);   // mlp_rr*.hip
 hipError_t launch_env(const TensorArgs& a, hipStream_t s);
 hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s);
 hipError_t launch_mix_adjoint(const TensorArgs& a, hipStream_t s);

@@ -2,8 +2,26 @@
 // (mlp_kernels.h; instantiated per precision in mlp_fp32.hip, mlp_bf16.hip
 // and mlp_bf16s.hip).
 #include "mlp_kernels.h"
+#include "mlp_rr.h"
 
 namespace allegro {
+
+// register-resident kernels, one source file per latent width and direction
+hipError_t launch_mlp_rr_256_fwd(const MlpArgs& a, hipStream_t s);   // mlp_rr1f.hip
+hipError_t launch_mlp_rr_256_bwd(const MlpArgs& a, hipStream_t s);   // mlp_rr1b.hip
+hipError_t launch_mlp_rr_128_fwd(const MlpArgs& a, hipStream_t s);   // mlp_rr2f.hip
+hipError_t launch_mlp_rr_128_bwd(const MlpArgs& a, hipStream_t s);   // mlp_rr2b.hip
+
+hipError_t launch_mlp_rr(const MlpArgs& a, bool bwd, hipStream_t s) {
+  if (a.E <= 0) return hipSuccess;
+  if (a.kind == kLatentFinal && (a.fold_v == nullptr || a.we == nullptr)) return hipErrorInvalidValue;
+  if (bwd && (a.act_scratch == nullptr || (a.kind != kLatentFinal && a.g_store == nullptr))) return hipErrorInvalidValue;
+  if (a.rr.cfg == 1) return bwd ? launch_mlp_rr_256_bwd(a, s) : launch_mlp_rr_256_fwd(a, s);
+  if (a.rr.cfg == 2) return bwd ? launch_mlp_rr_128_bwd(a, s) : launch_mlp_rr_128_fwd(a, s);
+  return hipErrorInvalidValue;
+}
+
+size_t mlp_rr_scratch_bytes(int64_t E, int d, int nl) { return rr::scratch_bytes(E, d, nl); }
 
 using namespace mlpk;
 
@@ -41,6 +59,8 @@ hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
   // the final layer's backward reads the scalars its forward pass stored
   if (bwd && a.kind == kLatentFinal && a.s_in == nullptr) return hipErrorInvalidValue;
   if (prec == 1 || prec == 2) {
+    // register-resident kernels by default where the model has them
+    if (a.rr.cfg != 0 && (a.tm == kRRTile || a.tm == 0)) return launch_mlp_rr(a, bwd, s);
     // tall tiles on request (autotuner or allegro_set_tiles), where they fit
     if (a.tm == kTallRows && tall_fits(a, prec, bwd))
       return prec == 1 ? launch_prec<1>(a, kTallRows, bwd, s) : launch_prec<2>(a, kTallRows, bwd, s);
@@ -68,6 +88,7 @@ size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd) {
 }
 
 bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm) {
+  if (tm == kRRTile) return prec != 0 && a.rr.cfg != 0;
   if (prec && tm == kTallRows) return tall_fits(a, prec, bwd);
   if (prec) return (tm == 64 || tm == 32) && fits<1>(a, bwd, tm);
   return (tm == 32 || tm == 16) && fits<0>(a, bwd, tm);

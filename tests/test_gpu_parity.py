@@ -166,6 +166,26 @@ def test_bf16_tile_shapes_agree(cfg2):
         assert rel_rms <= 2e-4
 
 
+# Register-resident BF16 chains (256) against the LDS-staged ones, alone and
+# mixed per kernel kind (they share the workspace conventions: the stored
+# final-layer scalars, the staged dE/dx_out rows).
+RR_TILES = [("rr_all", [256] * 6 + [32, 32]),
+            ("rr_fwd_lds_bwd", [256, 256, 256, 64, 64, 64, 32, 32]),
+            ("lds_fwd_rr_bwd", [64, 64, 64, 256, 256, 256, 16, 16])]
+
+
+@pytest.mark.parametrize("prec", [BF16, BF16M], ids=["bf16", "bf16_mixed"])
+@pytest.mark.parametrize("case", RR_TILES, ids=lambda c: c[0])
+def test_register_resident_chains_water_box(cfg2, prec, case):
+    mc, s, w, sc, sh, ref = cfg2
+    name, tiles = case
+    m = gpu_model(mc, w, prec, sc, sh)
+    m.set_tiles(tiles)
+    got = gpu_eval(m, s)
+    _check_bf16(f"cfg2_{name}_{'bf16' if prec == BF16 else 'bf16_mixed'}", got, ref, s.n_local)
+    assert np.allclose(got["atom_virial"].reshape(-1, 3, 3).sum(0), got["virial"].reshape(3, 3), atol=1e-6)
+
+
 def test_repeatable_bitwise(cfg2):
     mc, s, w, sc, sh, ref = cfg2
     m = gpu_model(mc, w, BF16, sc, sh)

@@ -29,13 +29,18 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pro
 # Tile sets, in the order mlp_fwd_twobody, mlp_fwd_latent, mlp_fwd_final,
 # mlp_bwd_final, mlp_bwd_latent, mlp_bwd_twobody, tp_mix, mix_adjoint.
 # Together they run every kernel instantiation the benchmark's autotuner can
-# pick at d = 256, n = 64: 128-row (two column tiles per wave), 64- and
-# 32-row MLP tiles in BF16, 32- and 16-row in FP32, and 32- and 16-edge
-# tensor-product / mixing tiles.
+# pick at d = 256, n = 64: the register-resident BF16 chains (256), 128-row
+# (two column tiles per wave), 64- and 32-row MLP tiles in BF16, 32- and
+# 16-row in FP32, and 32- and 16-edge tensor-product / mixing tiles.
 CASES = [
     ("fp32_rows32_tp32", FP32, [32] * 6 + [32, 32]),
     ("fp32_rows16_tp16", FP32, [16] * 6 + [16, 16]),
     ("bf16mixed_default", BF16M, None),
+    ("bf16mixed_rr_tp16", BF16M, [256] * 6 + [16, 16]),
+    ("bf16mixed_rr_tp32", BF16M, [256] * 6 + [32, 32]),
+    ("bf16_pairs_rr_tp16", BF16, [256] * 6 + [16, 16]),
+    ("bf16mixed_rr_fwd_lds_bwd", BF16M, [256, 256, 256, 64, 64, 64, 16, 16]),
+    ("bf16mixed_lds_fwd_rr_bwd", BF16M, [128, 128, 32, 256, 256, 256, 16, 16]),
     ("bf16mixed_rows128_tp16", BF16M, [128] * 6 + [16, 16]),
     ("bf16mixed_rows64_tp32", BF16M, [64] * 6 + [32, 32]),
     ("bf16mixed_rows32_tp16", BF16M, [32] * 6 + [16, 16]),
@@ -99,7 +104,7 @@ def test_protein_box_autotuned(box, prec):
     picks = m.autotune(pos, sp)
     torch.cuda.synchronize()
     _report(f"cfg3_autotune_{'fp32' if prec == FP32 else 'bf16mixed'}", **{k: int(v) for k, v in picks.items()})
-    allowed_mlp = {32, 16} if prec == FP32 else {128, 64, 32}
+    allowed_mlp = {32, 16} if prec == FP32 else {256, 128, 64, 32}
     assert all(picks[k] in allowed_mlp for k in P.Model.TILE_KINDS[:6])
     assert all(picks[k] in (16, 32) for k in P.Model.TILE_KINDS[6:])
     got = gpu_eval(m, s, want_atom_virial=False)   # keeps the tuned shapes
