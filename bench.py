@@ -405,13 +405,15 @@ def deep_workload_line(steps, warmup, cpu_sample, no_cpu):
 
 
 MD_SIGMA = 0.02
+MD_CLUSTER_SKIN = 0.5   # lists of up to one evaluation chunk are rebuilt inside the step graph
 HEADLINE_PREC = 3   # ALLEGRO_PREC_BF16_MIXED
 
 
 def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
-    """One GPU's MD share: the 1M-atom subdomain with its ghost shell (rebuild
-    every step), or 512 uneven clusters in one batched evaluation (hipGraph
-    replay between neighbour rebuilds)."""
+    """One GPU's MD share: the 1M-atom subdomain with its ghost shell (a list
+    of several evaluation chunks, rebuilt by the host when an atom has moved
+    half the skin), or 512 uneven clusters in one batched evaluation (every
+    step, neighbour rebuild included, a replay of one captured hipGraph)."""
     import torch
     import paper_2304_10061_amd as P
     import workloads as W
@@ -423,12 +425,12 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
     if kind == "subdomain":
         base = W.jittered_lattice_box(1_000_000, 215.0, 0.5, W.PROTEIN_MIX, 4, sites_per_side=100)
         sysm = W.ghost_shell(base, 6.0)
-        skin, rebuild = 0.3, 1
+        skin = 0.3
         chunk = 8_000_000
         masses = base.masses
     else:
         sysm = W.clusters(512, 5)
-        skin, rebuild = 1.0, 5
+        skin = MD_CLUSTER_SKIN
         chunk = 0
         masses = sysm.masses
     t_gen = time.perf_counter() - t_gen
@@ -457,34 +459,21 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
     if kind == "subdomain":
         own = sysm.ghost_owner
         m.set_ghosts(nl, own, sysm.pos[nl:] - base.pos[own])
-    build()
+    e_first = build()
     tiles = m.autotune(pos, sp)   # edge-tile shapes for this system (a few evaluations)
-    disp_max, edges = 0.0, []
-    done = 0
-    first = True
-    valid = True            # every chunk ended with max displacement <= skin / 2
+    # warm-up steps (the first call captures the step graph), then the timed
+    # steps in one call: the list is rebuilt inside the steps whenever an
+    # atom has moved half the skin since the last build
+    use_graph = kind == "clusters"
+    _, over_warm = m.md_run_all(warmup, dt_fs, mass, pos, vel, F, sp, thermo=thermo[:warmup], init_forces=True,
+                                use_graph=use_graph)
+    captures_warm = m.md_stats()[0]
     torch.cuda.synchronize()
-    t0 = None
-    while done < n_total_steps:
-        if done == warmup:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-        # chunks never straddle the end of the warm-up
-        k = min(rebuild, n_total_steps - done, warmup - done if done < warmup else n_total_steps)
-        if not first:
-            edges.append(build())
-        else:
-            edges.append(m.num_edges())
-        d = m.md_run(k, dt_fs, mass, pos, vel, F, sp, thermo=thermo[done:done + k], init_forces=first,
-                     use_graph=(kind == "clusters"), want_max_disp=True)
-        disp_max = max(disp_max, d)
-        valid = valid and d <= 0.5 * skin
-        if d > 0.35 * skin and rebuild > 1:
-            rebuild //= 2          # rebuild sooner when atoms approach half the skin
-        first = False
-        done += k
+    t0 = time.perf_counter()
+    disp, over_timed = m.md_run_all(steps, dt_fs, mass, pos, vel, F, sp, thermo=thermo[warmup:], use_graph=use_graph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    captures, capacity, dev_rebuild, rebuilds = m.md_stats()
     free1, _ = torch.cuda.mem_get_info()
     th = thermo.cpu().numpy()
     etot = th[:, 0] + th[:, 1]
@@ -495,18 +484,23 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": ("1,000,000-atom protein-like subdomain (215 A) + 6 A periodic-image ghost shell, "
-                                "model r_c 4 A, n 32, latent [128,128], neighbour list rebuilt every step"
+                                "model r_c 4 A, n 32, latent [128,128], list in 8M-edge chunks rebuilt by the host "
+                                "when an atom has moved half the skin"
                                 if kind == "subdomain" else
-                                "512 non-periodic clusters (20-2000 atoms, log-uniform), batched, hipGraph replay "
-                                "of the velocity-Verlet step, neighbour rebuild every 5 steps (sooner if atoms near half the skin)"),
+                                "512 non-periodic clusters (20-2000 atoms, log-uniform), batched; each step, neighbour "
+                                "rebuild on the device included, is a replay of one captured hipGraph"),
                    "atoms": int(nl), "ghosts": int(sysm.n_total - nl), "dt_fs": dt_fs,
-                   "neighbor_skin": skin, "edges_mean": float(np.mean(edges)) if edges else None},
+                   "neighbor_skin": skin, "edges_first_build": int(e_first), "edges_last_build": int(m.num_edges())},
         "peak_hbm_GB": (free0 - free1) / 1e9,
         "library_workspace_GB": m.workspace_bytes() / 1e9,
         "energy_drift_per_atom": float((etot[-1] - etot[0]) / nl),
         "energy_fluct_per_atom": float(np.std(etot) / nl),
-        "max_displacement_between_rebuilds": disp_max,
-        "neighbor_list_valid": bool(valid), "rebuild_every_final": rebuild, "species_energy_scale": MD_SIGMA,
+        "species_energy_scale": MD_SIGMA,
+        "neighbor_rebuilds_timed_last_call": int(rebuilds), "rebuilds_on_device": bool(dev_rebuild),
+        "edge_capacity": int(capacity), "graph_captures": int(captures),
+        "capacity_overflows": {"warmup": over_warm, "timed": over_timed},
+        "graph_captures_during_timed_steps": int(captures - captures_warm),
+        "max_displacement_since_last_rebuild": disp,
         "tiles": tiles, "setup_s": t_gen,
     }
     m.close()

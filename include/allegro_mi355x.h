@@ -39,8 +39,10 @@ enum {
   ALLEGRO_OK = 0,
   ALLEGRO_E_INVAL = -1,     /* bad argument, shape or unsupported configuration */
   ALLEGRO_E_NOMEM = -2,     /* device or host allocation failed */
-  ALLEGRO_E_CAPACITY = -3,  /* edge capacity exceeded (capacity-limited mode);
-                               capacity has been regrown, call again */
+  ALLEGRO_E_CAPACITY = -3,  /* a neighbour-list rebuild inside allegro_md_run
+                               needed more edges than the list's capacity; the
+                               capacity has been regrown, the steps before it are
+                               complete, call again for the rest */
   ALLEGRO_E_DEVICE = -4,    /* a HIP runtime call failed */
   ALLEGRO_E_NONFINITE = -5, /* non-finite positions (allegro_neighbors), or a
                                non-finite atom energy or force was produced
@@ -107,6 +109,14 @@ typedef struct AllegroModel AllegroModel; /* opaque, library-owned */
  *                    be reused over several MD steps; pairs beyond r_cut carry
  *                    a zero envelope and contribute exactly zero.  0 = the list
  *                    holds exactly the pairs inside r_cut.
+ *   edge_capacity_hint  edges the neighbour-list buffers hold (fixed-shape
+ *                    buffers for in-graph rebuilds in allegro_md_run, section
+ *                    "Optimized LAMMPS-Kokkos implementation": preprocessing on
+ *                    the device into padded buffers).  0 = 5 % more than the
+ *                    list allegro_neighbors builds; otherwise at least this
+ *                    many (never fewer than the list).  The capacity only
+ *                    grows; a rebuild inside allegro_md_run that needs more
+ *                    returns ALLEGRO_E_CAPACITY after regrowing it.
  *   r_cut_pair       host [n_species][n_species] cutoffs of ordered species pairs
  *                    (A), row = species of the centre, column = species of the
  *                    neighbour, each in (0, r_cut]; or NULL = r_cut for every
@@ -136,6 +146,7 @@ typedef struct {
   int32_t precision;
   int64_t edge_chunk;
   double neighbor_skin;
+  int64_t edge_capacity_hint;
   const double* r_cut_pair;
   const int32_t* atomic_numbers;
 } AllegroConfig;
@@ -334,28 +345,51 @@ int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const 
 
 /*
  * allegro_md_run: n_steps of FP64 velocity Verlet (section "Problem overview":
- * MD needs forces every step) on the current neighbour list, which should have
- * been built with a neighbor_skin large enough for the displacement over these
- * steps.  Per step: v += dt/2 F/m; x += dt v; ghosts follow their owners;
- * F = -dE/dx; ghost forces fold onto owners; v += dt/2 F/m.
+ * MD needs forces every step).  Per step: v += dt/2 F/m; x += dt v; ghosts
+ * follow their owners; the neighbour list is rebuilt when some centre has
+ * moved more than half the neighbor_skin since the last build; F = -dE/dx;
+ * ghost forces fold onto owners; v += dt/2 F/m.
+ * Lists that fit one evaluation chunk are rebuilt on the device, inside the
+ * step (section "Optimized LAMMPS-Kokkos implementation": preprocessing on the
+ * device into fixed-shape buffers): the list buffers keep their edge capacity
+ * (edge_capacity_hint), the cell grid of the last allegro_neighbors call is
+ * reused, and with use_graph one captured step (rebuild included) is replayed
+ * n_steps times with no host round trip.  Larger lists are rebuilt by the host
+ * between eager steps (use_graph is then ignored).
  *   n_steps      steps to run (>= 0); dt_fs the time step in fs
  *   masses       dev [n_local] double, amu
  *   pos, vel     dev [n_total][3] / [n_local][3] double, A and A/fs, updated
  *   forces       dev [n_total][3] double: on entry the (folded) forces at pos
- *                unless init_forces = 1; on return the forces at the final pos
+ *                (or pass init_forces = 1 to compute them first); on exit the
+ *                forces at the final positions
  *   species      dev [n_total] int32
- *   thermo       dev [n_steps][2] double, potential and kinetic energy after
- *                each step (may be NULL)
- *   use_graph    1 = capture one step in a HIP graph (captured once per
- *                neighbour list and argument set) and replay it n_steps times
+ *   thermo       dev [2 n_steps] double or NULL: per step (E_pot, E_kin) in eV
+ *   use_graph    1 = run the steps as replays of one captured HIP graph
  *   max_disp     host, receives the largest centre displacement since the
- *                neighbour build (may be NULL)
- * Synchronises the stream at the end and returns ALLEGRO_E_NONFINITE (as
- * allegro_check) when a step produced non-finite forces or energies.
+ *                last neighbour build (may be NULL)
+ *   steps_done   host, receives the number of completed steps (may be NULL)
+ * Returns ALLEGRO_E_CAPACITY when a device-side rebuild needed more edges than
+ * the capacity: pos, vel and forces then hold the state after *steps_done
+ * steps, the capacity has been regrown and the list rebuilt there, and
+ * calling again for the remaining steps continues the same trajectory (thermo
+ * rows from step *steps_done on are not valid).  Synchronises the stream at
+ * the end and returns ALLEGRO_E_NONFINITE (as allegro_check) when a step
+ * produced non-finite forces or energies.
  */
 int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos,
                    double* vel, double* forces, const int32_t* species, double* thermo,
-                   int32_t init_forces, int32_t use_graph, void* stream, double* max_disp);
+                   int32_t init_forces, int32_t use_graph, void* stream, double* max_disp,
+                   int32_t* steps_done);
+
+/*
+ * allegro_md_stats: MD step graphs captured so far by allegro_md_run, the
+ * neighbour list's edge capacity, whether its rebuilds run on the device (1)
+ * or on the host (0), and how many of the last allegro_md_run call's
+ * completed steps rebuilt the list (device rebuilds only; host rebuilds are
+ * counted too when they run).  Host outputs, each may be NULL.
+ */
+int allegro_md_stats(const AllegroModel* m, int64_t* graph_captures, int64_t* edge_capacity,
+                     int32_t* device_rebuild, int64_t* last_run_rebuilds);
 
 /*
  * allegro_check: synchronise `stream` and report what the device recorded

@@ -26,7 +26,7 @@ NOALLOC_SCRATCH_BYTES = 256 << 20   # ALLEGRO_NOALLOC_SCRATCH_BYTES
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTS = ("allegro_describe", "allegro_plan_chunks", "allegro_create", "allegro_neighbors", "allegro_neighbors_batched",
            "allegro_system_energies", "allegro_energy_forces", "allegro_energy_forces_noalloc",
-           "allegro_autotune", "allegro_set_tiles", "allegro_set_ghosts", "allegro_md_run", "allegro_check", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
+           "allegro_autotune", "allegro_set_tiles", "allegro_set_ghosts", "allegro_md_run", "allegro_md_stats", "allegro_check", "allegro_copy_edges", "allegro_num_edges", "allegro_set_timing", "allegro_kernel_times",
            "allegro_workspace_bytes", "allegro_destroy", "allegro_last_error", "allegro_status_string")
 
 
@@ -40,6 +40,7 @@ class AllegroConfig(ctypes.Structure):
                 ("r_cut", ctypes.c_double), ("avg_num_neighbors", ctypes.c_double),
                 ("channel_mix", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("edge_chunk", ctypes.c_int64), ("neighbor_skin", ctypes.c_double),
+                ("edge_capacity_hint", ctypes.c_int64),
                 ("r_cut_pair", ctypes.POINTER(ctypes.c_double)),
                 ("atomic_numbers", ctypes.POINTER(ctypes.c_int32))]
 
@@ -96,8 +97,10 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_set_ghosts.argtypes = [vp, i64, i64, vp, vp]
     lib.allegro_set_ghosts.restype = ctypes.c_int
     lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, i32, i32, vp,
-                                   ctypes.POINTER(ctypes.c_double)]
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     lib.allegro_md_run.restype = ctypes.c_int
+    lib.allegro_md_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.allegro_md_stats.restype = ctypes.c_int
     lib.allegro_check.argtypes = [vp, vp]
     lib.allegro_check.restype = ctypes.c_int
     lib.allegro_copy_edges.argtypes = [vp, dp, dp, dp, vp]
@@ -126,6 +129,7 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
                 latent_dims: Sequence[int] = (128, 128), edge_dims: Sequence[int] = (128,),
                 avg_num_neighbors: Optional[float] = None, channel_mix: bool = True,
                 precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0,
+                edge_capacity_hint: int = 0,
                 r_cut_pair=None, atomic_numbers=None) -> AllegroConfig:
     """r_cut_pair: optional [n_species][n_species] ordered cutoffs (row = centre species);
     atomic_numbers: optional [n_species] (switches on the ZBL pair term)."""
@@ -146,6 +150,7 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
     c.precision = int(precision)
     c.edge_chunk = int(edge_chunk)
     c.neighbor_skin = float(neighbor_skin)
+    c.edge_capacity_hint = int(edge_capacity_hint)
     if r_cut_pair is not None:
         flat = [float(v) for row in r_cut_pair for v in row]
         if len(flat) != n_species * n_species:
@@ -162,14 +167,15 @@ def make_config(n_species: int, r_cut: float, *, n_bessel: int = 8, envelope_p: 
     return c
 
 
-def config_from(mc, precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0) -> AllegroConfig:
+def config_from(mc, precision: int = PREC_BF16, edge_chunk: int = 0, neighbor_skin: float = 0.0,
+                edge_capacity_hint: int = 0) -> AllegroConfig:
     """Config from any object with the ModelConfig attribute names."""
     return make_config(mc.n_species, mc.r_cut, n_bessel=mc.n_bessel, envelope_p=mc.envelope_p,
                        l_max=mc.l_max, n_layers=mc.n_layers, n_tensor=mc.n_tensor,
                        twobody_dims=mc.twobody_dims, latent_dims=mc.latent_dims, edge_dims=mc.edge_dims,
                        avg_num_neighbors=mc.avg_num_neighbors, channel_mix=mc.channel_mix,
                        precision=precision, edge_chunk=edge_chunk, neighbor_skin=neighbor_skin,
-                       r_cut_pair=getattr(mc, "pair_cutoffs", None),
+                       edge_capacity_hint=edge_capacity_hint, r_cut_pair=getattr(mc, "pair_cutoffs", None),
                        atomic_numbers=getattr(mc, "atomic_numbers", None))
 
 
@@ -317,13 +323,45 @@ class Model:
     def md_run(self, n_steps, dt_fs, masses, pos, vel, forces, species, thermo=None, init_forces=False,
                use_graph=True, stream=None, want_max_disp=True):
         """Velocity Verlet on the device; returns the max displacement since the
-        last neighbour build (or None)."""
+        last neighbour build (or None).  Raises AllegroError (ALLEGRO_E_CAPACITY
+        with .steps_done set) when an in-graph rebuild outgrew the capacity."""
         md = ctypes.c_double(0.0)
-        self._check(self.lib.allegro_md_run(self.handle, int(n_steps), float(dt_fs), _ptr(masses), _ptr(pos),
-                                            _ptr(vel), _ptr(forces), _ptr(species), _ptr(thermo),
-                                            1 if init_forces else 0, 1 if use_graph else 0, _stream(stream),
-                                            ctypes.byref(md) if want_max_disp else None))
+        done = ctypes.c_int32(0)
+        st = self.lib.allegro_md_run(self.handle, int(n_steps), float(dt_fs), _ptr(masses), _ptr(pos),
+                                     _ptr(vel), _ptr(forces), _ptr(species), _ptr(thermo),
+                                     1 if init_forces else 0, 1 if use_graph else 0, _stream(stream),
+                                     ctypes.byref(md) if want_max_disp else None, ctypes.byref(done))
+        if st != ALLEGRO_OK:
+            err = AllegroError(st, self.lib.allegro_last_error(self.handle).decode())
+            err.steps_done = int(done.value)
+            raise err
         return md.value if want_max_disp else None
+
+    def md_run_all(self, n_steps, dt_fs, masses, pos, vel, forces, species, thermo=None, init_forces=False,
+                   use_graph=True, stream=None, max_overflows=16):
+        """md_run for n_steps, resuming after each ALLEGRO_E_CAPACITY (the
+        library has regrown the list by then); returns (max displacement since
+        the last build, number of overflows)."""
+        done, overflows = 0, 0
+        while True:
+            try:
+                d = self.md_run(n_steps - done, dt_fs, masses, pos, vel, forces, species,
+                                thermo=None if thermo is None else thermo[done:], init_forces=init_forces and done == 0,
+                                use_graph=use_graph, stream=stream)
+                return d, overflows
+            except AllegroError as e:
+                if e.status != -3 or overflows >= max_overflows:
+                    raise
+                overflows += 1
+                done += e.steps_done
+
+    def md_stats(self):
+        """(graph captures so far, edge capacity, 1 if rebuilds run on the device,
+        list rebuilds during the last md_run)."""
+        caps, cap, dev, nb = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int64(0)
+        self._check(self.lib.allegro_md_stats(self.handle, ctypes.byref(caps), ctypes.byref(cap), ctypes.byref(dev),
+                                              ctypes.byref(nb)))
+        return int(caps.value), int(cap.value), int(dev.value), int(nb.value)
 
     def check(self, stream=None):
         """Synchronise and raise AllegroError if an evaluation since the last

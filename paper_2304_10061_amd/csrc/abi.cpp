@@ -213,6 +213,7 @@ Validated validate(const AllegroConfig* c) {
           "precision must be 0, 1, 2 or 3");
   REQUIRE(c->edge_chunk >= 0, "edge_chunk must be >= 0");
   REQUIRE(c->neighbor_skin >= 0 && std::isfinite(c->neighbor_skin), "neighbor_skin must be >= 0");
+  REQUIRE(c->edge_capacity_hint >= 0, "edge_capacity_hint must be >= 0");
   if (c->atomic_numbers)
     for (int k = 0; k < v.S; ++k)
       REQUIRE(c->atomic_numbers[k] >= 1 && c->atomic_numbers[k] <= 118, "atomic_numbers must lie in 1..118");
@@ -506,6 +507,16 @@ struct AllegroModel {
   std::vector<int64_t> chunk_rp_off;      // offset of each chunk's rebased row pointers
   DevBuf chunk_rp;
   int64_t Ec = 0, Nc = 0;
+  // edge capacity of the list buffers, and what an in-graph rebuild needs:
+  // the last build's grid and buffers (NbrArgs), its cell count and box
+  int64_t cap = 0;
+  NbrArgs nbr{};
+  int64_t n_cells = 0;
+  bool dev_rebuild = false;               // single-chunk list: rebuilds can run on the device
+  double last_cell[9] = {0};
+  int32_t last_pbc[3] = {0, 0, 0};
+  bool last_has_cell = false;
+  std::vector<int64_t> last_sys_off;
 
   // tile shapes chosen by allegro_autotune (0 = default)
   int tm_choice[6] = {0, 0, 0, 0, 0, 0};   // MLP kernels, see kMlpSlotNames
@@ -517,11 +528,16 @@ struct AllegroModel {
   DevBuf g_owner, g_offset, g_ptr, g_idx; // ghost images and the owner -> ghosts CSR
   DevBuf pos_ref;                         // positions of the centres at the last neighbour build
   DevBuf md_epot, md_part, md_counter, md_atom_e, tune_forces;
+  DevBuf md_flags;                        // kFlag* slots of the in-graph rebuild
+  DevBuf bak_pos, bak_vel, bak_f;         // state at the start of the step that overflowed
   hipStream_t md_stream = nullptr;
   hipEvent_t md_ev[2] = {nullptr, nullptr};
   hipGraph_t md_graph = nullptr;
   hipGraphExec_t md_exec = nullptr;
   std::vector<uintptr_t> md_key;
+  int64_t graph_captures = 0;             // MD step graphs captured so far
+  int64_t last_run_rebuilds = 0;          // list rebuilds in the last allegro_md_run
+  int64_t need_edges = 0;                 // largest list a device rebuild asked for
 
   // optional per-kernel timing with HIP events on the caller's stream
   bool timing = false;
@@ -843,6 +859,19 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   REQUIRE(n_total < (int64_t)1 << 30, "at most 2^30 atoms");
   // earlier work on this stream may still use buffers that are regrown below
   HIP_OK(hipStreamSynchronize(s));
+  {
+    // the box of this build, for rebuilds requested later by allegro_md_run
+    // (copied first: the arguments may be these very arrays)
+    double cl[9] = {0};
+    int32_t pl[3] = {pbc[0], pbc[1], pbc[2]};
+    if (cell) std::memcpy(cl, cell, sizeof(cl));
+    std::vector<int64_t> so;
+    if (sys_off && n_sys > 0) so.assign(sys_off, sys_off + n_sys + 1);
+    std::memcpy(m->last_cell, cl, sizeof(cl));
+    std::memcpy(m->last_pbc, pl, sizeof(pl));
+    m->last_has_cell = cell != nullptr;
+    m->last_sys_off = std::move(so);
+  }
   const double rc = m->cfg.r_cut + m->cfg.neighbor_skin;   // list radius
   double L[3];
   int pb[3];
@@ -981,7 +1010,21 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   const int64_t E = m->h_row_ptr[n_local];
   REQUIRE(E <= ((((int64_t)1 << 31) - 1) / 3), "more than (2^31 - 1) / 3 edges");
   m->E = E;
-  const int64_t Ee = std::max<int64_t>(E, 1);
+  // Edge capacity of the list buffers: the list plus 5 % (or the caller's
+  // hint), never shrinking.  A list that fits one evaluation chunk, and has
+  // not outgrown one in a device rebuild, can be rebuilt on the device
+  // (allegro_md_run), within the capacity.
+  {
+    const int64_t hint = m->cfg.edge_capacity_hint;
+    const int64_t want = hint > 0 ? std::max<int64_t>(hint, E) : E + (E + 19) / 20;
+    const int64_t one_chunk = chunk_cap(m->v, m->cfg.edge_chunk);
+    const int64_t floor_e = std::max<int64_t>(std::max(E, m->need_edges), 1);
+    m->cap = std::max(std::max(want, m->cap), floor_e);
+    m->cap = std::min<int64_t>(m->cap, ((((int64_t)1 << 31) - 1) / 3));
+    m->dev_rebuild = floor_e <= one_chunk;
+    if (m->dev_rebuild) m->cap = std::max(std::min(m->cap, one_chunk), floor_e);
+  }
+  const int64_t Ee = m->cap;
   m->ei.ensure(Ee * 4); m->ej.ensure(Ee * 4); m->es.ensure(Ee * 12); m->keys.ensure(Ee * 8);
   m->redge.ensure(Ee * 4);
   a.keys = ptr<unsigned long long>(m->keys); a.ei = ptr<int32_t>(m->ei); a.ej = ptr<int32_t>(m->ej);
@@ -991,6 +1034,8 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   HIP_OK(launch_fill_i32(a.rcount, 0, n_total, s));
   HIP_OK(launch_fill_i32(a.rcursor, 0, n_total, s));
   HIP_OK(launch_reverse_csr(a, E, s));
+  m->nbr = a;
+  m->n_cells = ncell;
 
   // chunks of whole centres and the workspace they need
   {
@@ -1003,6 +1048,7 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
     m->Ec = std::max<int64_t>(m->Ec, m->h_row_ptr[cB] - m->h_row_ptr[cA]);
     m->Nc = std::max<int64_t>(m->Nc, cB - cA);
   }
+  if (m->dev_rebuild) m->Ec = std::max(m->Ec, m->cap);   // device rebuilds use the whole capacity
   {
     std::vector<int32_t> crp;
     m->chunk_rp_off.clear();
@@ -1014,10 +1060,10 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
     if (crp.empty()) crp.push_back(0);
     upload(m->chunk_rp, crp.data(), crp.size() * sizeof(int32_t));
   }
-  m->ws_bytes = ws_layout(m->v, m->Ec, m->Nc, E, n_local, n_total, !m->znum.empty(),
+  m->ws_bytes = ws_layout(m->v, m->Ec, m->Nc, m->cap, n_local, n_total, !m->znum.empty(),
                           m->prec != ALLEGRO_PREC_FP32, m->rr_cfg != 0, 0, nullptr);
   m->arena.ensure(m->ws_bytes);
-  ws_layout(m->v, m->Ec, m->Nc, E, n_local, n_total, !m->znum.empty(), m->prec != ALLEGRO_PREC_FP32,
+  ws_layout(m->v, m->Ec, m->Nc, m->cap, n_local, n_total, !m->znum.empty(), m->prec != ALLEGRO_PREC_FP32,
             m->rr_cfg != 0, (uintptr_t)m->arena.p, &m->ws);
   m->pos_ref.ensure(std::max<int64_t>(n_local, 1) * 3 * sizeof(double));
   if (n_local > 0)
@@ -1026,9 +1072,12 @@ void neighbors_impl(AllegroModel* m, int64_t n_local, int64_t n_total, const dou
   if (n_edges) *n_edges = E;
 }
 
+// dev_count: the list may have been rebuilt on the device since the host
+// last saw it (in-graph MD): launch over the edge capacity, with the live
+// edge count and the row pointers read on the device (single-chunk lists).
 void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const int32_t* species,
                         double* atom_energy, double* forces, double* virial, double* atom_virial, double* energy,
-                        hipStream_t s) {
+                        hipStream_t s, bool dev_count = false) {
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE((pos && species && forces) || m->n_total == 0, "pos, species and forces must not be NULL");
   const Validated& v = m->v;
@@ -1037,15 +1086,18 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
   const int32_t* ei = ptr<int32_t>(m->ei);
   const int32_t* ej = ptr<int32_t>(m->ej);
   const int32_t* es = ptr<int32_t>(m->es);
+  if (dev_count) REQUIRE(m->dev_rebuild && m->chunk_c.size() == 2, "device-side edge count needs a single chunk");
   for (size_t k = 0; k + 1 < m->chunk_c.size(); ++k) {
     const int64_t cA = m->chunk_c[k], cB = m->chunk_c[k + 1];
-    const int64_t eA = m->h_row_ptr[cA], eB = m->h_row_ptr[cB];
+    const int64_t eA = dev_count ? 0 : m->h_row_ptr[cA], eB = dev_count ? m->cap : m->h_row_ptr[cB];
     const int E = (int)(eB - eA), nc = (int)(cB - cA);
-    // row pointers of the chunk's centres, relative to its first edge
-    const int32_t* drp = ptr<int32_t>(m->chunk_rp) + m->chunk_rp_off[k];
+    // row pointers of the chunk's centres, relative to its first edge (the
+    // list's own row pointers for a device-side count: one chunk from 0)
+    const int32_t* drp = dev_count ? ptr<int32_t>(m->row_ptr) : ptr<int32_t>(m->chunk_rp) + m->chunk_rp_off[k];
+    const int32_t* E_dev = dev_count ? ptr<int32_t>(m->row_ptr) + m->n_local : nullptr;
 
     EdgeArgs ea;
-    ea.E = E; ea.pos = pos; ea.ei = ei + eA; ea.ej = ej + eA; ea.es = es + 3 * eA; ea.species = species;
+    ea.E = E; ea.E_dev = E_dev; ea.pos = pos; ea.ei = ei + eA; ea.ej = ej + eA; ea.es = es + 3 * eA; ea.species = species;
     for (int ax = 0; ax < 3; ++ax) ea.L[ax] = m->L[ax];
     ea.r_cut = m->cfg.r_cut; ea.p = v.p; ea.n_bessel = v.nb; ea.l_max = v.lmax;
     ea.rc_pair = m->rc_pair.empty() ? nullptr : ptr<float>(m->rc_pair_f); ea.n_species = v.S;
@@ -1054,7 +1106,7 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
     timed(m, "edge_basis", s, [&] { return launch_edge_basis(ea, s); });
 
     MlpArgs base;
-    base.E = E; base.d = d; base.n = n; base.l_max = v.lmax; base.n_species = v.S; base.n_bessel = v.nb;
+    base.E = E; base.E_dev = E_dev; base.d = d; base.n = n; base.l_max = v.lmax; base.n_species = v.S; base.n_bessel = v.nb;
     base.eb = w.eb; base.ei = ei + eA; base.ej = ej + eA; base.species = species;
     base.centre_base = (int)cA;
 
@@ -1066,7 +1118,7 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
     timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, m->prec_two, s); });
 
     TensorArgs tb;
-    tb.E = E; tb.n_centres = nc; tb.n = n; tb.l_max = v.lmax; tb.row_ptr = drp; tb.ei = ei + eA;
+    tb.E = E; tb.E_dev = E_dev; tb.n_centres = nc; tb.n = n; tb.l_max = v.lmax; tb.row_ptr = drp; tb.ei = ei + eA;
     tb.centre_base = (int)cA; tb.eb = w.eb; tb.c_norm = (float)m->c_norm;
     tb.channel_mix = m->cfg.channel_mix ? 1 : 0; tb.mix_scale = (float)(1.0 / std::sqrt((double)n));
     tb.mix_stride = m->mix_stride;
@@ -1226,45 +1278,134 @@ void release_graph(AllegroModel* m) {
   m->md_key.clear();
 }
 
+// Neighbour-list rebuild inside an MD step, on the device (single-chunk
+// lists): every kernel runs only when some centre moved more than half the
+// skin since the last build (flags[kFlagRebuild]).  The list keeps the cell
+// grid and buffers of the last host build and holds at most m->cap edges; a
+// rebuild that needs more sets kFlagHalt and clamps the row pointers to the
+// capacity, so that the rest of the step stays in bounds (allegro_md_run then
+// discards it).
+void device_rebuild(AllegroModel* m, const double* pos, const int32_t* species, hipStream_t s) {
+  int32_t* flags = ptr<int32_t>(m->md_flags);
+  NbrArgs a = m->nbr;
+  a.pos = pos;
+  a.species = species;
+  a.pred = flags + kFlagRebuild;
+  const double half = 0.5 * m->cfg.neighbor_skin;
+  HIP_OK(launch_fill_i32(flags + kFlagRebuild, 0, 1, s));
+  HIP_OK(launch_disp_check(m->n_local, pos, ptr<double>(m->pos_ref), half * half, flags, s));
+  HIP_OK(launch_fill_i32(a.cell_count, 0, m->n_cells, s));
+  HIP_OK(launch_fill_i32(a.cell_cursor, 0, m->n_cells, s));
+  HIP_OK(launch_fill_i32(a.rcount, 0, m->n_total, s));
+  HIP_OK(launch_fill_i32(a.rcursor, 0, m->n_total, s));
+  if (m->n_total > 0) HIP_OK(launch_bin_atoms_err(a, ptr<int>(m->err_flag), s));
+  HIP_OK(launch_exclusive_scan(a.cell_count, a.cell_start, m->n_cells, a.scan_tmp, s, a.pred));
+  if (m->n_total > 0) HIP_OK(launch_fill_cells(a, s));
+  HIP_OK(launch_count_neighbors(a, s));
+  HIP_OK(launch_exclusive_scan(a.count, a.row_ptr, m->n_local, a.scan_tmp, s, a.pred));
+  HIP_OK(launch_capacity_check(a.row_ptr, m->n_local, m->cap, flags, ptr<int>(m->status), s));
+  HIP_OK(launch_fill_neighbors(a, s));
+  HIP_OK(launch_sort_neighbors(a, s));
+  HIP_OK(launch_reverse_csr(a, m->cap, s));
+  HIP_OK(launch_copy_f64_flag(ptr<double>(m->pos_ref), pos, m->n_local * 3, flags, kFlagRebuild, 1, s));
+}
+
+// The last host build's box and systems, for rebuilds at new positions.
+void host_rebuild(AllegroModel* m, const double* pos, const int32_t* species, hipStream_t s) {
+  const std::vector<int64_t> so = m->last_sys_off;
+  double cl[9];
+  int32_t pl[3];
+  std::memcpy(cl, m->last_cell, sizeof(cl));
+  std::memcpy(pl, m->last_pbc, sizeof(pl));
+  neighbors_impl(m, m->n_local, m->n_total, pos, species, m->last_has_cell ? cl : nullptr, pl, s, nullptr,
+                 so.empty() ? nullptr : so.data(), so.empty() ? 0 : (int)so.size() - 1);
+}
+
+// Lists evaluated in several chunks cannot be rebuilt on the device: the host
+// checks the displacement and rebuilds (eager steps only).
+void host_rebuild_if_needed(AllegroModel* m, const double* pos, const int32_t* species, hipStream_t s) {
+  int nb = 0;
+  HIP_OK(launch_max_disp(m->n_local, pos, ptr<double>(m->pos_ref), ptr<double>(m->md_part), &nb, s));
+  std::vector<double> part(nb);
+  HIP_OK(hipMemcpyAsync(part.data(), m->md_part.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  double mx = 0.0;
+  for (double v : part) mx = std::max(mx, v);
+  const double half = 0.5 * m->cfg.neighbor_skin;
+  if (!(mx <= half * half)) {
+    host_rebuild(m, pos, species, s);
+    m->last_run_rebuilds++;
+  }
+}
+
+// One velocity-Verlet step; dev: the list is rebuilt on the device when needed
+// and the state at the start of the step is kept until a rebuild overflows.
 void md_step(AllegroModel* m, double dt, const double* masses, double* pos, double* vel, double* forces,
-             const int32_t* species, double* thermo, int cap, hipStream_t s) {
-  const int64_t nl = m->n_local;
+             const int32_t* species, bool dev, hipStream_t s) {
+  const int64_t nl = m->n_local, nt = m->n_total;
+  int32_t* flags = ptr<int32_t>(m->md_flags);
+  if (dev) {
+    HIP_OK(launch_copy_f64_flag(ptr<double>(m->bak_pos), pos, nt * 3, flags, kFlagHalt, 0, s));
+    HIP_OK(launch_copy_f64_flag(ptr<double>(m->bak_vel), vel, nl * 3, flags, kFlagHalt, 0, s));
+    HIP_OK(launch_copy_f64_flag(ptr<double>(m->bak_f), forces, nt * 3, flags, kFlagHalt, 0, s));
+  }
   HIP_OK(launch_kick_drift(nl, dt, masses, pos, vel, forces, s));
   if (m->n_ghost > 0)
     HIP_OK(launch_ghost_refresh(m->n_ghost, nl, ptr<int32_t>(m->g_owner), ptr<double>(m->g_offset), pos, s));
-  energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
+  if (dev) device_rebuild(m, pos, species, s);
+  else host_rebuild_if_needed(m, pos, species, s);
+  energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr,
+                     ptr<double>(m->md_epot), s, dev);
   if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
   HIP_OK(launch_kick(nl, dt, masses, vel, forces, s));
-  if (thermo)
-    HIP_OK(launch_thermo(nl, masses, vel, ptr<double>(m->md_part), ptr<double>(m->md_epot), thermo,
-                         ptr<int>(m->md_counter), cap, s));
+  HIP_OK(launch_thermo(nl, masses, vel, ptr<double>(m->md_part), ptr<double>(m->md_epot),
+                       ptr<ThermoTarget>(m->md_counter), s));
+  if (dev) HIP_OK(launch_step_done(flags, s));
 }
 
 void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, double* pos, double* vel,
                  double* forces, const int32_t* species, double* thermo, int init_forces, int use_graph,
-                 hipStream_t s, double* max_disp) {
+                 hipStream_t s, double* max_disp, int32_t* steps_done) {
+  if (steps_done) *steps_done = 0;
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
   REQUIRE(n_steps >= 0 && std::isfinite(dt) && dt > 0, "need n_steps >= 0 and dt > 0");
   REQUIRE(m->n_sys == 0 || m->n_ghost == 0, "ghost images are not used with batched systems");
   REQUIRE(m->n_ghost == 0 || (m->ghost_n_local == m->n_local && m->n_local + m->n_ghost == m->n_total),
           "ghost description does not match the neighbour list");
   REQUIRE((masses && pos && vel && forces && species) || m->n_total == 0, "NULL array");
-  const int64_t nl = m->n_local;
+  const int64_t nl = m->n_local, nt = m->n_total;
+  const bool dev = m->dev_rebuild;
   m->md_epot.ensure(sizeof(double));
-  m->md_counter.ensure(sizeof(int));
+  m->md_counter.ensure(sizeof(ThermoTarget));
   m->md_part.ensure(((std::max<int64_t>(nl, 1) + 255) / 256) * sizeof(double));
   m->md_atom_e.ensure(std::max<int64_t>(nl, 1) * sizeof(double));
+  m->md_flags.ensure(kNumFlags * sizeof(int32_t));
+  if (dev) {
+    m->bak_pos.ensure(std::max<int64_t>(nt, 1) * 3 * sizeof(double));
+    m->bak_vel.ensure(std::max<int64_t>(nl, 1) * 3 * sizeof(double));
+    m->bak_f.ensure(std::max<int64_t>(nt, 1) * 3 * sizeof(double));
+  }
+  int32_t* flags = ptr<int32_t>(m->md_flags);
   const bool was_timing = m->timing;
   m->timing = false;
+  m->last_run_rebuilds = 0;
   if (init_forces) {
     energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
     if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
   }
-  HIP_OK(launch_fill_i32(ptr<int32_t>(m->md_counter), 0, 1, s));
-  if (use_graph && n_steps > 0) {
+  HIP_OK(launch_set_thermo(ptr<ThermoTarget>(m->md_counter), thermo, n_steps, s));
+  HIP_OK(launch_fill_i32(flags, 0, kNumFlags, s));
+  if (use_graph && dev && n_steps > 0) {
+    // one step, neighbour rebuild included, captured once per list layout and
+    // state arrays and replayed n_steps times (the step count and the thermo
+    // rows are read from device memory, so they do not enter the key)
+    uint64_t dt_bits;
+    std::memcpy(&dt_bits, &dt, sizeof(dt_bits));
     const std::vector<uintptr_t> key{(uintptr_t)pos, (uintptr_t)vel, (uintptr_t)forces, (uintptr_t)masses,
-                                     (uintptr_t)species, (uintptr_t)thermo, (uintptr_t)m->nbr_version,
-                                     (uintptr_t)n_steps, (uintptr_t)(dt * 1e9)};
+                                     (uintptr_t)species, (uintptr_t)m->nbr_version, (uintptr_t)dt_bits,
+                                     (uintptr_t)m->md_flags.p, (uintptr_t)m->md_counter.p,
+                                     (uintptr_t)m->bak_pos.p, (uintptr_t)m->bak_vel.p, (uintptr_t)m->bak_f.p,
+                                     (uintptr_t)m->md_part.p, (uintptr_t)m->md_atom_e.p};
     if (!m->md_stream) HIP_OK(hipStreamCreateWithFlags(&m->md_stream, hipStreamNonBlocking));
     if (!m->md_ev[0]) {
       HIP_OK(hipEventCreateWithFlags(&m->md_ev[0], hipEventDisableTiming));
@@ -1276,7 +1417,7 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
       release_graph(m);
       HIP_OK(hipStreamBeginCapture(m->md_stream, hipStreamCaptureModeRelaxed));
       try {
-        md_step(m, dt, masses, pos, vel, forces, species, thermo, n_steps, m->md_stream);
+        md_step(m, dt, masses, pos, vel, forces, species, true, m->md_stream);
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(m->md_stream, &g);
@@ -1287,14 +1428,57 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
       HIP_OK(hipStreamEndCapture(m->md_stream, &m->md_graph));
       HIP_OK(hipGraphInstantiate(&m->md_exec, m->md_graph, nullptr, nullptr, 0));
       m->md_key = key;
+      m->graph_captures++;
     }
     for (int k = 0; k < n_steps; ++k) HIP_OK(hipGraphLaunch(m->md_exec, m->md_stream));
     HIP_OK(hipEventRecord(m->md_ev[1], m->md_stream));
     HIP_OK(hipStreamWaitEvent(s, m->md_ev[1], 0));
   } else {
-    for (int k = 0; k < n_steps; ++k) md_step(m, dt, masses, pos, vel, forces, species, thermo, n_steps, s);
+    for (int k = 0; k < n_steps; ++k) md_step(m, dt, masses, pos, vel, forces, species, dev, s);
   }
   m->timing = was_timing;
+  int32_t done = n_steps;
+  if (dev) {
+    int32_t hf[kNumFlags];
+    HIP_OK(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (!hf[kFlagHalt] && n_steps > 0) {
+      // the host's view of the list (edge count, the single chunk's row
+      // pointers) follows the device-side rebuilds
+      m->h_row_ptr.resize(nl + 1);
+      HIP_OK(hipMemcpyAsync(m->h_row_ptr.data(), m->row_ptr.p, (nl + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      if (nl > 0)
+        HIP_OK(hipMemcpyAsync(m->chunk_rp.p, m->row_ptr.p, (nl + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipStreamSynchronize(s));
+      m->E = m->h_row_ptr[nl];
+    }
+    m->last_run_rebuilds = hf[kFlagBuilds];
+    if (hf[kFlagHalt]) {
+      // a rebuild needed more edges than the capacity: back to the state at
+      // the start of that step, a larger capacity, and a list built there
+      done = hf[kFlagSteps];
+      HIP_OK(launch_copy_f64_flag(pos, ptr<double>(m->bak_pos), nt * 3, flags, kFlagHalt, 1, s));
+      HIP_OK(launch_copy_f64_flag(vel, ptr<double>(m->bak_vel), nl * 3, flags, kFlagHalt, 1, s));
+      HIP_OK(launch_copy_f64_flag(forces, ptr<double>(m->bak_f), nt * 3, flags, kFlagHalt, 1, s));
+      const int64_t need = hf[kFlagNeed];
+      m->need_edges = std::max(m->need_edges, need);
+      m->cap = std::max<int64_t>(m->cap, need + (need + 19) / 20);
+      host_rebuild(m, pos, species, s);
+      (void)take_status(m, s);   // the discarded steps' records
+      // the next step rebuilds the list at its drifted positions, as the
+      // overflowing step did, so that a resumed run follows the same lists
+      if (nl > 0) {
+        const std::vector<double> far(nl * 3, 1e30);
+        HIP_OK(hipMemcpyAsync(m->pos_ref.p, far.data(), nl * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+      }
+      if (steps_done) *steps_done = done;
+      throw Fail{ALLEGRO_E_CAPACITY, "a neighbour rebuild needed " + std::to_string(need) +
+                                         " edges, more than the capacity; regrown to " + std::to_string(m->cap) +
+                                         " after " + std::to_string(done) + " steps"};
+    }
+  }
+  if (steps_done) *steps_done = done;
   if (max_disp) {
     int nb = 0;
     HIP_OK(launch_max_disp(nl, pos, ptr<double>(m->pos_ref), ptr<double>(m->md_part), &nb, s));
@@ -1434,11 +1618,11 @@ int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const 
 
 int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos, double* vel,
                    double* forces, const int32_t* species, double* thermo, int32_t init_forces, int32_t use_graph,
-                   void* stream, double* max_disp) {
+                   void* stream, double* max_disp, int32_t* steps_done) {
   if (!m) return ALLEGRO_E_INVAL;
   try {
     md_run_impl(m, n_steps, dt_fs, masses, pos, vel, forces, species, thermo, init_forces, use_graph,
-                (hipStream_t)stream, max_disp);
+                (hipStream_t)stream, max_disp, steps_done);
     return ALLEGRO_OK;
   } catch (const Fail& f) {
     return fail(m, f);
@@ -1447,6 +1631,16 @@ int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double*
   }
 }
 
+
+int allegro_md_stats(const AllegroModel* m, int64_t* graph_captures, int64_t* edge_capacity, int32_t* device_rebuild,
+                     int64_t* last_run_rebuilds) {
+  if (!m) return ALLEGRO_E_INVAL;
+  if (last_run_rebuilds) *last_run_rebuilds = m->last_run_rebuilds;
+  if (graph_captures) *graph_captures = m->graph_captures;
+  if (edge_capacity) *edge_capacity = m->cap;
+  if (device_rebuild) *device_rebuild = m->dev_rebuild ? 1 : 0;
+  return ALLEGRO_OK;
+}
 
 int allegro_describe(const AllegroConfig* cfg, AllegroInfo* info) {
   try {
@@ -1620,7 +1814,7 @@ int allegro_energy_forces_noalloc(AllegroModel* m, const double* pos, const int3
     HIP_OK(hipGetDevice(&dev));
     REQUIRE(dev == m->device, "the current device is not the model's device");
     const bool zbl = !m->znum.empty(), tall = m->prec != ALLEGRO_PREC_FP32, rr = m->rr_cfg != 0;
-    const size_t need = ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, rr, 0, nullptr);
+    const size_t need = ws_layout(m->v, m->Ec, m->Nc, m->cap, m->n_local, m->n_total, zbl, tall, rr, 0, nullptr);
     REQUIRE(need <= (size_t)ALLEGRO_NOALLOC_SCRATCH_BYTES,
             "the neighbour list needs " + std::to_string(need) + " bytes of workspace, the static workspace holds " +
                 std::to_string((size_t)ALLEGRO_NOALLOC_SCRATCH_BYTES) +
@@ -1628,7 +1822,7 @@ int allegro_energy_forces_noalloc(AllegroModel* m, const double* pos, const int3
     void* base = g_scratch_ptr[dev];
     if (!base) throw Fail{ALLEGRO_E_STATE, "static workspace address not resolved on this device"};
     Ws w;
-    ws_layout(m->v, m->Ec, m->Nc, m->E, m->n_local, m->n_total, zbl, tall, rr, (uintptr_t)base, &w);
+    ws_layout(m->v, m->Ec, m->Nc, m->cap, m->n_local, m->n_total, zbl, tall, rr, (uintptr_t)base, &w);
     // no per-kernel timing here: recording it creates events
     const bool timing = m->timing;
     m->timing = false;

@@ -92,6 +92,7 @@ __device__ __forceinline__ void edge_vector(const EdgeArgs& a, int64_t e, double
 }
 
 __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
+  clamp_live_edges(a);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= a.E) return;
   double r[3];
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
+  clamp_live_edges(a);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= a.E) return;
   const float* o = a.eb + e * kEB;

@@ -39,6 +39,25 @@ __host__ __device__ constexpr int gy_width(int l_max) { return l_max >= 3 ? 16 :
 // Bits of the model's sticky device status word: set by kernels, read and
 // cleared by the host at its next check.
 constexpr int kStatusNonFinite = 1;   // a force or atom energy was not finite
+constexpr int kStatusCapacity = 2;    // an in-graph neighbour rebuild exceeded the edge capacity
+
+// Slots of the MD flag array (int32) of the in-graph neighbour rebuild.
+constexpr int kFlagRebuild = 0;   // this step rebuilds the list
+constexpr int kFlagHalt = 1;      // a rebuild overflowed: later steps are discarded
+constexpr int kFlagSteps = 2;     // steps completed before a halt
+constexpr int kFlagNeed = 3;      // edges the overflowing rebuild needed
+constexpr int kFlagBuilds = 4;    // completed steps that rebuilt the list
+constexpr int kNumFlags = 5;
+
+// Edge-wise kernels launched over a capacity take the live edge count from
+// the device (E_dev, the last row pointer of the list) when it is set.
+template <class A>
+__device__ __forceinline__ void clamp_live_edges(A& a) {
+  if (a.E_dev) {
+    const int e = *a.E_dev;
+    if (e < a.E) a.E = e;
+  }
+}
 
 constexpr int kMaxLayers = 4;
 constexpr int kTpwArgs = 83;  // fused-table non-zeros passed by value (larger tables are read from memory)
@@ -87,6 +106,7 @@ struct VSrc {
 
 struct MlpArgs {
   int E = 0;                  // rows of this launch
+  const int32_t* E_dev = nullptr;  // live rows on the device (launch over E = a capacity), or null
   int kind = 0;
   int tm = 0;                 // edge-tile rows (0 = largest that fits LDS)
   int d = 0, n = 0, l_max = 0, n_species = 0, n_bessel = 0;
@@ -134,6 +154,7 @@ struct MlpArgs {
 
 struct EdgeArgs {
   int64_t E = 0;
+  const int32_t* E_dev = nullptr;  // live edges on the device (launch over E = a capacity), or null
   const double* pos = nullptr;
   const int32_t* ei = nullptr;    // global centre index
   const int32_t* ej = nullptr;
@@ -156,6 +177,7 @@ struct EdgeArgs {
 
 struct TensorArgs {
   int E = 0;                      // edges of the chunk
+  const int32_t* E_dev = nullptr; // live edges on the device (launch over E = a capacity), or null
   int tile = 0;                   // edges per tile of the edge-tile kernels (16 or 32; 0 = 32)
   int n_centres = 0;
   int n = 0, l_max = 0;
@@ -279,6 +301,9 @@ struct NbrArgs {
   // offset added to its coordinates for binning only
   const int32_t* sys = nullptr;
   const double* sys_shift = nullptr;  // [n_systems][3]
+  // in-graph rebuild: the kernels run only when *pred != 0 (null: always);
+  // the edge count comes from row_ptr[n_local]
+  const int32_t* pred = nullptr;
 };
 hipError_t launch_bbox(const NbrArgs& a, int* n_blocks, hipStream_t s);
 hipError_t launch_system_bbox(const double* pos, const int64_t* offsets, int n_sys, double* out, hipStream_t s);
@@ -287,7 +312,8 @@ hipError_t launch_system_sums(const double* atom_value, const int64_t* offsets, 
 hipError_t launch_bin_atoms_err(const NbrArgs& a, int* err, hipStream_t s);
 hipError_t launch_fill_cells(const NbrArgs& a, hipStream_t s);
 hipError_t launch_count_neighbors(const NbrArgs& a, hipStream_t s);
-hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t s);
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t s,
+                                 const int32_t* pred = nullptr);
 size_t exclusive_scan_tmp_bytes(int64_t n);
 hipError_t launch_fill_neighbors(const NbrArgs& a, hipStream_t s);
 hipError_t launch_sort_neighbors(const NbrArgs& a, hipStream_t s);
@@ -301,8 +327,22 @@ hipError_t launch_kick(int64_t n, double dt, const double* m, double* v, const d
 hipError_t launch_ghost_refresh(int64_t n_ghost, int64_t n_local, const int32_t* owner, const double* offset,
                                 double* x, hipStream_t s);
 hipError_t launch_fold(int64_t n_local, const int32_t* gptr, const int32_t* gidx, double* f, hipStream_t s);
+// Where MD steps write their energies: rows [cap][2], the next row `counter`.
+struct ThermoTarget {
+  double* rows;
+  int64_t cap;
+  int64_t counter;
+};
 hipError_t launch_thermo(int64_t n, const double* m, const double* v, double* part, const double* epot,
-                         double* thermo, int* counter, int cap, hipStream_t s);
+                         ThermoTarget* target, hipStream_t s);
+hipError_t launch_set_thermo(ThermoTarget* target, double* rows, int64_t cap, hipStream_t s);
+hipError_t launch_disp_check(int64_t n, const double* x, const double* x0, double r2, int32_t* flags,
+                             hipStream_t s);
+hipError_t launch_copy_f64_flag(double* dst, const double* src, int64_t n, const int32_t* flags, int slot, int want,
+                                hipStream_t s);
+hipError_t launch_capacity_check(int32_t* row_ptr, int64_t n_local, int64_t cap, int32_t* flags, int* status,
+                                 hipStream_t s);
+hipError_t launch_step_done(int32_t* flags, hipStream_t s);
 hipError_t launch_max_disp(int64_t n, const double* x, const double* x0, double* part, int* n_blocks,
                            hipStream_t s);
 

@@ -503,6 +503,8 @@ constexpr int kWavesPerEu = TM * (PREC ? 1 : 2) <= 32 ? 4 : 1;
 template <int PREC, int KIND, int TM, int MAXCT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PREC, TM>, 8)))
 void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
+  clamp_live_edges(a);
+  if ((int)blockIdx.x * TM >= a.E) return;   // tiles beyond the live edges (capacity launches)
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -633,6 +635,8 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 template <int PREC, int KIND, int TM, int MAXCT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PREC, TM>, 8)))
 void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
+  clamp_live_edges(a);
+  if ((int)blockIdx.x * TM >= a.E) return;   // tiles beyond the live edges (capacity launches)
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -830,6 +834,8 @@ __device__ __forceinline__ size_t zslot(int l, int wave, int q, int rt, int lane
 
 template <int PREC, int KIND, int MAXCT>
 __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
+  clamp_live_edges(a);
+  if ((int)blockIdx.x * kTallRows >= a.E) return;   // tiles beyond the live edges (capacity launches)
   using T = typename PT<PREC>::T;
   constexpr int TM = kTallRows, RT = 8;
   extern __shared__ __align__(16) char smem[];
@@ -935,6 +941,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
 
 template <int PREC, int KIND, int MAXCT>
 __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, int) {
+  clamp_live_edges(a);
+  if ((int)blockIdx.x * kTallRows >= a.E) return;   // tiles beyond the live edges (capacity launches)
   using T = typename PT<PREC>::T;
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   constexpr int TM = kTallRows, RT = 8;

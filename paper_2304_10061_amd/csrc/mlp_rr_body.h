@@ -373,6 +373,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOc
 void k_rr_fwd(MlpArgs a) {
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = kin_steps<KIND, D, NT>();
+  clamp_live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int e0 = (blockIdx.x * kWaves + wave) * kEdgesPerWave;
@@ -447,6 +448,7 @@ void k_rr_fwd_final(MlpArgs a) {
   static_assert(NL >= 2, "folded final layer needs a hidden layer");
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = (D + NT) / 16;
+  clamp_live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int e0 = (blockIdx.x * kWaves + wave) * kEdgesPerWave;
@@ -596,6 +598,7 @@ void k_rr_bwd(MlpArgs a) {
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = kin_steps<KIND, D, NT>();
   constexpr int KH = HN / 16, NCH = (KH + kHeadChunk - 1) / kHeadChunk;
+  clamp_live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = blockIdx.x * kWaves + wave;
@@ -712,6 +715,7 @@ void k_rr_bwd_final(MlpArgs a) {
   static_assert(NL >= 2, "folded final layer needs a hidden layer");
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = (D + NT) / 16;
+  clamp_live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = blockIdx.x * kWaves + wave;

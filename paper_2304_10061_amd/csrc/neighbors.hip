@@ -63,7 +63,7 @@ __global__ void k_bbox(const double* __restrict__ pos, int64_t n, double* __rest
 // Cell index and periodic image of every atom; counts atoms per cell.
 __global__ void k_bin(NbrArgs a, int* __restrict__ err) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= a.n_total) return;
+  if (t >= a.n_total || (a.pred && !*a.pred)) return;
   int c[3];
   const int st = a.sys ? a.sys[t] : 0;
   for (int ax = 0; ax < 3; ++ax) {
@@ -94,7 +94,7 @@ __global__ void k_bin(NbrArgs a, int* __restrict__ err) {
 
 __global__ void k_fill_cells(NbrArgs a) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= a.n_total) return;
+  if (t >= a.n_total || (a.pred && !*a.pred)) return;
   const int cell = a.cell_of[t];
   const int slot = atomicAdd(&a.cell_cursor[cell], 1);
   a.cell_atoms[a.cell_start[cell] + slot] = (int32_t)t;
@@ -106,7 +106,7 @@ template <bool WRITE>
 __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
   const int lane = lane_id();
   const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.n_local) return;
+  if (i >= a.n_local || (a.pred && !*a.pred)) return;
   const double xi = a.pos[3 * i], yi = a.pos[3 * i + 1], zi = a.pos[3 * i + 2];
   // row of the centre's species in the ordered-pair radius table (species
   // are clamped: this pass may run before the host has seen their check)
@@ -120,6 +120,9 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
   const int nst = w[0] * w[1] * w[2];
   int hits = 0;
   int64_t out = WRITE ? a.row_ptr[i] : 0;
+  // end of the centre's segment: a list clamped to its edge capacity may hold
+  // fewer slots than candidates (its results are then discarded)
+  const int64_t seg_end = WRITE ? a.row_ptr[i + 1] : 0;
   for (int sb = 0; sb < nst; sb += kWave) {
     const int sidx = sb + lane;
     int cnt = 0, start = 0, k0 = 0, k1 = 0, k2 = 0;
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
         const unsigned long long mask = __ballot(hit);
         if (hit) {
           const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-          a.keys[out + rank] = pack_key(j, sx, sy, sz);
+          if (out + rank < seg_end) a.keys[out + rank] = pack_key(j, sx, sy, sz);
         }
         out += __popcll(mask);
       } else {
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void k_scan_stencil(NbrArgs a) {
 __global__ __launch_bounds__(256) void k_sort_segments(NbrArgs a) {
   const int lane = lane_id();
   const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.n_local) return;
+  if (i >= a.n_local || (a.pred && !*a.pred)) return;
   const int b = a.row_ptr[i], e = a.row_ptr[i + 1];
   for (int p = b + lane; p < e; p += kWave) {
     const unsigned long long kp = a.keys[p];
@@ -213,14 +216,22 @@ __global__ __launch_bounds__(256) void k_sort_segments(NbrArgs a) {
   }
 }
 
-__global__ void k_rcount(const int32_t* __restrict__ ej, int64_t E, int32_t* __restrict__ rcount) {
+// E: edges (or the capacity, with the live count in *e_dev); pred: run only
+// when *pred != 0 (null: always).
+__global__ void k_rcount(const int32_t* __restrict__ ej, int64_t E, const int32_t* __restrict__ e_dev,
+                         const int32_t* __restrict__ pred, int32_t* __restrict__ rcount) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (pred && !*pred) return;
+  if (e_dev && *e_dev < E) E = *e_dev;
   if (e < E) atomicAdd(&rcount[ej[e]], 1);
 }
 
-__global__ void k_rfill(const int32_t* __restrict__ ej, int64_t E, const int32_t* __restrict__ rrow,
+__global__ void k_rfill(const int32_t* __restrict__ ej, int64_t E, const int32_t* __restrict__ e_dev,
+                        const int32_t* __restrict__ pred, const int32_t* __restrict__ rrow,
                         int32_t* __restrict__ rcursor, int32_t* __restrict__ unsorted) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (pred && !*pred) return;
+  if (e_dev && *e_dev < E) E = *e_dev;
   if (e >= E) return;
   const int j = ej[e];
   const int slot = atomicAdd(&rcursor[j], 1);
@@ -229,10 +240,10 @@ __global__ void k_rfill(const int32_t* __restrict__ ej, int64_t E, const int32_t
 
 __global__ __launch_bounds__(256) void k_rsort(const int32_t* __restrict__ rrow, int64_t n,
                                                const int32_t* __restrict__ unsorted,
-                                               int32_t* __restrict__ redge) {
+                                               int32_t* __restrict__ redge, const int32_t* __restrict__ pred) {
   const int lane = lane_id();
   const int64_t a = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (a >= n) return;
+  if (a >= n || (pred && !*pred)) return;
   const int b = rrow[a], e = rrow[a + 1];
   for (int p = b + lane; p < e; p += kWave) {
     const int v = unsorted[p];
@@ -250,10 +261,14 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
 // Exclusive scan, three passes over blocks of 1024 values.
 constexpr int kScanBlock = 1024;
 
+// pred (every kernel of the scan): run only when *pred != 0 (null: always);
+// one value for the whole grid, so the early exits are block-uniform.
 __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__ in, int64_t n,
                                                      int32_t* __restrict__ out,
-                                                     int32_t* __restrict__ block_sum) {
+                                                     int32_t* __restrict__ block_sum,
+                                                     const int32_t* __restrict__ pred) {
   __shared__ int wsum[16];
+  if (pred && !*pred) return;
   const int64_t t = blockIdx.x * (int64_t)kScanBlock + threadIdx.x;
   const int v = t < n ? in[t] : 0;
   const int incl = wave_incl_scan(v);
@@ -267,9 +282,11 @@ __global__ __launch_bounds__(1024) void k_scan_local(const int32_t* __restrict__
 }
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ block_sum, int nb,
-                                                      int32_t* __restrict__ total_out) {
+                                                      int32_t* __restrict__ total_out,
+                                                      const int32_t* __restrict__ pred) {
   __shared__ int wsum[16];
   __shared__ int carry;
+  if (pred && !*pred) return;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int base = 0; base < nb; base += kScanBlock) {
@@ -289,7 +306,9 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ bloc
   if (threadIdx.x == 0) *total_out = carry;
 }
 
-__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ block_sum) {
+__global__ void k_scan_add(int32_t* __restrict__ out, int64_t n, const int32_t* __restrict__ block_sum,
+                           const int32_t* __restrict__ pred) {
+  if (pred && !*pred) return;
   const int64_t t = blockIdx.x * (int64_t)kScanBlock + threadIdx.x;
   if (t < n) out[t] += block_sum[blockIdx.x];
 }
@@ -371,13 +390,14 @@ size_t exclusive_scan_tmp_bytes(int64_t n) {
 }
 
 // out[0..n] = exclusive prefix sums of in[0..n), out[n] = total.
-hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t s) {
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, void* tmp, hipStream_t s,
+                                 const int32_t* pred) {
   if (n <= 0) return launch_fill_i32(out, 0, 1, s);
   const int nb = (int)grid_for(n, kScanBlock);
   int32_t* bs = (int32_t*)tmp;
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, in, n, out, bs);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, bs, nb, out + n);
-  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, out, n, (const int32_t*)bs);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, in, n, out, bs, pred);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, bs, nb, out + n, pred);
+  hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, out, n, (const int32_t*)bs, pred);
   return hipGetLastError();
 }
 
@@ -411,17 +431,20 @@ hipError_t launch_sort_neighbors(const NbrArgs& a, hipStream_t s) {
 
 // Reverse CSR: rcount/rcursor must be zeroed by the caller; `a.keys` is reused
 // as scratch for the unsorted edge ids (E int32 fit in E uint64).
+// With a.pred set (in-graph rebuild) E is the edge capacity and the live
+// count is row_ptr[n_local].
 hipError_t launch_reverse_csr(const NbrArgs& a, int64_t E, hipStream_t s) {
+  const int32_t* e_dev = a.pred ? a.row_ptr + a.n_local : nullptr;
   if (E > 0)
-    hipLaunchKernelGGL(k_rcount, dim3(grid_for(E, 256)), dim3(256), 0, s, a.ej, E, a.rcount);
-  hipError_t st = launch_exclusive_scan(a.rcount, a.rrow_ptr, a.n_total, a.scan_tmp, s);
+    hipLaunchKernelGGL(k_rcount, dim3(grid_for(E, 256)), dim3(256), 0, s, a.ej, E, e_dev, a.pred, a.rcount);
+  hipError_t st = launch_exclusive_scan(a.rcount, a.rrow_ptr, a.n_total, a.scan_tmp, s, a.pred);
   if (st != hipSuccess) return st;
   if (E <= 0) return hipGetLastError();
   int32_t* unsorted = (int32_t*)a.keys;
-  hipLaunchKernelGGL(k_rfill, dim3(grid_for(E, 256)), dim3(256), 0, s, a.ej, E,
+  hipLaunchKernelGGL(k_rfill, dim3(grid_for(E, 256)), dim3(256), 0, s, a.ej, E, e_dev, a.pred,
                      (const int32_t*)a.rrow_ptr, a.rcursor, unsorted);
   hipLaunchKernelGGL(k_rsort, dim3(grid_for(a.n_total, 4)), dim3(256), 0, s,
-                     (const int32_t*)a.rrow_ptr, a.n_total, (const int32_t*)unsorted, a.redge);
+                     (const int32_t*)a.rrow_ptr, a.n_total, (const int32_t*)unsorted, a.redge, a.pred);
   return hipGetLastError();
 }
 

@@ -254,6 +254,7 @@ constexpr bool kHoldMix = Pat::In == kNatural && Pat::Out == kNatural && Pat::Lm
 // fragments loaded once.
 template <class Pat, int TT>
 __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp, int Np) {
+  clamp_live_edges(a);
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
   constexpr bool HOLD = kHoldMix<Pat>;
   extern __shared__ __align__(16) float S[];   // [DOUT][TT][lds_ld]
@@ -315,6 +316,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
 // L+1's table.
 template <class PatN, int TT>
 __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, int Kp, int Np) {
+  clamp_live_edges(a);
   constexpr int LMAX = PatN::Lmax, DIM = PatN::DIM, DW = PatN::DIN, DN = PatN::DOUT;
   constexpr bool NEXT_FINAL = PatN::Out == kScalarOut;
   constexpr bool HOLD = NEXT_FINAL && PatN::In == kNatural && LMAX <= 2;
@@ -463,6 +465,7 @@ constexpr int kEdgesPerWave = 32;
 // A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a].
 template <class Pat, int G, bool A0>
 __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
+  clamp_live_edges(a);
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
   constexpr int GYW = gy_width(LMAX);
   constexpr int n = kWave / G;
