@@ -42,13 +42,19 @@ TRAFFIC_SUMMARY_DEEP = os.path.join(ROOT, "profiles", "hbm_traffic_deep_water_bo
 
 MLP_WAVES = 8                 # waves per MLP block
 TALL_ROWS = 128               # tile rows of the in-place (tall) MLP kernels
+RR_TILE = 256                 # tile code of the register-resident MLP kernels
+SIMDS = 1024                  # 256 CUs x 4 SIMDs
+CLOCK_GHZ = 2.4               # peak engine clock (the clock of the MFMA peak)
 
 
 def mlp_symbol(launch, precision, tile_rows, latent):
     """'mlp_bwd_final', 1, 32, 256 -> 'k_mlp_bwd<1, 2, 32, 2>' (the kernel's name
     without namespace and arguments; the last argument is the column tiles per
-    wave, ceil(d / (16 * MLP_WAVES))); 128-row tiles -> 'k_mlp_bwd_t<1, 2, 2>'."""
+    wave, ceil(d / (16 * MLP_WAVES))); 128-row tiles -> 'k_mlp_bwd_t<1, 2, 2>';
+    register-resident kernels -> 'k_rr_bwd_final<' / 'k_rr_fwd<1, ' (prefixes)."""
     _, fb, kind = launch.split("_", 2)
+    if tile_rows == RR_TILE:
+        return f"k_rr_{fb}_final<" if kind == "final" else f"k_rr_{fb}<{MLP_KIND[kind]}, "
     ct = -(-(-(-latent // 16)) // MLP_WAVES)
     if tile_rows == TALL_ROWS:
         return f"k_mlp_{fb}_t<{precision}, {MLP_KIND[kind]}, {ct}>"
@@ -66,10 +72,15 @@ def calibration_copy(mib):
     torch.cuda.synchronize()
 
 
-def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, commands):
+def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, commands, mfma_dir=None):
     """Markdown summary of a --kernel-trace --stats run and two --pmc runs
     (FETCH_SIZE, WRITE_SIZE): per-kernel average duration and counter values
-    per dispatch, the copy-kernel scale factors, and the source hash."""
+    per dispatch, the copy-kernel scale factors, and the source hash.  With
+    `mfma_dir` (a --pmc run of SQ_VALU_MFMA_BUSY_CYCLES and
+    SQ_INSTS_VALU_MFMA_MOPS_BF16), also each kernel's matrix-core busy
+    fraction, busy cycles / (1024 SIMDs x duration x 2.4 GHz) with the busy
+    cycles summed over the SIMDs, and its executed BF16 MFMA rate (MOPS x 512
+    flops / duration)."""
     import csv
     import glob
 
@@ -93,6 +104,8 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, com
         return per
 
     fetch, write = counters(fetch_dir, "FETCH_SIZE"), counters(write_dir, "WRITE_SIZE")
+    busy = counters(mfma_dir, "SQ_VALU_MFMA_BUSY_CYCLES") if mfma_dir else {}
+    mops = counters(mfma_dir, "SQ_INSTS_VALU_MFMA_MOPS_BF16") if mfma_dir else {}
     copy_kib = float(copy_mib) * 1024
     cf = max((v for k, vs in fetch.items() if "copyBuffer" in k for v in vs), default=None)
     cw = max((v for k, vs in write.items() if "copyBuffer" in k for v in vs), default=None)
@@ -113,17 +126,23 @@ def summarize_profiles(stats_dir, fetch_dir, write_dir, bench_log, copy_mib, com
     lines = [f"# rocprofv3 summary: {title}", ""]
     for c in commands:
         lines.append(f"    {c}")
-    lines += ["", "| kernel | calls | avg us | total ms | FETCH KiB/dispatch | WRITE KiB/dispatch |",
-              "|---|---|---|---|---|---|"]
+    lines += ["", "| kernel | calls | avg us | total ms | FETCH KiB/dispatch | WRITE KiB/dispatch |"
+              " MFMA busy | BF16 MFMA TFLOP/s |",
+              "|---|---|---|---|---|---|---|---|"]
+    mean = lambda v: sum(v) / len(v) if v else None
     for name, (calls, avg, tot) in sorted(stats.items(), key=lambda kv: -kv[1][2])[:28]:
-        fv, wv = fetch.get(name), write.get(name)
-        fa = sum(fv) / len(fv) if fv else None
-        wa = sum(wv) / len(wv) if wv else None
+        fa, wa = mean(fetch.get(name)), mean(write.get(name))
+        ba, ma = mean(busy.get(name)), mean(mops.get(name))
+        bfrac = ba / (SIMDS * avg * 1e-6 * CLOCK_GHZ * 1e9) if ba is not None else None
+        tfl = ma * 512 / (avg * 1e-6) / 1e12 if ma is not None else None
         short = name.replace("allegro::", "").replace("(anonymous namespace)::", "")[:90]
         lines.append(f"| `{short}` | {calls} | {avg:.1f} | {tot:.3f} | "
-                     f"{'' if fa is None else f'{fa:.0f}'} | {'' if wa is None else f'{wa:.0f}'} |")
+                     f"{'' if fa is None else f'{fa:.0f}'} | {'' if wa is None else f'{wa:.0f}'} | "
+                     f"{'' if bfrac is None or not ba else f'{bfrac:.3f}'} | {'' if not ma else f'{tfl:.0f}'} |")
         if fa is not None and wa is not None:
             blob["kernels"][short] = {"avg_us": avg, "fetch_KiB": fa, "write_KiB": wa}
+            if ba is not None:
+                blob["kernels"][short].update({"mfma_busy_cycles": ba, "mfma_mops_bf16": ma})
     if copy_mib:
         lines += ["", "Counter scale factors from the plain copy of %d MiB (bytes per counted byte):" % copy_mib]
     else:
@@ -143,6 +162,39 @@ def kernel_source_hash():
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _summary_kernels(summary):
+    try:
+        txt = open(summary).read()
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_hash") != kernel_source_hash():
+        return None
+    return blob.get("kernels", {})
+
+
+def mfma_busy_counters(symbols, summary=None):
+    """Counter-derived matrix-core figures of the kernels whose names contain
+    one of `symbols`, from the committed summary (None when it lacks them or
+    the sources changed): busy fraction over their summed durations and
+    executed BF16 MFMA TFLOP/s."""
+    ks = _summary_kernels(summary or TRAFFIC_SUMMARY)
+    if not ks:
+        return None
+    busy = mops = us = 0.0
+    found = 0
+    for name, k in ks.items():
+        if "mfma_busy_cycles" in k and any(s in name for s in symbols):
+            busy += k["mfma_busy_cycles"]
+            mops += k["mfma_mops_bf16"] or 0.0
+            us += k["avg_us"]
+            found += 1
+    if not found or us <= 0:
+        return None
+    return {"busy_frac": busy / (SIMDS * us * 1e-6 * CLOCK_GHZ * 1e9),
+            "executed_bf16_tflops": mops * 512 / (us * 1e-6) / 1e12, "kernels": found}
 
 
 def traffic_per_launch(symbol, summary=None):
@@ -187,9 +239,11 @@ def mlp_macs_per_edge(mc):
 
 
 def mlp_bytes_per_edge(mc):
-    """Algorithmic HBM bytes per edge of each MLP kernel kind: every input
-    row read once and every output row written once (FP32 arrays; per-centre
-    and per-species rows, which stay in cache, are not counted)."""
+    """HBM bytes per edge that each MLP kernel kind of this design stages:
+    every input row read once and every output row written once (FP32
+    arrays; per-centre and per-species rows, which stay in cache, are not
+    counted).  These are the staged design's own I/O, not the method's
+    minimum traffic."""
     d, n, LW, f = mc.latent, mc.n_tensor, (mc.l_max + 1) * mc.n_tensor, 4
     dim = (mc.l_max + 1) ** 2
     edge_in = f * (mc.n_bessel + 3)                 # radial basis, u and the species pair of the edge record
@@ -525,9 +579,11 @@ def main():
     ap.add_argument("--summarize", nargs=4, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR", "BENCH_LOG"),
                     help="print the markdown summary of rocprofv3 outputs (and the profiled run's output) and exit")
     ap.add_argument("--command", action="append", default=[], help="profiling command (for --summarize)")
+    ap.add_argument("--summarize-mfma", default=None, metavar="MFMA_DIR",
+                    help="--pmc run of SQ_VALU_MFMA_BUSY_CYCLES and SQ_INSTS_VALU_MFMA_MOPS_BF16 (for --summarize)")
     args = ap.parse_args()
     if args.summarize:
-        print(summarize_profiles(*args.summarize, args.calibration_copy_mib, args.command))
+        print(summarize_profiles(*args.summarize, args.calibration_copy_mib, args.command, args.summarize_mfma))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the energy/force path runs on a single MI355X "
@@ -572,13 +628,15 @@ def main():
         sym = mlp_symbol(dom, 1, (bf["tiles"] or {}).get(dom, 0), mc.latent)
         launches = max(1, bf["kernel_launches"].get(dom, 1))
         avg_ms = kms[dom] / launches
-        alg_bytes = mlp_bytes_per_edge(mc)[dom] * bf["edges"]   # per launch (one launch per chunk)
+        io_bytes = mlp_bytes_per_edge(mc)[dom] * bf["edges"]   # per launch (one launch per chunk)
         roof = {"kernel": dom, "symbol": sym, "bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS, "traffic": traffic_per_launch(sym),
                 "flops_per_launch": flops / launches, "avg_launch_ms": avg_ms,
-                # the same launch against the HBM roof, on algorithmic bytes
-                "alg_bytes_per_launch": alg_bytes / launches,
-                "hbm_frac_alg": alg_bytes / launches / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+                # the same launch against the HBM roof, on the bytes this
+                # kernel design itself stages (its input and output rows)
+                "staged_io_bytes_per_launch": io_bytes / launches,
+                "hbm_frac_staged_io": io_bytes / launches / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                "mfma_counters": mfma_busy_counters([sym])}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
                 "frac": None, "traffic": None}
@@ -609,7 +667,12 @@ def main():
         "roofline": roof,
         "mlp_gemm": {"tflops": mlp_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms else None,
                      "mfma_frac": (mlp_flops / (mlp_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS) if mlp_ms else None,
-                     "ms": mlp_ms},
+                     "ms": mlp_ms,
+                     # matrix-core busy fraction and executed rate from the
+                     # committed counter summary (weight pairs and the
+                     # backward's recomputation included)
+                     "mfma_counters": mfma_busy_counters(
+                         [mlp_symbol(k, 1, (bf["tiles"] or {}).get(k, 0), mc.latent) for k in macs])},
         "kernel_ms": {k: round(v, 4) for k, v in sorted(kms.items(), key=lambda kv: -kv[1])},
         "neighbors_ms": bf["neighbors_ms"],
         "workspace_GB": bf["workspace_GB"],

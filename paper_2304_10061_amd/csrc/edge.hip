@@ -92,9 +92,9 @@ __device__ __forceinline__ void edge_vector(const EdgeArgs& a, int64_t e, double
 }
 
 __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= a.E) return;
+  if (e >= E) return;
   double r[3];
   edge_vector(a, e, r);
   const double dd = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
@@ -141,9 +141,9 @@ __global__ __launch_bounds__(256) void k_edge_basis(EdgeArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_edge_adjoint(EdgeArgs a) {
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= a.E) return;
+  if (e >= E) return;
   const float* o = a.eb + e * kEB;
   const float d = o[kEB_D], u = o[kEB_U];
   const float x = o[kEB_RHAT], y = o[kEB_RHAT + 1], z = o[kEB_RHAT + 2];

@@ -51,12 +51,16 @@ constexpr int kNumFlags = 5;
 
 // Edge-wise kernels launched over a capacity take the live edge count from
 // the device (E_dev, the last row pointer of the list) when it is set.
+//
+// The argument struct itself is never modified: a kernel that wrote to it
+// would get a private copy of the whole struct (scratch memory).
 template <class A>
-__device__ __forceinline__ void clamp_live_edges(A& a) {
+__device__ __forceinline__ int live_edges(const A& a) {
   if (a.E_dev) {
     const int e = *a.E_dev;
-    if (e < a.E) a.E = e;
+    return e < a.E ? e : a.E;
   }
+  return a.E;
 }
 
 constexpr int kMaxLayers = 4;

@@ -342,7 +342,7 @@ __device__ __forceinline__ float4 final_tp4(const MlpArgs& a, int e, int centre,
 // STORED: the final layer's scalars are read from s_in (backward kernels;
 // the host guarantees s_in), never recomputed.
 template <int PREC, int KIND, int TM, bool STORED = false>
-__device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp) {
+__device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, int e0, int Kp, int E) {
   using T = typename PT<PREC>::T;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   constexpr int RPW = TM / kNW;
@@ -352,8 +352,8 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
     for (int t = lane; t < RPW * (Kp >> 2); t += 64) {
       const int r = t / (Kp >> 2), q = t - r * (Kp >> 2);
       const int row = wave * RPW + r, e = e0 + row;
-      const bool ok = e < a.E;
-      const int ec = ok ? e : a.E - 1;
+      const bool ok = e < E;
+      const int ec = ok ? e : E - 1;
       const float* rec = a.eb + (uint32_t)ec * kEB;
       const int zi = (int)rec[kEB_ZI], zj = (int)rec[kEB_ZJ];
       float x[4];
@@ -373,7 +373,7 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
   if (KIND == kLatent || STORED || a.s_in != nullptr) {
     // [x_prev | s] in one gather: s is V^L[0] (latent) or, for the final
     // layer, the tensor-product scalars its forward pass stored
-    gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, (d + n) >> 2, [&](int e, int c) {
+    gather_rows<PREC, TM>(X, ldx, e0, E, 0, (d + n) >> 2, [&](int e, int c) {
       const float* p = c < d ? a.x_prev + (uint32_t)e * d + c : a.s_in + (uint32_t)e * a.s_ld + (c - d);
       return *(const float4*)p;
     });
@@ -395,9 +395,9 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
     for (int j = 0; j < NI; ++j) {
       int row, q;
       const int e = item_edge(lane + 64 * j, &row, &q);
-      cen[j] = a.ei[e < a.E ? e : a.E - 1];
+      cen[j] = a.ei[e < E ? e : E - 1];
     }
-    gather_rows<PREC, TM>(X, ldx, e0, a.E, 0, d >> 2,
+    gather_rows<PREC, TM>(X, ldx, e0, E, 0, d >> 2,
                           [&](int e, int c) { return ld4(a.x_prev, (uint32_t)e * d + c); });
     for (int t0 = 0; t0 < total; t0 += 64 * NI) {
       if (t0 > 0) {
@@ -405,7 +405,7 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
         for (int j = 0; j < NI; ++j) {
           int row, q;
           const int e = item_edge(t0 + lane + 64 * j, &row, &q);
-          cen[j] = a.ei[e < a.E ? e : a.E - 1];
+          cen[j] = a.ei[e < E ? e : E - 1];
         }
       }
       float4 v[NI];
@@ -413,7 +413,7 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
       for (int j = 0; j < NI; ++j) {
         int row, q;
         const int e = item_edge(t0 + lane + 64 * j, &row, &q);
-        v[j] = final_tp4(a, e < a.E ? e : a.E - 1, cen[j], 4 * q);
+        v[j] = final_tp4(a, e < E ? e : E - 1, cen[j], 4 * q);
       }
 #pragma unroll
       for (int j = 0; j < NI; ++j) {
@@ -422,7 +422,7 @@ __device__ void build_input(const MlpArgs& a, typename PT<PREC>::T* X, int ldx, 
         const int e = item_edge(t, &row, &q);
         if (t >= total) continue;
         float4 vv = v[j];
-        if (e >= a.E) vv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (e >= E) vv = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         else if (a.tp_out) *(float4*)(a.tp_out + (uint32_t)e * n + 4 * q) = vv;
         store4(X + row * ldx + d + 4 * q, vv);
       }
@@ -503,8 +503,8 @@ constexpr int kWavesPerEu = TM * (PREC ? 1 : 2) <= 32 ? 4 : 1;
 template <int PREC, int KIND, int TM, int MAXCT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PREC, TM>, 8)))
 void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
-  clamp_live_edges(a);
-  if ((int)blockIdx.x * TM >= a.E) return;   // tiles beyond the live edges (capacity launches)
+  const int E = live_edges(a);
+  if ((int)blockIdx.x * TM >= E) return;   // tiles beyond the live edges (capacity launches)
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -528,7 +528,7 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-      ur[rt][i] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
+      ur[rt][i] = e < E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
     }
   float xp[RT][MAXCT][4];
   auto load_xp = [&] {
@@ -541,13 +541,13 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-          e = e < a.E ? e : a.E - 1;
+          e = e < E ? e : E - 1;
           xp[rt][q][i] = a.x_prev[(uint32_t)e * d + col];
         }
     }
   };
   if constexpr (KIND != kTwoBody && kEarly) load_xp();
-  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp, E);
   __syncthreads();
   int ldin;
   const T* in = hidden_layers<PREC, TM, MAXCT>(a, X, ldx, H, ldh, nullptr, 0, &ldin, wave, lane);
@@ -580,7 +580,7 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-        const bool ok = e < a.E && col < d;
+        const bool ok = e < E && col < d;
         if (!ok) acc[rt][q][i] = 0.0f;
         if (ok && a.x_out) a.x_out[(uint32_t)e * d + col] = acc[rt][q][i];
       }
@@ -603,7 +603,7 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
     __syncthreads();
     if ((int)threadIdx.x < TM) {
       const int e = e0 + threadIdx.x;
-      if (e < a.E)
+      if (e < E)
         a.eij[e] = wave_partials_sum(red, threadIdx.x);
     }
     return;
@@ -626,7 +626,7 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-          if (e < a.E) a.head_out[(size_t)e * Nh + col] = acc[rt][q][i];
+          if (e < E) a.head_out[(size_t)e * Nh + col] = acc[rt][q][i];
         }
     }
   }
@@ -635,8 +635,8 @@ void k_mlp_fwd(MlpArgs a, int ldx, int ldh) {
 template <int PREC, int KIND, int TM, int MAXCT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<PREC, TM>, 8)))
 void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
-  clamp_live_edges(a);
-  if ((int)blockIdx.x * TM >= a.E) return;   // tiles beyond the live edges (capacity launches)
+  const int E = live_edges(a);
+  if ((int)blockIdx.x * TM >= E) return;   // tiles beyond the live edges (capacity launches)
   using P = PT<PREC>;
   using T = typename P::T;
   constexpr int RT = TM / 16;
@@ -660,7 +660,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-        e = e < a.E ? e : a.E - 1;
+        e = e < E ? e : E - 1;
         rowoff[rt][i] = (uint32_t)(KIND == kLatentFinal ? (int)a.eb[(uint32_t)e * kEB + kEB_ZI] : e) * d;
       }
 #pragma unroll
@@ -684,7 +684,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-          if (!(e < a.E && col < d)) G[rt][q][i] = 0.0f;
+          if (!(e < E && col < d)) G[rt][q][i] = 0.0f;
         }
     }
   };
@@ -692,7 +692,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   __shared__ float us[TM];
   if ((int)threadIdx.x < TM) {
     const int e = e0 + threadIdx.x;
-    us[threadIdx.x] = e < a.E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
+    us[threadIdx.x] = e < E ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
   }
   f32x4 acc[RT][MAXCT];
   bool input_ready = false;
@@ -704,8 +704,8 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
       // the whole head gradient fits the H / pre-activation region (a
       // [TM][ldg] view of it): stage it there while the chain's input rows
       // gather into X, both in one memory round trip
-      stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, H, ldg, e0, 0, nkb * 32);
-      build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
+      stage_rows<PREC, TM>(a.g_head, Kh, Kh, E, H, ldg, e0, 0, nkb * 32);
+      build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp, E);
       __syncthreads();
       gemm_tile<PREC, RT, MAXCT>(acc, H, ldg, a.head_bwd, wave, lane, 0);
       __syncthreads();   // H is rewritten by the recomputation
@@ -716,7 +716,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
       for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
         const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
         const int w = (kb1 - kb0) * 32;
-        stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, w);
+        stage_rows<PREC, TM>(a.g_head, Kh, Kh, E, X, ldx, e0, kb0 * 32, w);
         __syncthreads();
         gemm_tile<PREC, RT, MAXCT>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, kb0 == 0);
         __syncthreads();
@@ -732,7 +732,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
 
   // 2. recompute the chain, keeping hidden pre-activations
   if (!input_ready) {
-    build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
+    build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp, E);
     __syncthreads();
   }
   int ldin;
@@ -753,7 +753,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
   __syncthreads();   // also: every wave is done reading `in`
   if ((int)threadIdx.x < TM) {
     const int e = e0 + threadIdx.x;
-    if (e < a.E) {
+    if (e < E) {
       const float gu = rs * wave_partials_sum(red, threadIdx.x);
       a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
     }
@@ -799,7 +799,7 @@ void k_mlp_bwd(MlpArgs a, int ldx, int ldh) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-          if (e >= a.E) continue;
+          if (e >= E) continue;
           const float g = acc[rt][q][i];
           if constexpr (KIND == kTwoBody) {
             if (col >= 2 * S && col < 2 * S + a.n_bessel) a.g_R[(size_t)e * a.n_bessel + col - 2 * S] = g;
@@ -834,8 +834,8 @@ __device__ __forceinline__ size_t zslot(int l, int wave, int q, int rt, int lane
 
 template <int PREC, int KIND, int MAXCT>
 __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, int) {
-  clamp_live_edges(a);
-  if ((int)blockIdx.x * kTallRows >= a.E) return;   // tiles beyond the live edges (capacity launches)
+  const int E = live_edges(a);
+  if ((int)blockIdx.x * kTallRows >= E) return;   // tiles beyond the live edges (capacity launches)
   using T = typename PT<PREC>::T;
   constexpr int TM = kTallRows, RT = 8;
   extern __shared__ __align__(16) char smem[];
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
   const int e0 = blockIdx.x * TM;
   const int d = a.d, nl = a.w.nl;
 
-  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  build_input<PREC, KIND, TM>(a, X, ldx, e0, a.w.fwd[0].Kp, E);
   __syncthreads();
   f32x4 acc[RT][MAXCT];
   for (int l = 0; l + 1 < nl; ++l) {
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
-        e = e < a.E ? e : a.E - 1;
+        e = e < E ? e : E - 1;
         ur[h][i] = a.eb[(uint32_t)e * kEB + kEB_U];
         if constexpr (KIND != kTwoBody) {
 #pragma unroll
@@ -887,7 +887,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
           const int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
           float v = ur[h][i] * acc[r0 + h][q][i];
           if constexpr (KIND != kTwoBody) v = a.res_scale * (xp[h][q][i] + v);
-          const bool ok = e < a.E && col < d;
+          const bool ok = e < E && col < d;
           v = ok ? v : 0.0f;
           acc[r0 + h][q][i] = v;
           if (ok && a.x_out) a.x_out[(uint32_t)e * d + col] = v;
@@ -911,7 +911,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
     __syncthreads();
     if ((int)threadIdx.x < TM) {
       const int e = e0 + threadIdx.x;
-      if (e < a.E)
+      if (e < E)
         a.eij[e] = wave_partials_sum(red, threadIdx.x);
     }
     return;
@@ -932,7 +932,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-            if (e < a.E) a.head_out[(uint32_t)e * Nh + col] = acc[rt][q][i];
+            if (e < E) a.head_out[(uint32_t)e * Nh + col] = acc[rt][q][i];
           }
       }
     }
@@ -941,8 +941,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_fwd_t(MlpArgs a, int ldx, i
 
 template <int PREC, int KIND, int MAXCT>
 __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, int) {
-  clamp_live_edges(a);
-  if ((int)blockIdx.x * kTallRows >= a.E) return;   // tiles beyond the live edges (capacity launches)
+  const int E = live_edges(a);
+  if ((int)blockIdx.x * kTallRows >= E) return;   // tiles beyond the live edges (capacity launches)
   using T = typename PT<PREC>::T;
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   constexpr int TM = kTallRows, RT = 8;
@@ -967,7 +967,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
       const int Kh = a.head_bwd.K, nkb = a.head_bwd.Kp >> 5, chunk = ldx >> 5;
       for (int kb0 = 0; kb0 < nkb; kb0 += chunk) {
         const int kb1 = kb0 + chunk < nkb ? kb0 + chunk : nkb;
-        stage_rows<PREC, TM>(a.g_head, Kh, Kh, a.E, X, ldx, e0, kb0 * 32, (kb1 - kb0) * 32);
+        stage_rows<PREC, TM>(a.g_head, Kh, Kh, E, X, ldx, e0, kb0 * 32, (kb1 - kb0) * 32);
         __syncthreads();
         gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.head_bwd, wave, lane, 0, kb0, kb1, false);
         __syncthreads();
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
-          e = e < a.E ? e : a.E - 1;
+          e = e < E ? e : E - 1;
           const uint32_t ro = (uint32_t)(KIND == kLatentFinal ? (int)a.eb[(uint32_t)e * kEB + kEB_ZI] : e) * d;
 #pragma unroll
           for (int q = 0; q < MAXCT; ++q) {
@@ -1001,14 +1001,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
-            if (e < a.E && col < d) gst[(uint32_t)e * d + col] = gv[h][q][i] + acc[r0 + h][q][i];
+            if (e < E && col < d) gst[(uint32_t)e * d + col] = gv[h][q][i] + acc[r0 + h][q][i];
           }
         }
     }
   }
 
   // 2. recompute the chain; hidden pre-activations to the scratch array
-  build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp);
+  build_input<PREC, KIND, TM, true>(a, X, ldx, e0, a.w.fwd[0].Kp, E);
   __syncthreads();
   for (int l = 0; l + 1 < nl; ++l) {
     gemm_tile<PREC, RT, MAXCT, false>(acc, X, ldx, a.w.fwd[l], wave, lane, 0);
@@ -1035,8 +1035,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         int e = e0 + (r0 + h) * 16 + 4 * (lane >> 4) + i;
-        const bool ok = e < a.E;
-        e = ok ? e : a.E - 1;
+        const bool ok = e < E;
+        e = ok ? e : E - 1;
         ur[h][i] = ok ? a.eb[(uint32_t)e * kEB + kEB_U] : 0.0f;
 #pragma unroll
         for (int q = 0; q < MAXCT; ++q) {
@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
   __syncthreads();   // red complete; every wave is done reading X
   if ((int)threadIdx.x < TM) {
     const int e = e0 + threadIdx.x;
-    if (e < a.E) {
+    if (e < E) {
       const float gu = rs * wave_partials_sum(red, threadIdx.x);
       a.g_u[e] = a.gu_accum ? a.g_u[e] + gu : gu;
     }
@@ -1101,7 +1101,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mlp_bwd_t(MlpArgs a, int ldx, i
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int e = e0 + rt * 16 + 4 * (lane >> 4) + i;
-          if (e >= a.E) continue;
+          if (e >= E) continue;
           const float g = acc[rt][q][i];
           if constexpr (KIND == kTwoBody) {
             if (col >= 2 * S && col < 2 * S + a.n_bessel) a.g_R[(uint32_t)e * a.n_bessel + col - 2 * S] = g;

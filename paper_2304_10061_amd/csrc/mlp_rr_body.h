@@ -373,12 +373,12 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(kOc
 void k_rr_fwd(MlpArgs a) {
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = kin_steps<KIND, D, NT>();
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int e0 = (blockIdx.x * kWaves + wave) * kEdgesPerWave;
-  if (e0 >= a.E) return;
-  const Rows R = rows_of(e0, a.E, lane);
+  if (e0 >= E) return;
+  const Rows R = rows_of(e0, E, lane);
   float u[kNE];
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) u[nb] = R.ok[nb] ? a.eb[(uint32_t)R.ec[nb] * kEB + kEB_U] : 0.0f;
@@ -448,12 +448,12 @@ void k_rr_fwd_final(MlpArgs a) {
   static_assert(NL >= 2, "folded final layer needs a hidden layer");
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = (D + NT) / 16;
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int e0 = (blockIdx.x * kWaves + wave) * kEdgesPerWave;
-  if (e0 >= a.E) return;
-  const Rows R = rows_of(e0, a.E, lane);
+  if (e0 >= E) return;
+  const Rows R = rows_of(e0, E, lane);
   float xw[kNE], av[kNE];
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) { xw[nb] = 0.0f; av[nb] = 0.0f; }
@@ -598,13 +598,13 @@ void k_rr_bwd(MlpArgs a) {
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = kin_steps<KIND, D, NT>();
   constexpr int KH = HN / 16, NCH = (KH + kHeadChunk - 1) / kHeadChunk;
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = blockIdx.x * kWaves + wave;
   const int e0 = tile * kEdgesPerWave;
-  if (e0 >= a.E) return;
-  const Rows R = rows_of(e0, a.E, lane);
+  if (e0 >= E) return;
+  const Rows R = rows_of(e0, E, lane);
   const float rs = KIND == kTwoBody ? 1.0f : a.res_scale;
   float u[kNE];
 #pragma unroll
@@ -715,13 +715,13 @@ void k_rr_bwd_final(MlpArgs a) {
   static_assert(NL >= 2, "folded final layer needs a hidden layer");
   constexpr int KD = D / 16, MBD = D / 32, NBP = rr_nbp(MBD);
   constexpr int KIN = (D + NT) / 16;
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int tile = blockIdx.x * kWaves + wave;
   const int e0 = tile * kEdgesPerWave;
-  if (e0 >= a.E) return;
-  const Rows R = rows_of(e0, a.E, lane);
+  if (e0 >= E) return;
+  const Rows R = rows_of(e0, E, lane);
   const float rs = a.res_scale;
   float ce[kNE], sg[kNE], av[kNE], xw[kNE];
   int zr[kNE];

@@ -254,7 +254,7 @@ constexpr bool kHoldMix = Pat::In == kNatural && Pat::Out == kNatural && Pat::Lm
 // fragments loaded once.
 template <class Pat, int TT>
 __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp, int Np) {
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
   constexpr bool HOLD = kHoldMix<Pat>;
   extern __shared__ __align__(16) float S[];   // [DOUT][TT][lds_ld]
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
     if constexpr (HOLD) load_mix_b(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
     else mix_geometry(mb, Np);
   }
-  const int ntiles = (a.E + TT - 1) / TT;
+  const int ntiles = (E + TT - 1) / TT;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = (int64_t)tile * TT;
     // TT * Kp is a multiple of 512: two (edge, channel) items per thread per
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
         const int p = p0 + 256 * h;
         const int r = p / Kp, u = p - r * Kp;
         const int64_t e = e0 + r;
-        ok[h] = e < a.E && u < n;
+        ok[h] = e < E && u < n;
         const int64_t ee = ok[h] ? e : 0;
         const int uu = ok[h] ? u : 0;
         load_v<LMAX, DIN>(a.v, a.eb + (size_t)ee * kEB, ee, uu, n, V[h]);
@@ -301,8 +301,8 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
     __syncthreads();
     if (a.channel_mix)
       mix_tile<LMAX, DOUT, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
-                                     a.v_out, e0, a.E);
-    else copy_tile<DOUT, TT>(S, lds_ld, n, a.v_out, e0, a.E);
+                                     a.v_out, e0, E);
+    else copy_tile<DOUT, TT>(S, lds_ld, n, a.v_out, e0, E);
     __syncthreads();   // S is rewritten by the next tile
   }
 }
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
 // L+1's table.
 template <class PatN, int TT>
 __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, int Kp, int Np) {
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   constexpr int LMAX = PatN::Lmax, DIM = PatN::DIM, DW = PatN::DIN, DN = PatN::DOUT;
   constexpr bool NEXT_FINAL = PatN::Out == kScalarOut;
   constexpr bool HOLD = NEXT_FINAL && PatN::In == kNatural && LMAX <= 2;
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
     if constexpr (HOLD) load_mix_b(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
     else mix_geometry(mb, Np);
   }
-  const int ntiles = (a.E + TT - 1) / TT;
+  const int ntiles = (E + TT - 1) / TT;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = (int64_t)tile * TT;
     for (int p0 = threadIdx.x; p0 < TT * Kp; p0 += 512) {
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
         const int p = p0 + 256 * h;
         const int r = p / Kp, u = p - r * Kp;
         const int64_t e = e0 + r;
-        ok[h] = e < a.E && u < n;
+        ok[h] = e < E && u < n;
         const int64_t ee = ok[h] ? e : 0;
         const int uu = ok[h] ? u : 0;
 #pragma unroll
@@ -377,8 +377,8 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
     __syncthreads();
     if (a.channel_mix)
       mix_tile<LMAX, DW, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
-                                   a.g_tout, e0, a.E);
-    else copy_tile<DW, TT>(S, lds_ld, n, a.g_tout, e0, a.E);
+                                   a.g_tout, e0, E);
+    else copy_tile<DW, TT>(S, lds_ld, n, a.g_tout, e0, E);
     __syncthreads();
   }
 }
@@ -465,7 +465,7 @@ constexpr int kEdgesPerWave = 32;
 // A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a].
 template <class Pat, int G, bool A0>
 __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
-  clamp_live_edges(a);
+  const int E = live_edges(a);
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
   constexpr int GYW = gy_width(LMAX);
   constexpr int n = kWave / G;
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
   // load phase, where its latency overlaps the batch's other loads.
   constexpr bool CACHE = G == 1 && !A0;
   const int64_t el = w0 + (lane & (kEdgesPerWave - 1));
-  const int ci_lane = el < a.E ? a.ei[el] - a.centre_base : 0;
+  const int ci_lane = el < E ? a.ei[el] - a.centre_base : 0;
   int cur = -1;
   float cG[CACHE ? DIM : 1];
   for (int j0 = 0; j0 < kEdgesPerWave; j0 += G * KB) {
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
     for (int q = 0; q < KB; ++q) {
       const int jj = j0 + g + G * q;
       const int64_t e = w0 + jj;
-      act[q] = jj < kEdgesPerWave && e < a.E;
+      act[q] = jj < kEdgesPerWave && e < E;
       const uint32_t ee = act[q] ? (uint32_t)e : 0u;
       eev[q] = ee;
       uint32_t ci = (uint32_t)__shfl(ci_lane, jj & (kEdgesPerWave - 1), kWave);
