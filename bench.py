@@ -555,7 +555,7 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
         "capacity_overflows": {"warmup": over_warm, "timed": over_timed},
         "graph_captures_during_timed_steps": int(captures - captures_warm),
         "max_displacement_since_last_rebuild": disp,
-        "tiles": tiles, "setup_s": t_gen,
+        "tiles": tiles, "setup_s": t_gen, "source_hash": kernel_source_hash(),
     }
     m.close()
     return out

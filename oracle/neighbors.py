@@ -146,6 +146,26 @@ def neighbor_list(pos, cell, pbc, r_cut, n_local=None, method="auto", species=No
     return i[order], j[order], s[order]
 
 
+def centre_neighbors(pos, r_cut, centres):
+    """The rows of the list above for the given centres only, in a
+    non-periodic system (a spatial-decomposition share with its ghost shell):
+    candidates from scipy's k-d tree over all atoms with a slightly enlarged
+    radius, decided by the same exact test.  Returns (i, j, shift) sorted like
+    neighbor_list; shifts are zero."""
+    from scipy.spatial import cKDTree
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    centres = np.unique(np.asarray(centres, dtype=np.int64))
+    rr = r_cut * (1.0 + 1e-9) + 1e-9
+    cand = cKDTree(pos).query_ball_point(pos[centres], rr)
+    ci = np.concatenate([np.full(len(c), a, dtype=np.int64) for a, c in zip(centres, cand)])
+    cj = np.concatenate([np.asarray(c, dtype=np.int64) for c in cand])
+    s = np.zeros((ci.shape[0], 3), dtype=np.int64)
+    keep = _exact_test(pos, np.zeros(3), ci, cj, s, r_cut)
+    i, j, s = ci[keep], cj[keep], s[keep]
+    order = np.lexsort((s[:, 2], s[:, 1], s[:, 0], j, i))
+    return i[order], j[order], s[order]
+
+
 def row_ptr(i: np.ndarray, n_local: int) -> np.ndarray:
     counts = np.bincount(i, minlength=n_local)
     return np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)

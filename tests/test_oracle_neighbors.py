@@ -12,7 +12,7 @@ import pytest
 from scipy.spatial import cKDTree
 
 import workloads as W
-from oracle.neighbors import neighbor_list
+from oracle.neighbors import centre_neighbors, neighbor_list
 
 
 def _as_set(i, j, s):
@@ -97,6 +97,24 @@ def test_ghost_shell_list_matches_periodic():
     own = np.concatenate([np.arange(s.n_local), g.ghost_owner])
     assert np.array_equal(i0, i1) or sorted(zip(i0, own[j1])) == sorted(zip(i0, j0))
     assert sorted(zip(i1.tolist(), own[j1].tolist())) == sorted(zip(i0.tolist(), j0.tolist()))
+
+
+def test_centre_rows_equal_the_brute_force_rows():
+    """Rows of chosen centres of a ghost-shell share (non-periodic, ghosts
+    after the centres) equal the brute-force list's rows for them, including
+    a centre whose neighbours are ghosts and an exact-cutoff tie."""
+    mc = W.model_config(1)
+    g = W.ghost_shell(W.system(1), mc.r_cut + 0.5)
+    pos = g.pos.copy()
+    # a pair at exactly r_c from centre 3 along x: excluded by the strict test
+    pos[5] = pos[3] + np.array([mc.r_cut, 0.0, 0.0])
+    i0, j0, s0 = neighbor_list(pos, g.cell, g.pbc, mc.r_cut, n_local=g.n_local, method="brute")
+    cents = np.array([0, 3, 5, 17, g.n_local - 1])
+    i1, j1, s1 = centre_neighbors(pos, mc.r_cut, cents[::-1])
+    m = np.isin(i0, cents)
+    assert np.array_equal(i1, i0[m]) and np.array_equal(j1, j0[m]) and np.array_equal(s1, s0[m])
+    assert not np.any((i1 == 3) & (j1 == 5))
+    assert np.any(j1 >= g.n_local)
 
 
 def _loop_pairs(pos, cell, pbc, Z, table, r_max):
