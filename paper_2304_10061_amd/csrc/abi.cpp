@@ -407,6 +407,10 @@ struct Ws {
         *ghead0 = nullptr, *gw2 = nullptr, *gT[2] = {}, *gY = nullptr, *gu = nullptr, *gR = nullptr,
         *ggam = nullptr, *epair = nullptr, *g_e = nullptr;
   void* zscr = nullptr;      // hidden pre-activations of the 128-row backward MLP kernels
+  // activations stored by the register-resident forward kernels for their
+  // backward (two-body, latent layers 0 .. nl-2, final; a . v of the final)
+  void* zst[kMaxLayers + 1] = {};
+  float* av = nullptr;
   double *atom_e = nullptr, *partial = nullptr;
 };
 
@@ -453,6 +457,10 @@ size_t ws_layout(const Validated& v, int64_t Ec, int64_t Nc, int64_t E, int64_t 
   if (tall || rr)
     t.zscr = take(std::max(tall ? mlp_tall_scratch_bytes(Ec, v.d) : (size_t)0,
                            rr ? mlp_rr_scratch_bytes(Ec, v.d, (int)v.dims2b.size()) : (size_t)0));
+  if (rr) {
+    for (int k = 0; k <= v.nl; ++k) t.zst[k] = take(mlp_rr_scratch_bytes(Ec, v.d, (int)v.dims2b.size()));
+    t.av = fl(Ec);
+  }
   t.g_e = fl(E * 3);
   t.atom_e = (double*)take((size_t)nl * sizeof(double));
   t.partial = (double*)take((size_t)((nt + 255) / 256) * 10 * sizeof(double));
@@ -1115,6 +1123,15 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
     m0.rr = rr_view(m->twobody, m->rr_cfg, &m->rr_head0, &m->rr_head0T);
     m0.x_out = w.x[0]; m0.head_out = w.head0o;
     m0.tm = m->tm_choice[0];
+    // a chain whose forward and backward both take the register-resident
+    // kernels keeps its activations for the backward instead of recomputing
+    auto stores = [&](MlpArgs t, int kf, int kb, int prec) {
+      t.tm = m->tm_choice[kf];
+      const bool f = mlp_uses_rr(t, prec);
+      t.tm = m->tm_choice[kb];
+      return f && mlp_uses_rr(t, prec);
+    };
+    if (stores(m0, 0, 5, m->prec_two)) m0.act_store = w.zst[0];
     timed(m, "mlp_fwd_twobody", s, [&] { return launch_mlp_fwd(m0, m->prec_two, s); });
 
     TensorArgs tb;
@@ -1153,6 +1170,7 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
       mL.x_prev = w.x[L]; mL.s_in = w.V[L]; mL.s_ld = v.w_out[L] * n;
       mL.x_out = w.x[L + 1]; mL.head_out = w.wenv[L + 1];
       mL.tm = m->tm_choice[1];
+      if (stores(mL, 1, 4, m->prec_lat)) mL.act_store = w.zst[1 + L];
       timed(m, "mlp_fwd_latent", s, [&] { return launch_mlp_fwd(mL, m->prec_lat, s); });
       TensorArgs te = tb;
       te.w_env = w.wenv[L + 1]; te.ld_w = LW; te.gam = w.gam[L + 1];
@@ -1163,6 +1181,10 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
     mf.tp_gam = w.gam[v.nl - 1];
     mf.tm = m->tm_choice[2];
     mf.tp_out = w.gTf;   // the final scalars, read back by the backward pass
+    if (stores(mf, 2, 3, m->prec_lat)) {
+      mf.act_store = w.zst[v.nl];
+      mf.av_store = w.av;
+    }
     timed(m, "mlp_fwd_final", s, [&] { return launch_mlp_fwd(mf, m->prec_lat, s); });
 
     ReduceArgs ra;
@@ -1511,9 +1533,9 @@ void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, h
   const int cand_tt[2] = {32, 16};
   m->tune_forces.ensure(std::max<int64_t>(m->n_total, 1) * 3 * sizeof(double));
   m->md_epot.ensure(sizeof(double));
-  double best[8];
-  int pick[8];
-  for (int k = 0; k < 8; ++k) { best[k] = 1e300; pick[k] = 0; }
+  double tk[4][8];   // [candidate][kind]: summed kernel ms of two evaluations
+  for (int c = 0; c < 4; ++c)
+    for (int k = 0; k < 8; ++k) tk[c][k] = 1e300;
   const bool was = m->timing;
   for (int c = 0; c < ntm; ++c) {
     for (int k = 0; k < 6; ++k) m->tm_choice[k] = cand_tm[c];
@@ -1531,13 +1553,35 @@ void autotune_impl(AllegroModel* m, const double* pos, const int32_t* species, h
     collect_times(m);
     for (int k = 0; k < 8; ++k)
       for (const auto& kt : m->ktimes)
-        if (kt.name == kTuneNames[k] && kt.ms < best[k] && (k < 6 || c < 2)) {
-          best[k] = kt.ms;
-          pick[k] = k < 6 ? cand_tm[c] : cand_tt[c];
-        }
+        if (kt.name == kTuneNames[k] && (k < 6 || c < 2)) tk[c][k] = std::min(tk[c][k], kt.ms);
     m->ktimes.clear();
   }
   m->timing = was;
+  int pick[8];
+  // MLP chains as (forward, backward) pairs: register-resident in both
+  // directions (the forward then stores the activations the backward reads;
+  // that is how the register-resident candidate was timed), or the fastest
+  // other tile in each direction
+  const int pairs[3][2] = {{0, 5}, {1, 4}, {2, 3}};
+  for (const auto& pr : pairs) {
+    double rr_cost = 1e300, other[2] = {1e300, 1e300};
+    int other_pick[2] = {0, 0};
+    for (int c = 0; c < ntm; ++c) {
+      if (cand_tm[c] == kRRTile) {
+        rr_cost = tk[c][pr[0]] + tk[c][pr[1]];
+        continue;
+      }
+      for (int d = 0; d < 2; ++d)
+        if (tk[c][pr[d]] < other[d]) { other[d] = tk[c][pr[d]]; other_pick[d] = cand_tm[c]; }
+    }
+    const bool rr = rr_cost < 1e299 && rr_cost <= other[0] + other[1];
+    for (int d = 0; d < 2; ++d) pick[pr[d]] = rr ? kRRTile : other_pick[d];
+  }
+  for (int k = 6; k < 8; ++k) {
+    pick[k] = cand_tt[0];
+    for (int c = 1; c < 2; ++c)
+      if (tk[c][k] < tk[0][k]) pick[k] = cand_tt[c];
+  }
   for (int k = 0; k < 6; ++k) m->tm_choice[k] = pick[k];
   for (int k = 0; k < 2; ++k) m->tt_choice[k] = pick[6 + k];
   release_graph(m);

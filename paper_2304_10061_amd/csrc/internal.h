@@ -151,6 +151,13 @@ struct MlpArgs {
   // tall-tile backward only
   float* g_store = nullptr;       // [E][d] receives dE/dx_out (g_xprev, or g_x itself for two-body)
   void* act_scratch = nullptr;    // hidden pre-activations of the recomputation (fragment order)
+  // Register-resident kernels: activations the forward pass stores and the
+  // backward pass reads instead of recomputing the chain (both directions
+  // must run the register-resident kernels on the same edges and tiles):
+  // hidden pre-activations and h (two-body, latent), or the last hidden
+  // pre-activations plus a . v per edge in av_store (final layer).
+  void* act_store = nullptr;
+  float* av_store = nullptr;
   RRW rr;                         // register-resident kernels' weights (rr.cfg = 0: unavailable)
   const float* fold_v = nullptr;  // final layer, register-resident kernels: v = W_last w_e [d]
   float sigma[16] = {0};          // species scales sigma_Z (final layer, register-resident backward)
@@ -228,7 +235,8 @@ hipError_t launch_mlp_bwd(const MlpArgs& a, int prec, hipStream_t s);
 size_t mlp_lds_bytes(const MlpArgs& a, int prec, bool bwd);
 bool mlp_tile_fits(const MlpArgs& a, int prec, bool bwd, int tm);
 size_t mlp_tall_scratch_bytes(int64_t E, int d);   // scratch of the 128-row backward kernels
-size_t mlp_rr_scratch_bytes(int64_t E, int d, int nl);   // scratch of the register-resident backward kernels
+size_t mlp_rr_scratch_bytes(int64_t E, int d, int nl);   // activation array of the register-resident kernels
+bool mlp_uses_rr(const MlpArgs& a, int prec);             // whether a launch takes the register-resident kernels
 hipError_t launch_mlp_rr(const MlpArgs& a, bool bwd, hipStream_t s);   // mlp_rr*.hip
 hipError_t launch_env(const TensorArgs& a, hipStream_t s);
 hipError_t launch_tp_mix(const TensorArgs& a, bool final_layer, hipStream_t s);

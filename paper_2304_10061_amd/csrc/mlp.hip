@@ -15,13 +15,20 @@ hipError_t launch_mlp_rr_128_bwd(const MlpArgs& a, hipStream_t s);   // mlp_rr2b
 hipError_t launch_mlp_rr(const MlpArgs& a, bool bwd, hipStream_t s) {
   if (a.E <= 0) return hipSuccess;
   if (a.kind == kLatentFinal && (a.fold_v == nullptr || a.we == nullptr)) return hipErrorInvalidValue;
-  if (bwd && (a.act_scratch == nullptr || (a.kind != kLatentFinal && a.g_store == nullptr))) return hipErrorInvalidValue;
+  if (a.kind == kLatentFinal && a.act_store != nullptr && a.av_store == nullptr) return hipErrorInvalidValue;
+  if (bwd && ((a.act_scratch == nullptr && a.act_store == nullptr) ||
+              (a.kind != kLatentFinal && a.g_store == nullptr)))
+    return hipErrorInvalidValue;
   if (a.rr.cfg == 1) return bwd ? launch_mlp_rr_256_bwd(a, s) : launch_mlp_rr_256_fwd(a, s);
   if (a.rr.cfg == 2) return bwd ? launch_mlp_rr_128_bwd(a, s) : launch_mlp_rr_128_fwd(a, s);
   return hipErrorInvalidValue;
 }
 
 size_t mlp_rr_scratch_bytes(int64_t E, int d, int nl) { return rr::scratch_bytes(E, d, nl); }
+
+bool mlp_uses_rr(const MlpArgs& a, int prec) {
+  return (prec == 1 || prec == 2) && a.rr.cfg != 0 && (a.tm == kRRTile || a.tm == 0);
+}
 
 using namespace mlpk;
 
@@ -60,7 +67,7 @@ hipError_t launch(const MlpArgs& a, int prec, bool bwd, hipStream_t s) {
   if (bwd && a.kind == kLatentFinal && a.s_in == nullptr) return hipErrorInvalidValue;
   if (prec == 1 || prec == 2) {
     // register-resident kernels by default where the model has them
-    if (a.rr.cfg != 0 && (a.tm == kRRTile || a.tm == 0)) return launch_mlp_rr(a, bwd, s);
+    if (mlp_uses_rr(a, prec)) return launch_mlp_rr(a, bwd, s);
     // tall tiles on request (autotuner or allegro_set_tiles), where they fit
     if (a.tm == kTallRows && tall_fits(a, prec, bwd))
       return prec == 1 ? launch_prec<1>(a, kTallRows, bwd, s) : launch_prec<2>(a, kTallRows, bwd, s);

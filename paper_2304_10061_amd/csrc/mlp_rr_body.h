@@ -168,11 +168,13 @@ __device__ __forceinline__ void load_bform(bf16x8 (&dst)[kNE][KS], int k0, const
   });
 }
 
-// Pre-activation scratch of hidden layer l, block mb, N block nb of wave tile t:
-// 32 bytes per lane.
+// Activation slot l (of NL per wave tile), block mb, N block nb of wave tile
+// t: 32 bytes per lane, the 16 accumulator values of the block in BF16.
+// Slots 0 .. NL-2 hold the hidden pre-activations; slot NL-1 the last
+// layer's output h before the envelope factor (two-body and latent chains).
 template <int NL, int MBD>
 __device__ __forceinline__ bf16x8* zslot(void* base, int t, int l, int mb, int nb, int lane) {
-  const size_t i = ((((size_t)t * (NL - 1) + l) * MBD + mb) * kNE + nb) * 64 + lane;
+  const size_t i = ((((size_t)t * NL + l) * MBD + mb) * kNE + nb) * 64 + lane;
   return (bf16x8*)base + 2 * i;
 }
 
@@ -376,7 +378,8 @@ void k_rr_fwd(MlpArgs a) {
   const int E = live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int e0 = (blockIdx.x * kWaves + wave) * kEdgesPerWave;
+  const int tile = blockIdx.x * kWaves + wave;
+  const int e0 = tile * kEdgesPerWave;
   if (e0 >= E) return;
   const Rows R = rows_of(e0, E, lane);
   float u[kNE];
@@ -391,7 +394,8 @@ void k_rr_fwd(MlpArgs a) {
       // no hidden layer: the input is the last layer's operand
       static_assert(NL > 1, "register-resident chains have a hidden layer");
     }
-    hidden<D, NL, KIN, NL - 1, SF, SR>(a, x0, area, lane, nullptr, 0);
+    // with act_store, the hidden pre-activations are kept for the backward pass
+    hidden<D, NL, KIN, NL - 1, SF, SR>(a, x0, area, lane, a.act_store, tile);
   }
   // last layer: x = u h (two-body) or rs (x_prev + u h) -> x_out rows and the
   // head's B operand
@@ -421,6 +425,11 @@ void k_rr_fwd(MlpArgs a) {
                 x[i] = KIND == kTwoBody ? h : a.res_scale * (xp[b][nb][i] + h);
               }
               const int mb = p * NBP + b;
+              if (a.act_store) {   // h, for dE/du in the backward pass
+                bf16x8* z = zslot<NL, MBD>(a.act_store, tile, NL - 1, mb, nb, lane);
+                z[0] = bform(acc[b][nb], 0, Ident());
+                z[1] = bform(acc[b][nb], 1, Ident());
+              }
               if (a.x_out && R.ok[nb]) store_c(a.x_out, (uint32_t)D, 0, mb, R.ec[nb], g, x);
               stash(area, 2 * mb, nb, lane, bform(x, 0, Ident()));
               stash(area, 2 * mb + 1, nb, lane, bform(x, 1, Ident()));
@@ -451,7 +460,8 @@ void k_rr_fwd_final(MlpArgs a) {
   const int E = live_edges(a);
   const int lane = threadIdx.x & 63, g = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int e0 = (blockIdx.x * kWaves + wave) * kEdgesPerWave;
+  const int tile = blockIdx.x * kWaves + wave;
+  const int e0 = tile * kEdgesPerWave;
   if (e0 >= E) return;
   const Rows R = rows_of(e0, E, lane);
   float xw[kNE], av[kNE];
@@ -464,20 +474,26 @@ void k_rr_fwd_final(MlpArgs a) {
 #pragma unroll
     for (int b = 0; b < NBP; ++b) vb[b] = load_c(a.fold_v, 0u, 0, p * NBP + b, 0, g);
   };
-  auto epi_dot = [&](int, f32x16 (&acc)[NBP][kNE]) {
+  auto epi_dot = [&](int p, f32x16 (&acc)[NBP][kNE]) {
 #pragma unroll
     for (int b = 0; b < NBP; ++b)
 #pragma unroll
-      for (int nb = 0; nb < kNE; ++nb)
+      for (int nb = 0; nb < kNE; ++nb) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) av[nb] = fmaf(silu(acc[b][nb][i]), vb[b][i], av[nb]);
+        if (a.act_store) {   // the last hidden layer's pre-activations
+          bf16x8* z = zslot<NL, MBD>(a.act_store, tile, NL - 2, p * NBP + b, nb, lane);
+          z[0] = bform(acc[b][nb], 0, Ident());
+          z[1] = bform(acc[b][nb], 1, Ident());
+        }
+      }
   };
   {
     bf16x8 x0[kNE][KIN];
     final_input<D, NT, DIM, KIN>(a, x0, R, g, false, xw);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (NL == 2) gemm<KIN, MBD, SF>(x0, a.rr.fwd[0], pre_dot, epi_dot);
-    else hidden<D, NL, KIN, NL - 2, SF, SR>(a, x0, area, lane, nullptr, 0);
+    else hidden<D, NL, KIN, NL - 2, SF, SR>(a, x0, area, lane, a.act_store, tile);
   }
   if constexpr (NL > 2) {
     bf16x8 ah[kNE][KD];
@@ -491,6 +507,7 @@ void k_rr_fwd_final(MlpArgs a) {
     if (g == 0 && R.ok[nb]) {
       const float u = a.eb[(uint32_t)R.ec[nb] * kEB + kEB_U];
       a.eij[R.ec[nb]] = a.res_scale * (xs + u * as);
+      if (a.act_store) a.av_store[R.ec[nb]] = as;
     }
   }
 }
@@ -643,18 +660,38 @@ void k_rr_bwd(MlpArgs a) {
     __builtin_amdgcn_sched_barrier(0);
   });
 
-  // 2. recompute the chain (pre-activations to scratch); 3. dE/du = rs sum G h
-  // and dE/dh = rs u G into the LDS area
-  {
-    bf16x8 x0[kNE][KIN];
-    chain_input<KIND, D, NT, KIN>(a, x0, R, g);
-    __builtin_amdgcn_sched_barrier(0);
-    hidden<D, NL, KIN, NL - 1, SF, SR>(a, x0, area, lane, a.act_scratch, tile);
-  }
+  // 2. recompute the chain (pre-activations to scratch), unless the forward
+  // pass stored them; 3. dE/du = rs sum G h and dE/dh = rs u G into the LDS
+  // area
+  void* const zs = a.act_store ? a.act_store : a.act_scratch;
   float gu[kNE];
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) gu[nb] = 0.0f;
-  {
+  if (a.act_store) {
+    for (int mb = 0; mb < MBD; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < kNE; ++nb) {
+        const f32x16 G = load_G(mb, nb);
+        const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
+        const bf16x8 h0 = z[0], h1 = z[1];
+        f32x16 t;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          gu[nb] = fmaf(G[j], (float)h0[j], gu[nb]);
+          gu[nb] = fmaf(G[8 + j], (float)h1[j], gu[nb]);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t[i] = rs * u[nb] * G[i];
+        stash(area, 2 * mb, nb, lane, bform(t, 0, Ident()));
+        stash(area, 2 * mb + 1, nb, lane, bform(t, 1, Ident()));
+      }
+  } else {
+    {
+      bf16x8 x0[kNE][KIN];
+      chain_input<KIND, D, NT, KIN>(a, x0, R, g);
+      __builtin_amdgcn_sched_barrier(0);
+      hidden<D, NL, KIN, NL - 1, SF, SR>(a, x0, area, lane, zs, tile);
+    }
     bf16x8 ah[kNE][KD];
     unstash<KD>(area, ah, lane);
     f32x16 Gb[NBP][kNE];
@@ -699,7 +736,7 @@ void k_rr_bwd(MlpArgs a) {
     constexpr int l = NL - 2 - decltype(lc)::value;   // hidden layer NL-2 down to 0
     bf16x8 d[kNE][KD];
     unstash<KD>(area, d, lane);
-    back_layer<D, NL, SR>(a.act_scratch, tile, lane, l, d, a.rr.bwd[l + 1], area);
+    back_layer<D, NL, SR>(zs, tile, lane, l, d, a.rr.bwd[l + 1], area);
   });
   bf16x8 dz[kNE][KD];
   unstash<KD>(area, dz, lane);
@@ -759,17 +796,41 @@ void k_rr_bwd_final(MlpArgs a) {
         stash(area, 2 * mb + 1, nb, lane, bform(t, 1, Ident()));
       }
   };
-  {
-    bf16x8 x0[kNE][KIN];
-    final_input<D, NT, 9, KIN>(a, x0, R, g, true, xw);
-    __builtin_amdgcn_sched_barrier(0);
-    if constexpr (NL == 2) gemm<KIN, MBD, SF>(x0, a.rr.fwd[0], pre_dot, epi_dot);
-    else hidden<D, NL, KIN, NL - 2, SF, SR>(a, x0, area, lane, a.act_scratch, tile);
-  }
-  if constexpr (NL > 2) {
-    bf16x8 ah[kNE][KD];
-    unstash<KD>(area, ah, lane);
-    gemm<KD, MBD, SR>(ah, a.rr.fwd[NL - 2], pre_dot, epi_dot);
+  void* const zs = a.act_store ? a.act_store : a.act_scratch;
+  if (a.act_store) {
+    // the forward pass stored the last hidden layer's pre-activations and a . v
+    for (int mb = 0; mb < MBD; ++mb) {
+      const f32x16 v = load_c(a.fold_v, 0u, 0, mb, 0, g);
+#pragma unroll
+      for (int nb = 0; nb < kNE; ++nb) {
+        const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 2, mb, nb, lane);
+        const bf16x8 z0 = z[0], z1 = z[1];
+        f32x16 t;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          t[j] = ce[nb] * v[j] * silu_grad((float)z0[j]);
+          t[8 + j] = ce[nb] * v[8 + j] * silu_grad((float)z1[j]);
+        }
+        stash(area, 2 * mb, nb, lane, bform(t, 0, Ident()));
+        stash(area, 2 * mb + 1, nb, lane, bform(t, 1, Ident()));
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < kNE; ++nb)
+      if (g == 0) av[nb] = a.av_store[R.ec[nb]];   // the full sum, in one half-wave
+  } else {
+    {
+      bf16x8 x0[kNE][KIN];
+      final_input<D, NT, 9, KIN>(a, x0, R, g, true, xw);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (NL == 2) gemm<KIN, MBD, SF>(x0, a.rr.fwd[0], pre_dot, epi_dot);
+      else hidden<D, NL, KIN, NL - 2, SF, SR>(a, x0, area, lane, zs, tile);
+    }
+    if constexpr (NL > 2) {
+      bf16x8 ah[kNE][KD];
+      unstash<KD>(area, ah, lane);
+      gemm<KD, MBD, SR>(ah, a.rr.fwd[NL - 2], pre_dot, epi_dot);
+    }
   }
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) {
@@ -784,17 +845,19 @@ void k_rr_bwd_final(MlpArgs a) {
     constexpr int l = NL - 3 - decltype(lc)::value;   // hidden layer NL-3 down to 0
     bf16x8 d[kNE][KD];
     unstash<KD>(area, d, lane);
-    back_layer<D, NL, SR>(a.act_scratch, tile, lane, l, d, a.rr.bwd[l + 1], area);
+    back_layer<D, NL, SR>(zs, tile, lane, l, d, a.rr.bwd[l + 1], area);
   });
   bf16x8 dz[kNE][KD];
   unstash<KD>(area, dz, lane);
   input_grad<kLatentFinal, D, NT, KIN, SF>(a, dz, R, g, rs, load_G);
 }
 
-// Scratch bytes of the backward kernels for E edges.
+// Bytes of an activation array (recomputation scratch of the backward
+// kernels, or the stored activations of one chain) for E edges: NL slots of
+// D BF16 values per edge.
 inline size_t scratch_bytes(int64_t E, int D, int NL) {
   const int64_t tiles = (E + kEdgesPerWave - 1) / kEdgesPerWave;
-  return (size_t)tiles * (NL > 1 ? NL - 1 : 1) * (D / 32) * kNE * 64 * 32;
+  return (size_t)tiles * NL * (D / 32) * kNE * 64 * 32;
 }
 
 // LDS bytes of a block (one B-operand area of D/16 K steps per wave).
