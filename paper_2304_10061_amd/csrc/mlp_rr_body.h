@@ -630,7 +630,15 @@ void k_rr_bwd(MlpArgs a) {
   auto load_G = [&](int mb, int nb) { return load_c(gst, (uint32_t)D, 0, mb, R.ec[nb], g); };
   bf16x8* area = lds_area<KD>();
 
-  // 1. G = g_x + g_head @ W_head^T -> g_store rows, in K chunks
+  // 1. G = g_x + g_head @ W_head^T -> g_store rows, in K chunks.  With the
+  // activations stored by the forward pass, the last chunk's epilogue also
+  // does step 3 below on the G it holds (and the two-body kind, which needs
+  // G nowhere else, does not store it).
+  void* const zs = a.act_store ? a.act_store : a.act_scratch;
+  const bool fused = a.act_store != nullptr;
+  float gu[kNE];
+#pragma unroll
+  for (int nb = 0; nb < kNE; ++nb) gu[nb] = 0.0f;
   static_for<0, NCH>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     constexpr int KC = KH - c * kHeadChunk < kHeadChunk ? KH - c * kHeadChunk : kHeadChunk;
@@ -651,41 +659,36 @@ void k_rr_bwd(MlpArgs a) {
             }
         },
         [&](int p, f32x16 (&acc)[NBP][kNE]) {
+          const bool last = c == NCH - 1 && fused;
 #pragma unroll
           for (int b = 0; b < NBP; ++b)
 #pragma unroll
-            for (int nb = 0; nb < kNE; ++nb)
-              if (R.ok[nb]) store_c(gst, (uint32_t)D, 0, p * NBP + b, R.ec[nb], g, acc[b][nb]);
+            for (int nb = 0; nb < kNE; ++nb) {
+              const int mb = p * NBP + b;
+              if (R.ok[nb] && !(last && KIND == kTwoBody)) store_c(gst, (uint32_t)D, 0, mb, R.ec[nb], g, acc[b][nb]);
+              if (last) {
+                const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
+                const bf16x8 h0 = z[0], h1 = z[1];
+                f32x16 t;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                  gu[nb] = fmaf(acc[b][nb][j], (float)h0[j], gu[nb]);
+                  gu[nb] = fmaf(acc[b][nb][8 + j], (float)h1[j], gu[nb]);
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) t[i] = rs * u[nb] * acc[b][nb][i];
+                stash(area, 2 * mb, nb, lane, bform(t, 0, Ident()));
+                stash(area, 2 * mb + 1, nb, lane, bform(t, 1, Ident()));
+              }
+            }
         });
     __builtin_amdgcn_sched_barrier(0);
   });
 
   // 2. recompute the chain (pre-activations to scratch), unless the forward
   // pass stored them; 3. dE/du = rs sum G h and dE/dh = rs u G into the LDS
-  // area
-  void* const zs = a.act_store ? a.act_store : a.act_scratch;
-  float gu[kNE];
-#pragma unroll
-  for (int nb = 0; nb < kNE; ++nb) gu[nb] = 0.0f;
-  if (a.act_store) {
-    for (int mb = 0; mb < MBD; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < kNE; ++nb) {
-        const f32x16 G = load_G(mb, nb);
-        const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
-        const bf16x8 h0 = z[0], h1 = z[1];
-        f32x16 t;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          gu[nb] = fmaf(G[j], (float)h0[j], gu[nb]);
-          gu[nb] = fmaf(G[8 + j], (float)h1[j], gu[nb]);
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) t[i] = rs * u[nb] * G[i];
-        stash(area, 2 * mb, nb, lane, bform(t, 0, Ident()));
-        stash(area, 2 * mb + 1, nb, lane, bform(t, 1, Ident()));
-      }
-  } else {
+  // area (done in step 1's epilogue with stored activations)
+  if (!fused) {
     {
       bf16x8 x0[kNE][KIN];
       chain_input<KIND, D, NT, KIN>(a, x0, R, g);
