@@ -45,6 +45,7 @@ namespace allegro {
 // the accumulation registers, the activations of two N blocks in the others).
 namespace rr_fwd {
 constexpr int kNE = 2, kOcc = 1, kWaves = 4, kPD = 4;
+constexpr bool kNonTemporalOut = true;
 #include "mlp_rr_body.h"
 }  // namespace rr_fwd
 
@@ -52,10 +53,15 @@ constexpr int kNE = 2, kOcc = 1, kWaves = 4, kPD = 4;
 // dE/dx_out and the pre-activation reads, fit the accumulation registers).
 namespace rr_bwd {
 constexpr int kNE = 2, kOcc = 1, kWaves = 4, kPD = 4;
+constexpr bool kNonTemporalOut = false;
 #include "mlp_rr_body.h"
 }  // namespace rr_bwd
 
 namespace rr {
+
+// The forward kernels store activations in the tile layout the backward
+// kernels read.
+static_assert(rr_fwd::kNE == rr_bwd::kNE && rr_fwd::kWaves == rr_bwd::kWaves, "tile shapes must agree");
 
 inline size_t scratch_bytes(int64_t E, int D, int NL) { return rr_bwd::scratch_bytes(E, D, NL); }
 

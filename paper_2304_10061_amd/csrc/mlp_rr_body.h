@@ -117,6 +117,22 @@ struct Silu {
 
 // Accumulator block `mb` of a row-major FP32 array (row stride ld, column
 // offset c0): features c0 + 32 mb + 8 q + 4 g + (0..3) are slots 4 q .. 4 q + 3.
+// Stores of the kernel's outputs.  The forward kernels store non-temporally:
+// their outputs (rows for later kernels, the activation store for the
+// backward pass) would otherwise displace the weight fragments that every
+// wave streams from L2.  The backward kernels' outputs are read by the very
+// next kernels and keep ordinary stores.
+__device__ __forceinline__ void out_store4(float* p, float4 v) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 w = {v.x, v.y, v.z, v.w};
+  if constexpr (kNonTemporalOut) __builtin_nontemporal_store(w, (v4*)p);
+  else *(v4*)p = w;
+}
+__device__ __forceinline__ void out_store8(bf16x8* p, const bf16x8& v) {
+  if constexpr (kNonTemporalOut) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 __device__ __forceinline__ f32x16 load_c(const float* p, uint32_t ld, int c0, int mb, int e, int g) {
   const float* q0 = p + (uint32_t)e * ld + (uint32_t)(c0 + 32 * mb + 4 * g);
   f32x16 a;
@@ -130,7 +146,7 @@ __device__ __forceinline__ f32x16 load_c(const float* p, uint32_t ld, int c0, in
 __device__ __forceinline__ void store_c(float* p, uint32_t ld, int c0, int mb, int e, int g, const f32x16& a) {
   float* q0 = p + (uint32_t)e * ld + (uint32_t)(c0 + 32 * mb + 4 * g);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) *(float4*)(q0 + 8 * q) = make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+  for (int q = 0; q < 4; ++q) out_store4(q0 + 8 * q, make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]));
 }
 
 // K steps [k0, k0 + KN) of the B operand from row-major FP32 rows: step k0 + k
@@ -169,13 +185,16 @@ __device__ __forceinline__ void load_bform(bf16x8 (&dst)[kNE][KS], int k0, const
 }
 
 // Activation slot l (of NL per wave tile), block mb, N block nb of wave tile
-// t: 32 bytes per lane, the 16 accumulator values of the block in BF16.
-// Slots 0 .. NL-2 hold the hidden pre-activations; slot NL-1 the last
-// layer's output h before the envelope factor (two-body and latent chains).
+// t: the 16 accumulator values of the block in BF16, as two halves of
+// 64 lanes x 16 bytes (z[0] and z[kZHalf]), so that each half is one fully
+// coalesced 1 KB access of the wave.  Slots 0 .. NL-2 hold the hidden
+// pre-activations; slot NL-1 the last layer's output h before the envelope
+// factor (two-body and latent chains).
+constexpr int kZHalf = 64;
 template <int NL, int MBD>
 __device__ __forceinline__ bf16x8* zslot(void* base, int t, int l, int mb, int nb, int lane) {
-  const size_t i = ((((size_t)t * NL + l) * MBD + mb) * kNE + nb) * 64 + lane;
-  return (bf16x8*)base + 2 * i;
+  const size_t i = (((size_t)t * NL + l) * MBD + mb) * kNE + nb;
+  return (bf16x8*)base + i * 2 * kZHalf + lane;
 }
 
 // Per-wave LDS area holding one layer's output as the next layer's B operand:
@@ -187,6 +206,44 @@ __device__ __forceinline__ bf16x8* lds_area() {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   return (bf16x8*)smem + (size_t)wave * KS * kNE * 64;
 }
+// Per-wave 4 KB staging area after the B-operand areas of the block, for
+// storing one 32 x 32 FP32 accumulator block as whole row segments.
+template <int KS>
+__device__ __forceinline__ float* stage_area() {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  return (float*)(smem + (size_t)kWaves * KS * kNE * 64 * 16 + (size_t)wave * 4096);
+}
+
+// Accumulator block `mb` of N block nb (edges e_nb .. e_nb + 31, those below E
+// stored) into row-major FP32 rows (row stride ld, column offset c0),
+// transposed through the wave's staging area so that each store instruction
+// writes eight whole 128-byte row segments.  Chunks of 4 features are
+// XOR-swizzled by row in the staging area.
+__device__ __forceinline__ void store_c_rows(float* p, uint32_t ld, int c0, int mb, int e_nb, int E, int lane,
+                                             const f32x16& a, float* st) {
+  const int g = lane >> 5, col = lane & 31;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    *(float4*)(st + col * 32 + (((2 * q + g) ^ (col & 7)) * 4)) =
+        make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int ch = lane & 7;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int row = 8 * k + (lane >> 3);
+    const float4 v = *(const float4*)(st + row * 32 + ((ch ^ (row & 7)) * 4));
+    const int e = e_nb + row;
+    if (e < E) out_store4(p + (uint32_t)e * ld + (uint32_t)(c0 + 32 * mb + 4 * ch), v);
+  }
+  // the next block overwrites the staging area
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void stash(bf16x8* area, int k, int nb, int lane, const bf16x8& v) {
   area[(k * kNE + nb) * 64 + lane] = v;
 }
@@ -343,8 +400,8 @@ struct ToArea {
         const int mb = p * NBP + b;
         if (scratch) {
           bf16x8* z = zslot<NL, MBD>(scratch, tile, l, mb, nb, lane);
-          z[0] = bform(acc[b][nb], 0, Ident());
-          z[1] = bform(acc[b][nb], 1, Ident());
+          out_store8(&z[0], bform(acc[b][nb], 0, Ident()));
+          out_store8(&z[kZHalf], bform(acc[b][nb], 1, Ident()));
         }
         stash(area, 2 * mb, nb, lane, bform(acc[b][nb], 0, F()));
         stash(area, 2 * mb + 1, nb, lane, bform(acc[b][nb], 1, F()));
@@ -385,6 +442,7 @@ void k_rr_fwd(MlpArgs a) {
   float u[kNE];
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) u[nb] = R.ok[nb] ? a.eb[(uint32_t)R.ec[nb] * kEB + kEB_U] : 0.0f;
+  float* st = stage_area<KD>();
   bf16x8* area = lds_area<KD>();
   {
     bf16x8 x0[kNE][KIN];
@@ -427,10 +485,10 @@ void k_rr_fwd(MlpArgs a) {
               const int mb = p * NBP + b;
               if (a.act_store) {   // h, for dE/du in the backward pass
                 bf16x8* z = zslot<NL, MBD>(a.act_store, tile, NL - 1, mb, nb, lane);
-                z[0] = bform(acc[b][nb], 0, Ident());
-                z[1] = bform(acc[b][nb], 1, Ident());
+                out_store8(&z[0], bform(acc[b][nb], 0, Ident()));
+                out_store8(&z[kZHalf], bform(acc[b][nb], 1, Ident()));
               }
-              if (a.x_out && R.ok[nb]) store_c(a.x_out, (uint32_t)D, 0, mb, R.ec[nb], g, x);
+              if (a.x_out) store_c_rows(a.x_out, (uint32_t)D, 0, mb, e0 + 32 * nb, E, lane, x, st);
               stash(area, 2 * mb, nb, lane, bform(x, 0, Ident()));
               stash(area, 2 * mb + 1, nb, lane, bform(x, 1, Ident()));
             }
@@ -445,7 +503,7 @@ void k_rr_fwd(MlpArgs a) {
     for (int b = 0; b < HB; ++b)
 #pragma unroll
       for (int nb = 0; nb < kNE; ++nb)
-        if (R.ok[nb]) store_c(a.head_out, (uint32_t)HN, 0, p * HB + b, R.ec[nb], g, acc[b][nb]);
+        store_c_rows(a.head_out, (uint32_t)HN, 0, p * HB + b, e0 + 32 * nb, E, lane, acc[b][nb], st);
   });
 }
 
@@ -483,8 +541,8 @@ void k_rr_fwd_final(MlpArgs a) {
         for (int i = 0; i < 16; ++i) av[nb] = fmaf(silu(acc[b][nb][i]), vb[b][i], av[nb]);
         if (a.act_store) {   // the last hidden layer's pre-activations
           bf16x8* z = zslot<NL, MBD>(a.act_store, tile, NL - 2, p * NBP + b, nb, lane);
-          z[0] = bform(acc[b][nb], 0, Ident());
-          z[1] = bform(acc[b][nb], 1, Ident());
+          out_store8(&z[0], bform(acc[b][nb], 0, Ident()));
+          out_store8(&z[kZHalf], bform(acc[b][nb], 1, Ident()));
         }
       }
   };
@@ -528,7 +586,7 @@ __device__ __forceinline__ void back_layer(void* scratch, int tile, int lane, in
 #pragma unroll
           for (int nb = 0; nb < kNE; ++nb) {
             const bf16x8* z = zslot<NL, MBD>(scratch, tile, l, p * NBP + b, nb, lane);
-            const bf16x8 z0 = z[0], z1 = z[1];
+            const bf16x8 z0 = z[0], z1 = z[kZHalf];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               zz[b][nb][j] = silu_grad((float)z0[j]);
@@ -668,7 +726,7 @@ void k_rr_bwd(MlpArgs a) {
               if (R.ok[nb] && !(last && KIND == kTwoBody)) store_c(gst, (uint32_t)D, 0, mb, R.ec[nb], g, acc[b][nb]);
               if (last) {
                 const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
-                const bf16x8 h0 = z[0], h1 = z[1];
+                const bf16x8 h0 = z[0], h1 = z[kZHalf];
                 f32x16 t;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -807,7 +865,7 @@ void k_rr_bwd_final(MlpArgs a) {
 #pragma unroll
       for (int nb = 0; nb < kNE; ++nb) {
         const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 2, mb, nb, lane);
-        const bf16x8 z0 = z[0], z1 = z[1];
+        const bf16x8 z0 = z[0], z1 = z[kZHalf];
         f32x16 t;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -864,7 +922,7 @@ inline size_t scratch_bytes(int64_t E, int D, int NL) {
 }
 
 // LDS bytes of a block (one B-operand area of D/16 K steps per wave).
-constexpr size_t lds_bytes(int D) { return (size_t)kWaves * (D / 16) * kNE * 64 * 16; }
+constexpr size_t lds_bytes(int D) { return (size_t)kWaves * ((D / 16) * kNE * 64 * 16 + 4096); }
 
 template <class K>
 hipError_t launch_kernel(K k, const MlpArgs& a, int D, hipStream_t s) {
