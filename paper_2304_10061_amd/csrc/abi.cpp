@@ -1138,6 +1138,7 @@ void energy_forces_impl(AllegroModel* m, const Ws& w, const double* pos, const i
     tb.E = E; tb.E_dev = E_dev; tb.n_centres = nc; tb.n = n; tb.l_max = v.lmax; tb.row_ptr = drp; tb.ei = ei + eA;
     tb.centre_base = (int)cA; tb.eb = w.eb; tb.c_norm = (float)m->c_norm;
     tb.channel_mix = m->cfg.channel_mix ? 1 : 0; tb.mix_scale = (float)(1.0 / std::sqrt((double)n));
+    tb.mix_bf3 = m->prec != ALLEGRO_PREC_FP32 ? 1 : 0;   // BF16 modes: mixing as BF16 x 3
     tb.mix_stride = m->mix_stride;
 
     TensorArgs t1 = tb;

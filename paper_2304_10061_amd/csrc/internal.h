@@ -210,6 +210,7 @@ struct TensorArgs {
                                   // (natural l = 0..l_max, then unnatural l = 0..l_max)
   int mix_stride = 0;             // floats between consecutive blocks
   int channel_mix = 1;
+  int mix_bf3 = 0;                // mixing as three BF16 MFMAs per product (BF16 modes)
   float mix_scale = 1.0f;         // 1/sqrt(n)
   float* v_out = nullptr;         // [E][w_out][n]
   // backward

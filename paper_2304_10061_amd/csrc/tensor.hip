@@ -13,7 +13,11 @@
 // per path); its sparsity pattern is a compile-time constant, so each (edge,
 // channel) pair executes only the non-zero multiply-adds.
 // Linear channel mixing: V^L[e][c][v] = sum_u M_{l(c)}[v][u] T[e][c][u] / sqrt(n),
-// a dense contraction over channels run on FP32 MFMA.
+// a dense contraction over channels run on FP32 MFMA, or, in the BF16 modes,
+// as three BF16 MFMAs per product: with x = x_hi + x_lo split into two BF16
+// numbers for both operands, hi*hi + hi*lo + lo*hi keeps about 16
+// significant bits (more than the TF32 of section "Mixed-precision
+// calculations") at a fifth of the FP32 MFMA time.
 //
 // Deeper models (three or more layers) also carry unnatural-parity irreps
 // (1e, 2o, 3e): the features of those layers hold 2 dim components (natural
@@ -130,6 +134,23 @@ __device__ __forceinline__ f32x4 mma8(const float* a, const float* b, f32x4 c) {
   return c;
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// The K = 32 block in one step per product term: lane group g holds
+// k = 8 g .. 8 g + 7, the same assignment as mma8's.
+__device__ __forceinline__ f32x4 mma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh, const bf16x8& bl,
+                                      f32x4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+}
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi).
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
 // Channel mixing out[e][c][v] = scale * sum_k S[c][e][k] B_{slot(c)}[k][v] for
 // the rows of an edge tile.  Each wave owns one 16-wide column tile of the
 // output (with fewer column tiles than waves, the waves also split the
@@ -139,14 +160,20 @@ __device__ __forceinline__ f32x4 mma8(const float* a, const float* b, f32x4 c) {
 // fragments per component instead.
 constexpr int kMixKB = 2;   // K = n <= 64
 
-template <int NS>
+// B fragments of NS slots: FP32, or (BF3) split into BF16 hi and lo parts.
+template <int NS, bool BF3 = false>
 struct MixB {
   float b[NS][kMixKB][8];
   int nt, csub, wpt;
 };
-
 template <int NS>
-__device__ __forceinline__ void mix_geometry(MixB<NS>& m, int Np) {
+struct MixB<NS, true> {
+  bf16x8 bh[NS][kMixKB], bl[NS][kMixKB];
+  int nt, csub, wpt;
+};
+
+template <class MB>
+__device__ __forceinline__ void mix_geometry(MB& m, int Np) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nct = Np >> 4;   // 2 or 4 (Np a multiple of 32, n <= 64)
   m.nt = wave % nct;
@@ -166,12 +193,33 @@ __device__ __forceinline__ void load_mix_slot(float (&b)[kMixKB][8], const float
   }
 }
 
-template <int NS>
-__device__ __forceinline__ void load_mix_b(MixB<NS>& m, const float* Bbase, int b_stride, int Kp, int Np) {
+__device__ __forceinline__ void split_mix_slot(const float (&b)[kMixKB][8], bf16x8 (&bh)[kMixKB],
+                                               bf16x8 (&bl)[kMixKB]) {
+#pragma unroll
+  for (int kb = 0; kb < kMixKB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      __bf16 h, l;
+      split_bf16(b[kb][j], h, l);
+      bh[kb][j] = h;
+      bl[kb][j] = l;
+    }
+}
+
+template <int NS, bool BF3>
+__device__ __forceinline__ void load_mix_b(MixB<NS, BF3>& m, const float* Bbase, int b_stride, int Kp, int Np) {
   mix_geometry(m, Np);
   const int nkb = Kp >> 5;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) load_mix_slot(m.b[s], Bbase + (size_t)s * b_stride, m.nt, nkb);
+  for (int s = 0; s < NS; ++s) {
+    if constexpr (BF3) {
+      float b[kMixKB][8];
+      load_mix_slot(b, Bbase + (size_t)s * b_stride, m.nt, nkb);
+      split_mix_slot(b, m.bh[s], m.bl[s]);
+    } else {
+      load_mix_slot(m.b[s], Bbase + (size_t)s * b_stride, m.nt, nkb);
+    }
+  }
 }
 
 // One strided component c of the tile: rows e0.., output row stride ldo components.
@@ -210,20 +258,77 @@ __device__ __forceinline__ void mix_one(const float* S, int lds_ld, int c, const
   }
 }
 
+// The BF16 x 3 form of mix_one: the tile is staged as two BF16 planes (hi
+// parts, then lo parts, row stride lds_ld elements, a multiple of 8), and the
+// B fragments come pre-split.
+template <int TT>
+__device__ __forceinline__ void mix_one3(const __bf16* Sh, const __bf16* Sl, int lds_ld, int c,
+                                         const bf16x8 (&bh)[kMixKB], const bf16x8 (&bl)[kMixKB], int nt, int n,
+                                         int Kp, float scale, float* out, int ldo, int64_t e0, int E) {
+  constexpr int RT = TT / 16;
+  const int lane = lane_id();
+  const int nkb = Kp >> 5;
+  const int col = nt * 16 + (lane & 15);
+  f32x4 acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int kb = 0; kb < kMixKB; ++kb) {
+    if (kb < nkb) {
+      const size_t at = ((size_t)c * TT + (lane & 15)) * lds_ld + kb * 32 + 8 * (lane >> 4);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const bf16x8 ah = *(const bf16x8*)(Sh + at + (size_t)rt * 16 * lds_ld);
+        const bf16x8 al = *(const bf16x8*)(Sl + at + (size_t)rt * 16 * lds_ld);
+        acc[rt] = mma3(ah, al, bh[kb], bl[kb], acc[rt]);
+      }
+    }
+  }
+  if (col < n) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = rt * 16 + 4 * (lane >> 4) + i;
+        if (e0 + r < E) out[((size_t)(e0 + r) * ldo + c) * n + col] = acc[rt][i] * scale;
+      }
+  }
+}
+
+// Writes value v of component c, tile row r, channel u into the staged tile:
+// FP32, or (BF3) its hi and lo BF16 parts into the two planes of DIMS
+// components each.
+template <bool BF3, int DIMS, int TT>
+__device__ __forceinline__ void stage_value(float* S, int lds_ld, int c, int r, int u, float v) {
+  const size_t at = ((size_t)c * TT + r) * lds_ld + u;
+  if constexpr (BF3) {
+    __bf16* Sh = (__bf16*)S;
+    __bf16 h, l;
+    split_bf16(v, h, l);
+    Sh[at] = h;
+    Sh[(size_t)DIMS * TT * lds_ld + at] = l;
+  } else {
+    S[at] = v;
+  }
+}
+
 // HOLD: m holds the fragments of slots 0..LMAX (natural-parity output).
 // Otherwise each component's slot is loaded from Bbase; the unnatural l = 0
 // slot (component D of a 2 D wide feature) is never kept and is skipped.
-template <int LMAX, int DOUT, int TT, bool HOLD, int NS>
-__device__ void mix_tile(const float* S, int lds_ld, const MixB<NS>& m, const float* Bbase, int b_stride, int n,
+template <int LMAX, int DOUT, int TT, bool HOLD, int NS, bool BF3>
+__device__ void mix_tile(const float* S, int lds_ld, const MixB<NS, BF3>& m, const float* Bbase, int b_stride, int n,
                          int Kp, float scale, float* out, int64_t e0, int E) {
   constexpr int D = (LMAX + 1) * (LMAX + 1);
+  const __bf16* Sh = (const __bf16*)S;
+  const __bf16* Sl = Sh + (size_t)DOUT * TT * lds_ld;
   if constexpr (HOLD) {
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
 #pragma unroll 1
       for (int c = l * l; c < (l + 1) * (l + 1); ++c) {
         if (c % m.wpt != m.csub) continue;
-        mix_one<TT>(S, lds_ld, c, m.b[l], m.nt, n, Kp, scale, out, DOUT, e0, E);
+        if constexpr (BF3) mix_one3<TT>(Sh, Sl, lds_ld, c, m.bh[l], m.bl[l], m.nt, n, Kp, scale, out, DOUT, e0, E);
+        else mix_one<TT>(S, lds_ld, c, m.b[l], m.nt, n, Kp, scale, out, DOUT, e0, E);
       }
     }
   } else {
@@ -232,7 +337,13 @@ __device__ void mix_tile(const float* S, int lds_ld, const MixB<NS>& m, const fl
       if (c % m.wpt != m.csub || (DOUT > D && c == D)) continue;
       float b[kMixKB][8];
       load_mix_slot(b, Bbase + (size_t)mix_slot<LMAX>(c) * b_stride, m.nt, Kp >> 5);
-      mix_one<TT>(S, lds_ld, c, b, m.nt, n, Kp, scale, out, DOUT, e0, E);
+      if constexpr (BF3) {
+        bf16x8 bh[kMixKB], bl[kMixKB];
+        split_mix_slot(b, bh, bl);
+        mix_one3<TT>(Sh, Sl, lds_ld, c, bh, bl, m.nt, n, Kp, scale, out, DOUT, e0, E);
+      } else {
+        mix_one<TT>(S, lds_ld, c, b, m.nt, n, Kp, scale, out, DOUT, e0, E);
+      }
     }
   }
 }
@@ -252,15 +363,15 @@ constexpr bool kHoldMix = Pat::In == kNatural && Pat::Out == kNatural && Pat::Lm
 // Tensor product (non-final layers) + channel mixing -> V^L.  Each block
 // walks edge tiles blockIdx.x, blockIdx.x + gridDim.x, ... with the mixing
 // fragments loaded once.
-template <class Pat, int TT>
+template <class Pat, int TT, bool BF3>
 __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp, int Np) {
   const int E = live_edges(a);
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
   constexpr bool HOLD = kHoldMix<Pat>;
-  extern __shared__ __align__(16) float S[];   // [DOUT][TT][lds_ld]
+  extern __shared__ __align__(16) float S[];   // [DOUT][TT][lds_ld] (BF3: two BF16 planes of that shape)
   const int n = a.n;
   const auto w = tp_weights<Pat>(a);   // uniform: read with scalar loads
-  MixB<HOLD ? LMAX + 1 : 1> mb;
+  MixB<HOLD ? LMAX + 1 : 1, BF3> mb;
   if (a.channel_mix) {
     if constexpr (HOLD) load_mix_b(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
     else mix_geometry(mb, Np);
@@ -295,11 +406,11 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
         for (int c = 0; c < DOUT; ++c) T[c] = 0.0f;
         if (ok[h]) tp_forward<Pat>(V[h], G[h], T, per_iteration(w));
 #pragma unroll
-        for (int c = 0; c < DOUT; ++c) S[((size_t)c * TT + r) * lds_ld + u] = T[c];
+        for (int c = 0; c < DOUT; ++c) stage_value<BF3, DOUT, TT>(S, lds_ld, c, r, u, T[c]);
       }
     }
     __syncthreads();
-    if (a.channel_mix)
+    if (BF3 || a.channel_mix)   // the BF16 x 3 form is only launched with mixing on
       mix_tile<LMAX, DOUT, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
                                      a.v_out, e0, E);
     else copy_tile<DOUT, TT>(S, lds_ld, n, a.v_out, e0, E);
@@ -314,7 +425,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
 // plus dE/ds at a = 0 (the scalars read by layer L's latent MLP); then the
 // transposed mixing gives dE/dT^L.  The launch's tpw / tpw_v hold layer
 // L+1's table.
-template <class PatN, int TT>
+template <class PatN, int TT, bool BF3>
 __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, int Kp, int Np) {
   const int E = live_edges(a);
   constexpr int LMAX = PatN::Lmax, DIM = PatN::DIM, DW = PatN::DIN, DN = PatN::DOUT;
@@ -324,7 +435,7 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
   extern __shared__ __align__(16) float S[];
   const int n = a.n;
   const auto wn = tp_weights<PatN>(a);
-  MixB<HOLD ? LMAX + 1 : 1> mb;
+  MixB<HOLD ? LMAX + 1 : 1, BF3> mb;
   if (a.channel_mix) {
     if constexpr (HOLD) load_mix_b(mb, (const float*)a.mixB, a.mix_stride, Kp, Np);
     else mix_geometry(mb, Np);
@@ -359,7 +470,7 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
           for (int c = 0; c < DIM; ++c) {
             // one explicit fma per element: rows of both item halves round alike
             const float gV = ok[h] ? fmaf(a.tp_wnext[c] * gam[h][c], gt[h][0], c == 0 ? gs[h] : 0.0f) : 0.0f;
-            S[((size_t)c * TT + r) * lds_ld + u] = gV;
+            stage_value<BF3, DW, TT>(S, lds_ld, c, r, u, gV);
           }
         } else {
           float gV[DW];
@@ -370,12 +481,12 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
             gV[0] += gs[h];
           }
 #pragma unroll
-          for (int c = 0; c < DW; ++c) S[((size_t)c * TT + r) * lds_ld + u] = gV[c];
+          for (int c = 0; c < DW; ++c) stage_value<BF3, DW, TT>(S, lds_ld, c, r, u, gV[c]);
         }
       }
     }
     __syncthreads();
-    if (a.channel_mix)
+    if (BF3 || a.channel_mix)   // the BF16 x 3 form is only launched with mixing on
       mix_tile<LMAX, DW, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
                                    a.g_tout, e0, E);
     else copy_tile<DW, TT>(S, lds_ld, n, a.g_tout, e0, E);
@@ -593,11 +704,13 @@ inline unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / p
 // walking many tiles with its mixing fragments in registers.
 constexpr unsigned kMixBlocks = 256 * 8;
 
-void mix_dims(int n, int dim, int tt, int* lds_ld, int* Kp, int* Np, size_t* bytes) {
+// Staged tile: FP32 rows of Kp + 4 floats, or (bf3) two BF16 planes with
+// rows of Kp + 8 elements (16-byte aligned, conflict-free 16-byte reads).
+void mix_dims(int n, int dim, int tt, int* lds_ld, int* Kp, int* Np, size_t* bytes, bool bf3 = false) {
   *Kp = ((n + 31) / 32) * 32;
   *Np = ((n + 31) / 32) * 32;
-  *lds_ld = *Kp + 4;
-  *bytes = (size_t)dim * tt * (*lds_ld) * sizeof(float);
+  *lds_ld = bf3 ? *Kp + 8 : *Kp + 4;
+  *bytes = bf3 ? (size_t)2 * dim * tt * (*lds_ld) * sizeof(__bf16) : (size_t)dim * tt * (*lds_ld) * sizeof(float);
 }
 
 template <class K>
@@ -657,22 +770,26 @@ namespace {
 
 template <class Pat, int TT>
 hipError_t launch_tp_mix_pt(const TensorArgs& a, hipStream_t s) {
+  const bool bf3 = a.mix_bf3 && a.channel_mix;
   int ld, Kp, Np;
   size_t bytes;
-  mix_dims(a.n, Pat::DOUT, TT, &ld, &Kp, &Np, &bytes);
+  mix_dims(a.n, Pat::DOUT, TT, &ld, &Kp, &Np, &bytes, bf3);
   // one tile per block: the tensor-product phase's load latency is hidden by
   // many resident blocks rather than by a tile loop
   const unsigned grid = blocks(a.E, TT);
-  return launch_lds(k_tp_mix<Pat, TT>, grid, bytes, s, a, ld, Kp, Np);
+  if (bf3) return launch_lds(k_tp_mix<Pat, TT, true>, grid, bytes, s, a, ld, Kp, Np);
+  return launch_lds(k_tp_mix<Pat, TT, false>, grid, bytes, s, a, ld, Kp, Np);
 }
 
 template <class PatN, int TT>
 hipError_t launch_mix_adjoint_pt(const TensorArgs& a, hipStream_t s) {
+  const bool bf3 = a.mix_bf3 && a.channel_mix;
   int ld, Kp, Np;
   size_t bytes;
-  mix_dims(a.n, PatN::DIN, TT, &ld, &Kp, &Np, &bytes);
+  mix_dims(a.n, PatN::DIN, TT, &ld, &Kp, &Np, &bytes, bf3);
   const unsigned grid = std::min<unsigned>(blocks(a.E, TT), kMixBlocks);
-  return launch_lds(k_mix_adjoint<PatN, TT>, grid, bytes, s, a, ld, Kp, Np);
+  if (bf3) return launch_lds(k_mix_adjoint<PatN, TT, true>, grid, bytes, s, a, ld, Kp, Np);
+  return launch_lds(k_mix_adjoint<PatN, TT, false>, grid, bytes, s, a, ld, Kp, Np);
 }
 
 template <class Pat, int G>
