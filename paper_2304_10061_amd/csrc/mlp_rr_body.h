@@ -690,10 +690,13 @@ void k_rr_bwd(MlpArgs a) {
 
   // 1. G = g_x + g_head @ W_head^T -> g_store rows, in K chunks.  With the
   // activations stored by the forward pass, the last chunk's epilogue also
-  // does step 3 below on the G it holds (and the two-body kind, which needs
-  // G nowhere else, does not store it).
+  // does step 3 below on the G it holds, and the two-body kind, which needs
+  // G nowhere else, neither stores it nor passes the partial sums between
+  // chunks through memory: they stay in the wave's (then unused) LDS area in
+  // BF16, the precision of the operand G then becomes.
   void* const zs = a.act_store ? a.act_store : a.act_scratch;
   const bool fused = a.act_store != nullptr;
+  const bool lds_partial = fused && KIND == kTwoBody;
   float gu[kNE];
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) gu[nb] = 0.0f;
@@ -710,10 +713,20 @@ void k_rr_bwd(MlpArgs a) {
           for (int b = 0; b < NBP; ++b)
 #pragma unroll
             for (int nb = 0; nb < kNE; ++nb) {
-              if constexpr (c == 0)
-                acc[b][nb] = a.g_x ? load_c(a.g_x, (uint32_t)D, 0, p * NBP + b, R.ec[nb], g) : zero16();
-              else
-                acc[b][nb] = load_G(p * NBP + b, nb);
+              const int mb = p * NBP + b;
+              if constexpr (c == 0) {
+                acc[b][nb] = a.g_x ? load_c(a.g_x, (uint32_t)D, 0, mb, R.ec[nb], g) : zero16();
+              } else if (lds_partial) {
+                const bf16x8 q0 = area[(2 * mb * kNE + nb) * 64 + lane];
+                const bf16x8 q1 = area[((2 * mb + 1) * kNE + nb) * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                  acc[b][nb][j] = (float)q0[j];
+                  acc[b][nb][8 + j] = (float)q1[j];
+                }
+              } else {
+                acc[b][nb] = load_G(mb, nb);
+              }
             }
         },
         [&](int p, f32x16 (&acc)[NBP][kNE]) {
@@ -723,7 +736,12 @@ void k_rr_bwd(MlpArgs a) {
 #pragma unroll
             for (int nb = 0; nb < kNE; ++nb) {
               const int mb = p * NBP + b;
-              if (R.ok[nb] && !(last && KIND == kTwoBody)) store_c(gst, (uint32_t)D, 0, mb, R.ec[nb], g, acc[b][nb]);
+              if (!last && lds_partial) {   // partial sums for the next chunk
+                stash(area, 2 * mb, nb, lane, bform(acc[b][nb], 0, Ident()));
+                stash(area, 2 * mb + 1, nb, lane, bform(acc[b][nb], 1, Ident()));
+              } else if (R.ok[nb] && !(last && KIND == kTwoBody)) {
+                store_c(gst, (uint32_t)D, 0, mb, R.ec[nb], g, acc[b][nb]);
+              }
               if (last) {
                 const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
                 const bf16x8 h0 = z[0], h1 = z[kZHalf];
