@@ -284,6 +284,31 @@ def tensor_flops_per_edge(mc, info):
     return out
 
 
+def P_describe(mc):
+    """allegro_describe of the model configuration (None without the library)."""
+    try:
+        import paper_2304_10061_amd as P
+        return P.describe(P.config_from(mc))
+    except Exception:
+        return None
+
+
+def tensor_bytes_per_unit(mc):
+    """Algorithmic HBM bytes per edge of one launch unit of each tensor-track
+    kind, from the staged per-unit figures: a non-final tensor product (or its
+    adjoint) reads and writes one w x n FP32 feature row per edge (4 * 2 w n
+    bytes; 4.6 KB for l_max 2, n 64); an environment scatter (or its adjoint)
+    reads the (l_max + 1) n weights and the dim harmonics of each edge; the
+    final layer's product reads one w x n row.  Per-centre rows (which stay
+    in cache) are not counted."""
+    n, D = mc.n_tensor, (mc.l_max + 1) ** 2
+    w = D                                           # natural-parity features (two-layer models)
+    tp = 4 * 2 * w * n
+    env = 4 * ((mc.l_max + 1) * n + D)
+    return {"env": env, "tp_mix": tp, "mix_adjoint": tp, "tp_env_adjoint": tp + env,
+            "tp_env_adjoint_final": 4 * w * n + env}
+
+
 def tensor_symbols(mc):
     """Kernel symbols (as rocprofv3 prints them) behind each timed tensor-track
     launch kind of one step: the layers' patterns TpPattern<l_max, input kind,
@@ -637,6 +662,28 @@ def main():
                 "staged_io_bytes_per_launch": io_bytes / launches,
                 "hbm_frac_staged_io": io_bytes / launches / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                 "mfma_counters": mfma_busy_counters([sym])}
+    elif dom in tensor_bytes_per_unit(mc) and mc.n_layers == 2:
+        # a staged tensor-track unit: HBM-bound (its FP32 arithmetic is ~25 flop per
+        # byte moved, near the FP32 ridge), measured against 8 TB/s on the
+        # algorithmic bytes of one launch unit
+        launches = max(1, bf["kernel_launches"].get(dom, 1))
+        avg_ms = kms[dom] / launches
+        unit_bytes = tensor_bytes_per_unit(mc)[dom] * bf["edges"]
+        achieved = unit_bytes / (avg_ms * 1e-3) / 1e9
+        syms = tensor_symbols(mc).get(dom, [])
+        per = [traffic_per_launch(sym) for sym in syms]
+        traffic = sum(per) / launches if syms and all(v is not None for v in per) else None
+        roof = {"kernel": dom, "symbols": syms, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "bytes_per_launch": unit_bytes, "avg_launch_ms": avg_ms}
+        if traffic is not None:
+            roof["hbm_frac_traffic"] = traffic / (avg_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
+        info = P_describe(mc)
+        if info is not None:
+            tfl = tensor_flops_per_edge(mc, info).get(dom)
+            if tfl:
+                # the same unit against the FP32 vector roof
+                roof["alu_frac"] = tfl * bf["edges"] / (avg_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
                 "frac": None, "traffic": None}
