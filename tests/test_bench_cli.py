@@ -41,6 +41,22 @@ def test_tensor_flop_counts():
     assert f["tp_env_adjoint_final"] == 2 * 9 * 32 + 4 * 9 * 32
 
 
+def test_tensor_unit_bytes():
+    """Algorithmic bytes per edge of the tensor-track units on the protein
+    box (l_max 2, n 64): a staged non-final tensor product moves one 9 x 64
+    FP32 row in and one out (4,608 B, the ~4.6 KB of the staged estimate),
+    an environment scatter the 3 x 64 weights and 9 harmonics (804 B, ~0.8
+    KB); the tensor adjoint unit is one of each."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    b = bench.tensor_bytes_per_unit(W.model_config(3))
+    assert b["tp_mix"] == 4 * 2 * 9 * 64 == 4608
+    assert b["env"] == 4 * (3 * 64 + 9) == 804
+    assert b["tp_env_adjoint"] == 4608 + 804
+    assert b["tp_env_adjoint_final"] == 4 * 9 * 64 + 804
+
+
 def test_tensor_symbols_name_profiled_kernels():
     """The kernel symbols the deep roofline sums are the ones the committed
     kernel-trace summary of that workload lists."""
