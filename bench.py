@@ -544,12 +544,14 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
     # steps in one call: the list is rebuilt inside the steps whenever an
     # atom has moved half the skin since the last build
     use_graph = kind == "clusters"
+    vir = torch.zeros((n_total_steps, 9), dtype=torch.float64, device=dev)
     _, over_warm = m.md_run_all(warmup, dt_fs, mass, pos, vel, F, sp, thermo=thermo[:warmup], init_forces=True,
-                                use_graph=use_graph)
+                                use_graph=use_graph, virial=vir[:warmup])
     captures_warm = m.md_stats()[0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    disp, over_timed = m.md_run_all(steps, dt_fs, mass, pos, vel, F, sp, thermo=thermo[warmup:], use_graph=use_graph)
+    disp, over_timed = m.md_run_all(steps, dt_fs, mass, pos, vel, F, sp, thermo=thermo[warmup:], use_graph=use_graph,
+                                    virial=vir[warmup:])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     captures, capacity, dev_rebuild, rebuilds = m.md_stats()
@@ -573,6 +575,9 @@ def md_workload(kind, steps, warmup, dt_fs, precision=HEADLINE_PREC):
         "peak_hbm_GB": (free0 - free1) / 1e9,
         "library_workspace_GB": m.workspace_bytes() / 1e9,
         "energy_drift_per_atom": float((etot[-1] - etot[0]) / nl),
+        # per-step FP64 virial (eV): its trace at the last step and the mean over the timed steps
+        "virial_trace_last_step": float(np.trace(vir[-1].cpu().numpy().reshape(3, 3))),
+        "virial_trace_mean_timed": float(np.mean([np.trace(r.reshape(3, 3)) for r in vir[warmup:].cpu().numpy()])),
         "energy_fluct_per_atom": float(np.std(etot) / nl),
         "species_energy_scale": MD_SIGMA,
         "neighbor_rebuilds_timed_last_call": int(rebuilds), "rebuilds_on_device": bool(dev_rebuild),

@@ -364,6 +364,9 @@ int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const 
  *                forces at the final positions
  *   species      dev [n_total] int32
  *   thermo       dev [2 n_steps] double or NULL: per step (E_pot, E_kin) in eV
+ *   virial       dev [9 n_steps] double or NULL: per step the virial
+ *                W = -sum_e r_e (x) dE/dr_e (row-major 3x3, eV) at that step's
+ *                positions, in FP64 as allegro_energy_forces reports it
  *   use_graph    1 = run the steps as replays of one captured HIP graph
  *   max_disp     host, receives the largest centre displacement since the
  *                last neighbour build (may be NULL)
@@ -372,12 +375,12 @@ int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const 
  * the capacity: pos, vel and forces then hold the state after *steps_done
  * steps, the capacity has been regrown and the list rebuilt there, and
  * calling again for the remaining steps continues the same trajectory (thermo
- * rows from step *steps_done on are not valid).  Synchronises the stream at
+ * and virial rows from step *steps_done on are not valid).  Synchronises the stream at
  * the end and returns ALLEGRO_E_NONFINITE (as allegro_check) when a step
  * produced non-finite forces or energies.
  */
 int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos,
-                   double* vel, double* forces, const int32_t* species, double* thermo,
+                   double* vel, double* forces, const int32_t* species, double* thermo, double* virial,
                    int32_t init_forces, int32_t use_graph, void* stream, double* max_disp,
                    int32_t* steps_done);
 

@@ -96,7 +96,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.allegro_set_tiles.restype = ctypes.c_int
     lib.allegro_set_ghosts.argtypes = [vp, i64, i64, vp, vp]
     lib.allegro_set_ghosts.restype = ctypes.c_int
-    lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, i32, i32, vp,
+    lib.allegro_md_run.argtypes = [vp, i32, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp, i32, i32, vp,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     lib.allegro_md_run.restype = ctypes.c_int
     lib.allegro_md_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -321,14 +321,16 @@ class Model:
                                                 of.ctypes.data if ow.size else None))
 
     def md_run(self, n_steps, dt_fs, masses, pos, vel, forces, species, thermo=None, init_forces=False,
-               use_graph=True, stream=None, want_max_disp=True):
+               use_graph=True, stream=None, want_max_disp=True, virial=None):
         """Velocity Verlet on the device; returns the max displacement since the
-        last neighbour build (or None).  Raises AllegroError (ALLEGRO_E_CAPACITY
-        with .steps_done set) when an in-graph rebuild outgrew the capacity."""
+        last neighbour build (or None).  thermo [n_steps][2] and virial
+        [n_steps][9] (cuda float64, optional) receive (E_pot, E_kin) and the
+        virial of each step.  Raises AllegroError (ALLEGRO_E_CAPACITY with
+        .steps_done set) when an in-graph rebuild outgrew the capacity."""
         md = ctypes.c_double(0.0)
         done = ctypes.c_int32(0)
         st = self.lib.allegro_md_run(self.handle, int(n_steps), float(dt_fs), _ptr(masses), _ptr(pos),
-                                     _ptr(vel), _ptr(forces), _ptr(species), _ptr(thermo),
+                                     _ptr(vel), _ptr(forces), _ptr(species), _ptr(thermo), _ptr(virial),
                                      1 if init_forces else 0, 1 if use_graph else 0, _stream(stream),
                                      ctypes.byref(md) if want_max_disp else None, ctypes.byref(done))
         if st != ALLEGRO_OK:
@@ -338,7 +340,7 @@ class Model:
         return md.value if want_max_disp else None
 
     def md_run_all(self, n_steps, dt_fs, masses, pos, vel, forces, species, thermo=None, init_forces=False,
-                   use_graph=True, stream=None, max_overflows=16):
+                   use_graph=True, stream=None, max_overflows=16, virial=None):
         """md_run for n_steps, resuming after each ALLEGRO_E_CAPACITY (the
         library has regrown the list by then); returns (max displacement since
         the last build, number of overflows)."""
@@ -347,7 +349,8 @@ class Model:
             try:
                 d = self.md_run(n_steps - done, dt_fs, masses, pos, vel, forces, species,
                                 thermo=None if thermo is None else thermo[done:], init_forces=init_forces and done == 0,
-                                use_graph=use_graph, stream=stream)
+                                use_graph=use_graph, stream=stream,
+                                virial=None if virial is None else virial[done:])
                 return d, overflows
             except AllegroError as e:
                 if e.status != -3 or overflows >= max_overflows:

@@ -535,7 +535,7 @@ struct AllegroModel {
   int64_t n_ghost = 0, ghost_n_local = 0;
   DevBuf g_owner, g_offset, g_ptr, g_idx; // ghost images and the owner -> ghosts CSR
   DevBuf pos_ref;                         // positions of the centres at the last neighbour build
-  DevBuf md_epot, md_part, md_counter, md_atom_e, tune_forces;
+  DevBuf md_epot, md_part, md_counter, md_atom_e, tune_forces, md_vir;
   DevBuf md_flags;                        // kFlag* slots of the in-graph rebuild
   DevBuf bak_pos, bak_vel, bak_f;         // state at the start of the step that overflowed
   hipStream_t md_stream = nullptr;
@@ -1364,7 +1364,7 @@ void host_rebuild_if_needed(AllegroModel* m, const double* pos, const int32_t* s
 // One velocity-Verlet step; dev: the list is rebuilt on the device when needed
 // and the state at the start of the step is kept until a rebuild overflows.
 void md_step(AllegroModel* m, double dt, const double* masses, double* pos, double* vel, double* forces,
-             const int32_t* species, bool dev, hipStream_t s) {
+             const int32_t* species, bool dev, bool want_virial, hipStream_t s) {
   const int64_t nl = m->n_local, nt = m->n_total;
   int32_t* flags = ptr<int32_t>(m->md_flags);
   if (dev) {
@@ -1377,17 +1377,19 @@ void md_step(AllegroModel* m, double dt, const double* masses, double* pos, doub
     HIP_OK(launch_ghost_refresh(m->n_ghost, nl, ptr<int32_t>(m->g_owner), ptr<double>(m->g_offset), pos, s));
   if (dev) device_rebuild(m, pos, species, s);
   else host_rebuild_if_needed(m, pos, species, s);
-  energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr,
+  double* vir = want_virial ? ptr<double>(m->md_vir) : nullptr;
+  energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, vir, nullptr,
                      ptr<double>(m->md_epot), s, dev);
   if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
   HIP_OK(launch_kick(nl, dt, masses, vel, forces, s));
-  HIP_OK(launch_thermo(nl, masses, vel, ptr<double>(m->md_part), ptr<double>(m->md_epot),
+  HIP_OK(launch_thermo(nl, masses, vel, ptr<double>(m->md_part), ptr<double>(m->md_epot), vir,
                        ptr<ThermoTarget>(m->md_counter), s));
   if (dev) HIP_OK(launch_step_done(flags, s));
 }
 
 void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, double* pos, double* vel,
-                 double* forces, const int32_t* species, double* thermo, int init_forces, int use_graph,
+                 double* forces, const int32_t* species, double* thermo, double* virial, int init_forces,
+                 int use_graph,
                  hipStream_t s, double* max_disp, int32_t* steps_done) {
   if (steps_done) *steps_done = 0;
   if (m->n_local < 0) throw Fail{ALLEGRO_E_STATE, "allegro_neighbors has not been called"};
@@ -1400,6 +1402,8 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
   const bool dev = m->dev_rebuild;
   m->md_epot.ensure(sizeof(double));
   m->md_counter.ensure(sizeof(ThermoTarget));
+  m->md_vir.ensure(9 * sizeof(double));
+  const bool want_virial = virial != nullptr;
   m->md_part.ensure(((std::max<int64_t>(nl, 1) + 255) / 256) * sizeof(double));
   m->md_atom_e.ensure(std::max<int64_t>(nl, 1) * sizeof(double));
   m->md_flags.ensure(kNumFlags * sizeof(int32_t));
@@ -1416,7 +1420,7 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
     energy_forces_impl(m, m->ws, pos, species, ptr<double>(m->md_atom_e), forces, nullptr, nullptr, ptr<double>(m->md_epot), s);
     if (m->n_ghost > 0) HIP_OK(launch_fold(nl, ptr<int32_t>(m->g_ptr), ptr<int32_t>(m->g_idx), forces, s));
   }
-  HIP_OK(launch_set_thermo(ptr<ThermoTarget>(m->md_counter), thermo, n_steps, s));
+  HIP_OK(launch_set_thermo(ptr<ThermoTarget>(m->md_counter), thermo, virial, n_steps, s));
   HIP_OK(launch_fill_i32(flags, 0, kNumFlags, s));
   if (use_graph && dev && n_steps > 0) {
     // one step, neighbour rebuild included, captured once per list layout and
@@ -1428,7 +1432,8 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
                                      (uintptr_t)species, (uintptr_t)m->nbr_version, (uintptr_t)dt_bits,
                                      (uintptr_t)m->md_flags.p, (uintptr_t)m->md_counter.p,
                                      (uintptr_t)m->bak_pos.p, (uintptr_t)m->bak_vel.p, (uintptr_t)m->bak_f.p,
-                                     (uintptr_t)m->md_part.p, (uintptr_t)m->md_atom_e.p};
+                                     (uintptr_t)m->md_part.p, (uintptr_t)m->md_atom_e.p, (uintptr_t)m->md_vir.p,
+                                     (uintptr_t)want_virial};
     if (!m->md_stream) HIP_OK(hipStreamCreateWithFlags(&m->md_stream, hipStreamNonBlocking));
     if (!m->md_ev[0]) {
       HIP_OK(hipEventCreateWithFlags(&m->md_ev[0], hipEventDisableTiming));
@@ -1440,7 +1445,7 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
       release_graph(m);
       HIP_OK(hipStreamBeginCapture(m->md_stream, hipStreamCaptureModeRelaxed));
       try {
-        md_step(m, dt, masses, pos, vel, forces, species, true, m->md_stream);
+        md_step(m, dt, masses, pos, vel, forces, species, true, want_virial, m->md_stream);
       } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(m->md_stream, &g);
@@ -1457,7 +1462,7 @@ void md_run_impl(AllegroModel* m, int n_steps, double dt, const double* masses, 
     HIP_OK(hipEventRecord(m->md_ev[1], m->md_stream));
     HIP_OK(hipStreamWaitEvent(s, m->md_ev[1], 0));
   } else {
-    for (int k = 0; k < n_steps; ++k) md_step(m, dt, masses, pos, vel, forces, species, dev, s);
+    for (int k = 0; k < n_steps; ++k) md_step(m, dt, masses, pos, vel, forces, species, dev, want_virial, s);
   }
   m->timing = was_timing;
   int32_t done = n_steps;
@@ -1662,11 +1667,11 @@ int allegro_set_ghosts(AllegroModel* m, int64_t n_local, int64_t n_ghost, const 
 }
 
 int allegro_md_run(AllegroModel* m, int32_t n_steps, double dt_fs, const double* masses, double* pos, double* vel,
-                   double* forces, const int32_t* species, double* thermo, int32_t init_forces, int32_t use_graph,
-                   void* stream, double* max_disp, int32_t* steps_done) {
+                   double* forces, const int32_t* species, double* thermo, double* virial, int32_t init_forces,
+                   int32_t use_graph, void* stream, double* max_disp, int32_t* steps_done) {
   if (!m) return ALLEGRO_E_INVAL;
   try {
-    md_run_impl(m, n_steps, dt_fs, masses, pos, vel, forces, species, thermo, init_forces, use_graph,
+    md_run_impl(m, n_steps, dt_fs, masses, pos, vel, forces, species, thermo, virial, init_forces, use_graph,
                 (hipStream_t)stream, max_disp, steps_done);
     return ALLEGRO_OK;
   } catch (const Fail& f) {

@@ -341,14 +341,16 @@ hipError_t launch_ghost_refresh(int64_t n_ghost, int64_t n_local, const int32_t*
                                 double* x, hipStream_t s);
 hipError_t launch_fold(int64_t n_local, const int32_t* gptr, const int32_t* gidx, double* f, hipStream_t s);
 // Where MD steps write their energies: rows [cap][2], the next row `counter`.
+// Per-step virial rows [cap][9] too, when set.
 struct ThermoTarget {
   double* rows;
   int64_t cap;
   int64_t counter;
+  double* vrows;
 };
 hipError_t launch_thermo(int64_t n, const double* m, const double* v, double* part, const double* epot,
-                         ThermoTarget* target, hipStream_t s);
-hipError_t launch_set_thermo(ThermoTarget* target, double* rows, int64_t cap, hipStream_t s);
+                         const double* vir, ThermoTarget* target, hipStream_t s);
+hipError_t launch_set_thermo(ThermoTarget* target, double* rows, double* vrows, int64_t cap, hipStream_t s);
 hipError_t launch_disp_check(int64_t n, const double* x, const double* x0, double r2, int32_t* flags,
                              hipStream_t s);
 hipError_t launch_copy_f64_flag(double* dst, const double* src, int64_t n, const int32_t* flags, int slot, int want,

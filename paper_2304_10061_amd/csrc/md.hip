@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_ke_partial(int64_t n, const double* __r
 // counter; the destination lives in device memory so that a captured step
 // does not depend on it.
 __global__ __launch_bounds__(256) void k_thermo(const double* __restrict__ part, int nb,
-                                                const double* __restrict__ epot, ThermoTarget* __restrict__ t) {
+                                                const double* __restrict__ epot, const double* __restrict__ vir,
+                                                ThermoTarget* __restrict__ t) {
   __shared__ double red[256];
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
@@ -92,13 +93,16 @@ __global__ __launch_bounds__(256) void k_thermo(const double* __restrict__ part,
       t->rows[2 * c] = *epot;
       t->rows[2 * c + 1] = 0.5 * kKE * red[0];
     }
+    if (vir && t->vrows && c < t->cap)
+      for (int k = 0; k < 9; ++k) t->vrows[9 * c + k] = vir[k];
     t->counter = c + 1;
   }
 }
 
-__global__ void k_set_thermo(ThermoTarget* t, double* rows, int64_t cap) {
+__global__ void k_set_thermo(ThermoTarget* t, double* rows, double* vrows, int64_t cap) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     t->rows = rows;
+    t->vrows = vrows;
     t->cap = cap;
     t->counter = 0;
   }
@@ -235,15 +239,15 @@ hipError_t launch_fold(int64_t n_local, const int32_t* gptr, const int32_t* gidx
 }
 
 hipError_t launch_thermo(int64_t n, const double* m, const double* v, double* part, const double* epot,
-                         ThermoTarget* target, hipStream_t s) {
+                         const double* vir, ThermoTarget* target, hipStream_t s) {
   const int nb = (int)blocks(n > 0 ? n : 1);
   hipLaunchKernelGGL(k_ke_partial, dim3(nb), dim3(256), 0, s, n, m, v, part);
-  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(256), 0, s, (const double*)part, nb, epot, target);
+  hipLaunchKernelGGL(k_thermo, dim3(1), dim3(256), 0, s, (const double*)part, nb, epot, vir, target);
   return hipGetLastError();
 }
 
-hipError_t launch_set_thermo(ThermoTarget* target, double* rows, int64_t cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_thermo, dim3(1), dim3(64), 0, s, target, rows, cap);
+hipError_t launch_set_thermo(ThermoTarget* target, double* rows, double* vrows, int64_t cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_thermo, dim3(1), dim3(64), 0, s, target, rows, vrows, cap);
   return hipGetLastError();
 }
 

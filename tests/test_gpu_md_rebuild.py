@@ -120,6 +120,33 @@ def test_host_rebuilds_of_chunked_lists_match_device_rebuilds():
         assert np.abs(x - y).max() <= 1e-9 * max(1.0, np.abs(x).max())
 
 
+def test_per_step_virial_rows():
+    """The per-step virial of allegro_md_run: graph replays give the eager
+    rows bit for bit, and the last row is the virial allegro_energy_forces
+    reports at the final positions (the last half kick moves no atom)."""
+    mc, s, w = W.workload(2)
+    v0 = W.maxwell_boltzmann(s.masses, 300.0, W.seeds(2)[4])
+    rows = []
+    for use_graph in (False, True):
+        m = _model(mc, w, FP32, skin=0.1, hint=160000)
+        pos, sp, vel, masses, F = _state(s, v0)
+        m.neighbors(pos, sp, s.cell, s.pbc)
+        vir = torch.full((12, 9), float("nan"), dtype=torch.float64, device=pos.device)
+        m.md_run(12, 0.5, masses, pos, vel, F, sp, virial=vir, init_forces=True, use_graph=use_graph)
+        rows.append(_host(vir)[0])
+        assert m.md_stats()[3] >= 1
+        F2 = torch.empty_like(F)
+        v_now = torch.empty(9, dtype=torch.float64, device=pos.device)
+        m.energy_forces(pos, sp, F2, virial=v_now)
+        last, ef = _host(vir[-1], v_now)
+        assert np.allclose(last, ef, rtol=1e-12, atol=1e-12)
+    assert np.all(np.isfinite(rows[0]))
+    assert np.array_equal(rows[0], rows[1])
+    # an invariant model's virial is symmetric (FP32 sums)
+    W3 = rows[0].reshape(-1, 3, 3)
+    assert np.abs(W3 - W3.transpose(0, 2, 1)).max() <= 1e-5 * np.abs(W3).max()
+
+
 @pytest.mark.parametrize("prec", [FP32, MIXED], ids=["fp32", "bf16_mixed"])
 def test_capacity_overflow_regrows_and_resumes_on_the_same_trajectory(prec):
     """The list is first built on the unjittered lattice (about 23 neighbours
