@@ -120,6 +120,64 @@ def test_host_rebuilds_of_chunked_lists_match_device_rebuilds():
         assert np.abs(x - y).max() <= 1e-9 * max(1.0, np.abs(x).max())
 
 
+def test_batched_clusters_graph_rebuilds_equal_eager():
+    """Uneven non-periodic clusters in one batched list (each system binned
+    in its own slot of the cell grid), rebuilt on the device inside the step:
+    graph replays give the eager steps' bits, and the rebuilt lists keep
+    every system's pairs to itself."""
+    mc = W.model_config(5)
+    w = W.make_weights(mc, np.random.default_rng(4))
+    b = W.clusters(12, 21, lo=20, hi=300)
+    v0 = W.maxwell_boltzmann(b.masses, 300.0, np.random.default_rng(22))
+    out, stats = [], []
+    for use_graph in (False, True):
+        m = _model(mc, w, MIXED, skin=0.1, hint=4 * 30 * b.n_local)
+        pos, sp, vel, masses, F = _state(b, v0)
+        m.neighbors_batched(b.atom_offsets, pos, sp)
+        thermo = torch.zeros((24, 2), dtype=torch.float64, device=pos.device)
+        m.md_run(24, 0.5, masses, pos, vel, F, sp, thermo=thermo, init_forces=True, use_graph=use_graph)
+        stats.append(m.md_stats())
+        ci, nj, _ = m.copy_edges()
+        ci, nj = _host(ci, nj)
+        sysid = np.searchsorted(b.atom_offsets, np.arange(b.n_local), side="right") - 1
+        assert np.array_equal(sysid[ci], sysid[nj])
+        out.append(_host(pos, vel, F, thermo))
+    for a_, b_ in zip(out[0], out[1]):
+        assert np.array_equal(a_, b_)
+    assert stats[0][2] == 1 and stats[0][3] >= 2 and stats[0][3] == stats[1][3]
+    assert stats[1][0] == 1
+
+
+def test_ghost_shell_with_device_rebuilds_matches_periodic_box():
+    """One GPU's share with its ghost shell (non-periodic, ghosts following
+    their owners) against the periodic box, with a 0.1 A skin so that the
+    device rebuilds the lists during the run: the same trajectory up to FP32
+    summation order."""
+    mc = W.model_config(4)
+    w = W.make_weights(mc, np.random.default_rng(3))
+    base = W.jittered_lattice_box(1000, (1000 / 0.1) ** (1 / 3), 0.5, W.PROTEIN_MIX, 31)
+    g = W.ghost_shell(base, 6.0)
+    v0 = W.maxwell_boltzmann(base.masses, 300.0, W.seeds(4)[4])
+    res = []
+    for sysm in (base, g):
+        m = _model(mc, w, FP32, skin=0.1, hint=60 * sysm.n_total)
+        pos, sp = to_dev(sysm)
+        dev = pos.device
+        vel = torch.as_tensor(v0, dtype=torch.float64, device=dev)
+        masses = torch.as_tensor(base.masses, dtype=torch.float64, device=dev)
+        F = torch.zeros((sysm.n_total, 3), dtype=torch.float64, device=dev)
+        if sysm is g:
+            own = g.ghost_owner
+            m.set_ghosts(base.n_local, own, g.pos[base.n_local:] - base.pos[own])
+        m.neighbors(pos, sp, sysm.cell, sysm.pbc, sysm.n_local)
+        thermo = torch.zeros((20, 2), dtype=torch.float64, device=dev)
+        m.md_run(20, 0.5, masses, pos, vel, F, sp, thermo=thermo, init_forces=True, use_graph=True)
+        assert m.md_stats()[2] == 1 and m.md_stats()[3] >= 2
+        res.append((_host(pos)[0][:base.n_local], _host(thermo)[0]))
+    assert np.abs(res[0][0] - res[1][0]).max() < 1e-6
+    assert np.abs(res[0][1] - res[1][1]).max() < 1e-4
+
+
 def test_per_step_virial_rows():
     """The per-step virial of allegro_md_run: graph replays give the eager
     rows bit for bit, and the last row is the virial allegro_energy_forces
