@@ -700,6 +700,7 @@ void k_rr_bwd(MlpArgs a) {
   float gu[kNE];
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) gu[nb] = 0.0f;
+  bf16x8 hz[NBP][kNE][2];   // the pass's stored h, requested before its MFMAs
   static_for<0, NCH>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     constexpr int KC = KH - c * kHeadChunk < kHeadChunk ? KH - c * kHeadChunk : kHeadChunk;
@@ -714,6 +715,11 @@ void k_rr_bwd(MlpArgs a) {
 #pragma unroll
             for (int nb = 0; nb < kNE; ++nb) {
               const int mb = p * NBP + b;
+              if (c == NCH - 1 && fused) {
+                const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
+                hz[b][nb][0] = z[0];
+                hz[b][nb][1] = z[kZHalf];
+              }
               if constexpr (c == 0) {
                 acc[b][nb] = a.g_x ? load_c(a.g_x, (uint32_t)D, 0, mb, R.ec[nb], g) : zero16();
               } else if (lds_partial) {
@@ -743,8 +749,7 @@ void k_rr_bwd(MlpArgs a) {
                 store_c(gst, (uint32_t)D, 0, mb, R.ec[nb], g, acc[b][nb]);
               }
               if (last) {
-                const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 1, mb, nb, lane);
-                const bf16x8 h0 = z[0], h1 = z[kZHalf];
+                const bf16x8 h0 = hz[b][nb][0], h1 = hz[b][nb][1];
                 f32x16 t;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -877,13 +882,31 @@ void k_rr_bwd_final(MlpArgs a) {
   };
   void* const zs = a.act_store ? a.act_store : a.act_scratch;
   if (a.act_store) {
-    // the forward pass stored the last hidden layer's pre-activations and a . v
+    // the forward pass stored the last hidden layer's pre-activations and a . v;
+    // the next block's are requested while this block's are used
+    bf16x8 zn[kNE][2];
+#pragma unroll
+    for (int nb = 0; nb < kNE; ++nb) {
+      const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 2, 0, nb, lane);
+      zn[nb][0] = z[0];
+      zn[nb][1] = z[kZHalf];
+    }
     for (int mb = 0; mb < MBD; ++mb) {
       const f32x16 v = load_c(a.fold_v, 0u, 0, mb, 0, g);
+      bf16x8 zc[kNE][2];
 #pragma unroll
       for (int nb = 0; nb < kNE; ++nb) {
-        const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 2, mb, nb, lane);
-        const bf16x8 z0 = z[0], z1 = z[kZHalf];
+        zc[nb][0] = zn[nb][0];
+        zc[nb][1] = zn[nb][1];
+        if (mb + 1 < MBD) {
+          const bf16x8* z = zslot<NL, MBD>(zs, tile, NL - 2, mb + 1, nb, lane);
+          zn[nb][0] = z[0];
+          zn[nb][1] = z[kZHalf];
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < kNE; ++nb) {
+        const bf16x8 z0 = zc[nb][0], z1 = zc[nb][1];
         f32x16 t;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
