@@ -576,7 +576,9 @@ template <int D, int NL, bool SPLIT>
 __device__ __forceinline__ void back_layer(void* scratch, int tile, int lane, int l, const bf16x8 (&in)[kNE][D / 16],
                                            const void* W, bf16x8* area) {
   constexpr int MBD = D / 32, NBP = rr_nbp(MBD);
-  f32x16 zz[NBP][kNE];
+  // the pass's pre-activations are requested before its MFMAs and turned
+  // into silu'(z) after them
+  bf16x8 zr[NBP][kNE][2];
   gemm<D / 16, MBD, SPLIT>(
       in, W,
       [&](int p, f32x16 (&acc)[NBP][kNE]) {
@@ -586,12 +588,8 @@ __device__ __forceinline__ void back_layer(void* scratch, int tile, int lane, in
 #pragma unroll
           for (int nb = 0; nb < kNE; ++nb) {
             const bf16x8* z = zslot<NL, MBD>(scratch, tile, l, p * NBP + b, nb, lane);
-            const bf16x8 z0 = z[0], z1 = z[kZHalf];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              zz[b][nb][j] = silu_grad((float)z0[j]);
-              zz[b][nb][8 + j] = silu_grad((float)z1[j]);
-            }
+            zr[b][nb][0] = z[0];
+            zr[b][nb][1] = z[kZHalf];
           }
       },
       [&](int p, f32x16 (&acc)[NBP][kNE]) {
@@ -601,7 +599,10 @@ __device__ __forceinline__ void back_layer(void* scratch, int tile, int lane, in
           for (int nb = 0; nb < kNE; ++nb) {
             f32x16 t;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) t[i] = acc[b][nb][i] * zz[b][nb][i];
+            for (int j = 0; j < 8; ++j) {
+              t[j] = acc[b][nb][j] * silu_grad((float)zr[b][nb][0][j]);
+              t[8 + j] = acc[b][nb][8 + j] * silu_grad((float)zr[b][nb][1][j]);
+            }
             const int mb = p * NBP + b;
             stash(area, 2 * mb, nb, lane, bform(t, 0, Ident()));
             stash(area, 2 * mb + 1, nb, lane, bform(t, 1, Ident()));
