@@ -702,6 +702,7 @@ void k_rr_bwd(MlpArgs a) {
 #pragma unroll
   for (int nb = 0; nb < kNE; ++nb) gu[nb] = 0.0f;
   bf16x8 hz[NBP][kNE][2];   // the pass's stored h, requested before its MFMAs
+  f32x16 gxp[NBP][kNE];     // the pass's g_x rows (first chunk), added after its MFMAs
   static_for<0, NCH>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     constexpr int KC = KH - c * kHeadChunk < kHeadChunk ? KH - c * kHeadChunk : kHeadChunk;
@@ -722,7 +723,8 @@ void k_rr_bwd(MlpArgs a) {
                 hz[b][nb][1] = z[kZHalf];
               }
               if constexpr (c == 0) {
-                acc[b][nb] = a.g_x ? load_c(a.g_x, (uint32_t)D, 0, mb, R.ec[nb], g) : zero16();
+                acc[b][nb] = zero16();
+                if (a.g_x) gxp[b][nb] = load_c(a.g_x, (uint32_t)D, 0, mb, R.ec[nb], g);
               } else if (lds_partial) {
                 const bf16x8 q0 = area[(2 * mb * kNE + nb) * 64 + lane];
                 const bf16x8 q1 = area[((2 * mb + 1) * kNE + nb) * 64 + lane];
@@ -743,6 +745,11 @@ void k_rr_bwd(MlpArgs a) {
 #pragma unroll
             for (int nb = 0; nb < kNE; ++nb) {
               const int mb = p * NBP + b;
+              if constexpr (c == 0) {
+                if (a.g_x)
+#pragma unroll
+                  for (int i = 0; i < 16; ++i) acc[b][nb][i] += gxp[b][nb][i];
+              }
               if (!last && lds_partial) {   // partial sums for the next chunk
                 stash(area, 2 * mb, nb, lane, bform(acc[b][nb], 0, Ident()));
                 stash(area, 2 * mb + 1, nb, lane, bform(acc[b][nb], 1, Ident()));
