@@ -319,14 +319,18 @@ def tensor_symbols(mc):
     kin = [1 if (L == 0 or L == nl - 1) else 2 for L in range(nl)]
     kout = [0 if L == nl - 1 else (2 if nl >= 3 and L < nl - 2 else 1) for L in range(nl)]
     pat = lambda L: f"TpPattern<{lm}, {kin[L]}, {kout[L]}>"
-    out = {"tp_env_adjoint_final": [f"k_tp_adjoint_gamma<{pat(nl - 1)}, {G}>",
-                                    f"k_tp_adjoint_edges<{pat(nl - 1)}, {G}, {'true' if nl == 1 else 'false'}>"]}
+    a0 = lambda L: "true" if L == 0 else "false"
+    # the edge pass adds to dE/dY rows written before it: every layer but the
+    # last (run first), and the last too when it is the rank-1 first layer
+    keep = lambda L: "true" if (L < nl - 1 or L == 0) else "false"
+    out = {"tp_env_adjoint_final": [f"k_tp_adjoint_gamma<{pat(nl - 1)}, {G}, {a0(nl - 1)}>",
+                                    f"k_tp_adjoint_edges<{pat(nl - 1)}, {G}, {keep(nl - 1)}>"]}
     if nl > 1:
         out["tp_mix"] = [f"k_tp_mix<{pat(L)}, 16>" for L in range(nl - 1)]
         out["mix_adjoint"] = [f"k_mix_adjoint<{pat(L + 1)}, 16>" for L in range(nl - 1)]
         out["tp_env_adjoint"] = [s for L in range(nl - 1)
-                                 for s in (f"k_tp_adjoint_gamma<{pat(L)}, {G}>",
-                                           f"k_tp_adjoint_edges<{pat(L)}, {G}, {'true' if L == 0 else 'false'}>")]
+                                 for s in (f"k_tp_adjoint_gamma<{pat(L)}, {G}, {a0(L)}>",
+                                           f"k_tp_adjoint_edges<{pat(L)}, {G}, {keep(L)}>")]
     return out
 
 

@@ -500,65 +500,131 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
 // k_tp_adjoint_gamma (one wavefront per centre; lane = channel u, and with
 // n < 64 the G = 64/n lane groups take interleaved edges) accumulates
 //   dE/dGamma_i[b][u] = sum_{e in N(i)} sum_{a,c} W[a][b][c] V_e[a][u] dE/dT_e[c][u]
-// in registers and writes it once per centre (without the factor c).
-//
-// k_tp_adjoint_edges (edge-parallel; G edges per wavefront step, each wave a
-// contiguous run of edges) then produces the per-edge gradients:
-//   dE/dw_e[l][u] = c sum_{b: l(b)=l} dE/dGamma_i[b][u] Y_e[b]
-//   dE/dY_e[b]   += c sum_u dE/dGamma_i[b][u] w_e[l(b)][u]
-// and, when V_e = a0_e[l(a)][u] Y_e[a] (first layer),
+// in registers and writes it once per centre (without the factor c).  When
+// V_e = a0_e[l(a)][u] Y_e[a] (first layer) the same pass, which already holds
+// each edge's dE/dT_e, a0_e and Y_e, also forms the per-edge terms that need
+// only the centre's Gamma_i:
 //   dE/dV_e[a][u] = sum_{b,c} W[a][b][c] Gamma_i[b][u] dE/dT_e[c][u]
 //   dE/da0_e[l][u] = sum_{a: l(a)=l} dE/dV_e[a][u] Y_e[a]
-//   dE/dY_e[a]   += sum_u dE/dV_e[a][u] a0_e[l(a)][u].
-// (For later layers dE/dV_e is formed by the previous layer's mixing
-// adjoint.)  The sums over channels use DPP lane moves within each group of n
-// lanes, in a fixed order: deterministic.
+//   dE/dY_e[a]   += sum_u dE/dV_e[a][u] a0_e[l(a)][u],
+// so that dE/dT_e is read once.  (For later layers dE/dV_e is formed by the
+// previous layer's mixing adjoint.)
+//
+// k_tp_adjoint_edges (edge-parallel; G edges per wavefront step, each wave a
+// contiguous run of edges) then produces the per-edge gradients that need
+// dE/dGamma_i:
+//   dE/dw_e[l][u] = c sum_{b: l(b)=l} dE/dGamma_i[b][u] Y_e[b]
+//   dE/dY_e[b]   += c sum_u dE/dGamma_i[b][u] w_e[l(b)][u].
+// The sums over channels use DPP lane moves within each group of n lanes, in
+// a fixed order: deterministic.
 
 // Edges per lane group whose loads are issued together: as many as fit a
 // register budget of about 80 values.
-template <class Pat>
-constexpr int kGammaBatch = 4 * (Pat::DIN + Pat::DOUT) <= 80 ? 4 : (2 * (Pat::DIN + Pat::DOUT) <= 80 ? 2 : 1);
+template <class Pat, bool A0>
+constexpr int kGammaBatch = A0 ? (4 * (Pat::Lmax + 1 + Pat::DIM + Pat::DOUT) <= 80 ? 4 : 2)
+                               : (4 * (Pat::DIN + Pat::DOUT) <= 80 ? 4 : (2 * (Pat::DIN + Pat::DOUT) <= 80 ? 2 : 1));
 
-template <class Pat, int G>
+// A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a]; the pass
+// then also writes dE/da0_e and its part of dE/dY_e.
+template <class Pat, int G, bool A0>
 __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
-  constexpr int KB = kGammaBatch<Pat>;
+  constexpr int GYW = gy_width(LMAX);
+  constexpr int KB = kGammaBatch<Pat, A0>;
   constexpr int n = kWave / G;
   const int lane = lane_id();
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.n_centres) return;
   const int u = lane & (n - 1), g = lane / n;
-  const auto w = tp_weights<Pat>(a);
+  // The rank-1 form runs two contractions per edge: its weights come from the
+  // table in memory, reloaded (scalar loads) at each iteration, since the
+  // kernel-argument copy would be hoisted whole into vector registers.
+  const auto w = [&] {
+    if constexpr (A0) return (ConstFloatPtr)a.tpw;
+    else return tp_weights<Pat>(a);
+  }();
   float gG[DIM];
 #pragma unroll
   for (int b = 0; b < DIM; ++b) gG[b] = 0.0f;
   const int eb0 = a.row_ptr[c], eb1 = a.row_ptr[c + 1];
-  const bool from_a0 = a.v.from_a0 != 0;
+  float Gm[A0 ? DIM : 1];
+  if constexpr (A0) {
+    static_assert(Pat::In == kNatural, "the rank-1 form is natural");
+    const float* gmp = a.gam + c * (uint32_t)(DIM * n) + u;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) Gm[b] = gmp[b * n];
+  }
+  const bool keep_gy = a.gy_accum != 0;
   for (int e0 = eb0; e0 < eb1; e0 += G * KB) {
-    float V[KB][DIN], gT[KB][DOUT];
+    float V[A0 ? 1 : KB][DIN], gT[KB][DOUT];
+    float Yv[A0 ? KB : 1][DIM], a0v[A0 ? KB : 1][LMAX + 1];
+    float gyo[A0 ? KB : 1][DIM];   // the edge's dE/dY row so far (every lane of its group)
+    bool act[KB];
+    uint32_t eev[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
       const int e = e0 + g + G * j;
-      const bool act = e < eb1;
-      const uint32_t ee = act ? e : eb0;
+      act[j] = e < eb1;
+      const uint32_t ee = act[j] ? e : eb0;
+      eev[j] = ee;
       const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
       const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
-      if (from_a0) {
+      if constexpr (A0) {
         const float* Y = a.eb + ee * kEB;
-        float a0v[LMAX + 1];
 #pragma unroll
-        for (int l = 0; l <= LMAX; ++l) a0v[l] = vp[l * n];
+        for (int l = 0; l <= LMAX; ++l) a0v[j][l] = vp[l * n];
 #pragma unroll
-        for (int k = 0; k < DIN; ++k) V[j][k] = k < DIM ? a0v[lof(k < DIM ? k : 0)] * Y[eb_y(k < DIM ? k : 0)] : 0.0f;
+        for (int k = 0; k < DIM; ++k) Yv[j][k] = Y[eb_y(k)];
+        if (keep_gy) {
+          const float* o = a.g_Y + ee * (uint32_t)GYW;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) gyo[j][k] = o[k];
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < DIN; ++k) V[j][k] = vp[k * n];
       }
 #pragma unroll
-      for (int k = 0; k < DOUT; ++k) gT[j][k] = act ? gtp[k * n] : 0.0f;
+      for (int k = 0; k < DOUT; ++k) gT[j][k] = act[j] ? gtp[k * n] : 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < KB; ++j) tp_adjoint_g<Pat>(V[j], gT[j], gG, per_iteration(w));
+    for (int j = 0; j < KB; ++j) {
+      if constexpr (A0) {
+        float Vj[DIN];
+#pragma unroll
+        for (int k = 0; k < DIN; ++k) Vj[k] = k < DIM ? a0v[j][lof(k < DIM ? k : 0)] * Yv[j][k < DIM ? k : 0] : 0.0f;
+        tp_adjoint_g<Pat>(Vj, gT[j], gG, per_iteration(w));
+        float gV[DIN];
+#pragma unroll
+        for (int k = 0; k < DIN; ++k) gV[k] = 0.0f;
+        tp_adjoint_v<Pat>(Gm, gT[j], gV, per_iteration(w));
+        float ga[LMAX + 1], r[DIM];
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          ga[lof(k)] = fmaf(gV[k], Yv[j][k], ga[lof(k)]);
+          r[k] = gV[k] * a0v[j][lof(k)];
+        }
+        const uint32_t ee = eev[j];
+        if (act[j]) {
+#pragma unroll
+          for (int l = 0; l <= LMAX; ++l) a.g_a0[ee * (uint32_t)a.ld_gw + l * n + u] = ga[l];
+        }
+        // sums over the group's channels (DPP; the group's last lane holds them)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) r[k] = group_sum_dpp<n>(r[k]);
+        if (act[j] && u == n - 1) {
+#pragma unroll
+          for (int k = 0; k < GYW; ++k) {
+            const int kk = k < DIM ? k : 0;
+            if (k < DIM || !keep_gy) a.g_Y[ee * (uint32_t)GYW + k] = k < DIM ? (keep_gy ? gyo[j][kk] + r[kk] : r[kk]) : 0.0f;
+          }
+        }
+      } else {
+        tp_adjoint_g<Pat>(V[j], gT[j], gG, per_iteration(w));
+      }
+    }
   }
   if constexpr (G > 1) {
 #pragma unroll
@@ -573,35 +639,32 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_gamma(TensorArgs a) {
 
 constexpr int kEdgesPerWave = 32;
 
-// A0: the layer's V is the rank-1 first-layer form a0[l(a)][u] Y[a].
-template <class Pat, int G, bool A0>
+// KEEP: adds its terms to the dE/dY_e rows written before it (by a later
+// layer, or by the first layer's gamma pass) instead of writing them.
+template <class Pat, int G, bool KEEP>
 __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
   const int E = live_edges(a);
-  constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM, DIN = Pat::DIN, DOUT = Pat::DOUT;
+  constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM;
   constexpr int GYW = gy_width(LMAX);
   constexpr int n = kWave / G;
   // edges per lane group whose loads are issued together
-  constexpr int KB = A0 ? (DOUT > 16 ? 1 : 2) : (DIM > 9 ? 2 : 4);
+  constexpr int KB = DIM > 9 ? 2 : 4;
   const int lane = lane_id();
   const int u = lane & (n - 1), g = lane / n;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t w0 = (int64_t)wave * kEdgesPerWave;
-  const auto w = tp_weights<Pat>(a);
-  const bool keep_gy = a.gy_accum != 0;
   const float cn = a.c_norm;
   // centres of the wave's edges: one load per lane, read out per edge.  With
-  // one edge per wave step (G = 1) the centre is wave-uniform; without the
-  // first-layer rank-1 form its dE/dGamma rows then stay in registers until
-  // it changes (CACHE).  The rank-1 form keeps every row load in the batched
-  // load phase, where its latency overlaps the batch's other loads.
-  constexpr bool CACHE = G == 1 && !A0;
+  // one edge per wave step (G = 1) the centre is wave-uniform and its
+  // dE/dGamma rows stay in registers until it changes (CACHE).
+  constexpr bool CACHE = G == 1;
   const int64_t el = w0 + (lane & (kEdgesPerWave - 1));
   const int ci_lane = el < E ? a.ei[el] - a.centre_base : 0;
   int cur = -1;
   float cG[CACHE ? DIM : 1];
   for (int j0 = 0; j0 < kEdgesPerWave; j0 += G * KB) {
     float gG[CACHE ? 1 : KB][DIM], Yv[KB][DIM], wv[KB][LMAX + 1];
-    float Gm[A0 ? KB : 1][DIM], gT[A0 ? KB : 1][DOUT], a0v[A0 ? KB : 1][LMAX + 1];
+    float gyo[KEEP ? KB : 1][DIM];   // the edge's dE/dY row so far (every lane of its group)
     bool act[KB];
     uint32_t eev[KB], civ[KB];
 #pragma unroll
@@ -620,21 +683,15 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       for (int b = 0; b < DIM; ++b) Yv[q][b] = Y[eb_y(b)];
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) wv[q][l] = wp[l * n];
+      if constexpr (KEEP) {
+        const float* o = a.g_Y + ee * (uint32_t)GYW;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) gyo[q][k] = o[k];
+      }
       if constexpr (!CACHE) {
         const float* ggp = a.g_gam + ci * (uint32_t)(DIM * n) + u;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) gG[q][b] = ggp[b * n];
-      }
-      if constexpr (A0) {
-        const float* gtp = a.g_t + ee * (uint32_t)(DOUT * n) + u;
-        const float* vp = a.v.p + ee * (uint32_t)a.v.ld + u;
-        const float* gmp = a.gam + ci * (uint32_t)(DIM * n) + u;
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) Gm[q][b] = gmp[b * n];
-#pragma unroll
-        for (int k = 0; k < DOUT; ++k) gT[q][k] = gtp[k * n];
-#pragma unroll
-        for (int l = 0; l <= LMAX; ++l) a0v[q][l] = vp[l * n];
       }
     }
 #pragma unroll
@@ -660,25 +717,6 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
         gw[lof(b)] = fmaf(gGq[b], Yv[q][b], gw[lof(b)]);
         r[b] = cn * gGq[b] * wv[q][lof(b)];
       }
-      if constexpr (A0) {
-        static_assert(Pat::In == kNatural, "the rank-1 form is natural");
-        float gV[DIN];
-#pragma unroll
-        for (int k = 0; k < DIN; ++k) gV[k] = 0.0f;
-        tp_adjoint_v<Pat>(Gm[q], gT[q], gV, per_iteration(w));
-        float ga[LMAX + 1];
-#pragma unroll
-        for (int l = 0; l <= LMAX; ++l) ga[l] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          ga[lof(k)] = fmaf(gV[k], Yv[q][k], ga[lof(k)]);
-          r[k] = fmaf(gV[k], a0v[q][lof(k)], r[k]);
-        }
-        if (act[q]) {
-#pragma unroll
-          for (int l = 0; l <= LMAX; ++l) a.g_a0[ee * (uint32_t)a.ld_gw + l * n + u] = ga[l];
-        }
-      }
       if (act[q]) {
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) a.g_w[ee * (uint32_t)a.ld_gw + l * n + u] = gw[l] * cn;
@@ -689,9 +727,8 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
       if (act[q] && u == n - 1) {
 #pragma unroll
         for (int k = 0; k < GYW; ++k) {
-          float* o = a.g_Y + ee * (uint32_t)GYW + k;
-          const float val = k < DIM ? r[k < DIM ? k : 0] : 0.0f;
-          *o = (keep_gy && k < DIM) ? *o + val : val;
+          const int kk = k < DIM ? k : 0;
+          if (k < DIM || !KEEP) a.g_Y[ee * (uint32_t)GYW + k] = k < DIM ? (KEEP ? gyo[KEEP ? q : 0][kk] + r[kk] : r[kk]) : 0.0f;
         }
       }
     }
@@ -792,19 +829,23 @@ hipError_t launch_mix_adjoint_pt(const TensorArgs& a, hipStream_t s) {
   return launch_lds(k_mix_adjoint<PatN, TT, false>, grid, bytes, s, a, ld, Kp, Np);
 }
 
+// The rank-1 first layer's gamma pass writes dE/dY_e first (accumulating
+// when the layer's arguments say so); the edge pass then always adds to it.
 template <class Pat, int G>
 hipError_t launch_adjoint_g(const TensorArgs& a, hipStream_t s) {
-  if (a.n_centres > 0)
-    hipLaunchKernelGGL((k_tp_adjoint_gamma<Pat, G>), dim3(blocks(a.n_centres, 4)), dim3(256), 0, s, a);
+  bool a0 = false;
+  if constexpr (Pat::In == kNatural) a0 = a.v.from_a0 != 0;
+  if (a.n_centres > 0) {
+    const dim3 grid(blocks(a.n_centres, 4));
+    if constexpr (Pat::In == kNatural) {
+      if (a0) hipLaunchKernelGGL((k_tp_adjoint_gamma<Pat, G, true>), grid, dim3(256), 0, s, a);
+    }
+    if (!a0) hipLaunchKernelGGL((k_tp_adjoint_gamma<Pat, G, false>), grid, dim3(256), 0, s, a);
+  }
   if (a.E > 0) {
     const dim3 grid(blocks(a.E, 4 * kEdgesPerWave));
-    if constexpr (Pat::In == kNatural) {
-      if (a.v.from_a0) {
-        hipLaunchKernelGGL((k_tp_adjoint_edges<Pat, G, true>), grid, dim3(256), 0, s, a);
-        return hipGetLastError();
-      }
-    }
-    hipLaunchKernelGGL((k_tp_adjoint_edges<Pat, G, false>), grid, dim3(256), 0, s, a);
+    if (a0 || a.gy_accum) hipLaunchKernelGGL((k_tp_adjoint_edges<Pat, G, true>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_tp_adjoint_edges<Pat, G, false>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
