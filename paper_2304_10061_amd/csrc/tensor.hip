@@ -356,6 +356,21 @@ __device__ void copy_tile(const float* S, int lds_ld, int n, float* out, int64_t
   }
 }
 
+// The centres of an edge tile's TT edges, for the tile kernels below.  Thread
+// t < TT requests centre t of the block's next tile before the current
+// tile's mixing and publishes it after the mixing, so the next tile's
+// gathers of centre rows read the index from LDS and wait on no other load.
+template <int TT>
+struct TileCentres {
+  int next = 0;
+  __device__ __forceinline__ void request(const TensorArgs& a, int64_t e0, int E) {
+    if (threadIdx.x < TT) next = e0 + threadIdx.x < E ? a.ei[e0 + threadIdx.x] - a.centre_base : 0;
+  }
+  __device__ __forceinline__ void publish(int* cent) const {
+    if (threadIdx.x < TT) cent[threadIdx.x] = next;
+  }
+};
+
 // Whether a layer's mixing keeps every slot's fragments in registers.
 template <class Pat>
 constexpr bool kHoldMix = Pat::In == kNatural && Pat::Out == kNatural && Pat::Lmax <= 2;
@@ -377,6 +392,11 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
     else mix_geometry(mb, Np);
   }
   const int ntiles = (E + TT - 1) / TT;
+  __shared__ int cent[TT];
+  TileCentres<TT> tc;
+  tc.request(a, (int64_t)blockIdx.x * TT, E);
+  tc.publish(cent);
+  __syncthreads();
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = (int64_t)tile * TT;
     // TT * Kp is a multiple of 512: two (edge, channel) items per thread per
@@ -393,7 +413,7 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
         const int64_t ee = ok[h] ? e : 0;
         const int uu = ok[h] ? u : 0;
         load_v<LMAX, DIN>(a.v, a.eb + (size_t)ee * kEB, ee, uu, n, V[h]);
-        const float* gp = a.gam + (size_t)(a.ei[ee] - a.centre_base) * DIM * n + uu;
+        const float* gp = a.gam + (size_t)cent[ok[h] ? r : 0] * DIM * n + uu;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) G[h][b] = gp[b * n];
       }
@@ -409,12 +429,14 @@ __global__ __launch_bounds__(256) void k_tp_mix(TensorArgs a, int lds_ld, int Kp
         for (int c = 0; c < DOUT; ++c) stage_value<BF3, DOUT, TT>(S, lds_ld, c, r, u, T[c]);
       }
     }
+    tc.request(a, e0 + (int64_t)gridDim.x * TT, E);
     __syncthreads();
     if (BF3 || a.channel_mix)   // the BF16 x 3 form is only launched with mixing on
       mix_tile<LMAX, DOUT, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
                                      a.v_out, e0, E);
     else copy_tile<DOUT, TT>(S, lds_ld, n, a.v_out, e0, E);
-    __syncthreads();   // S is rewritten by the next tile
+    tc.publish(cent);   // every read of this tile's centres was before the barrier
+    __syncthreads();    // S and cent are rewritten by the next tile
   }
 }
 
@@ -441,6 +463,11 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
     else mix_geometry(mb, Np);
   }
   const int ntiles = (E + TT - 1) / TT;
+  __shared__ int cent[TT];
+  TileCentres<TT> tc;
+  tc.request(a, (int64_t)blockIdx.x * TT, E);
+  tc.publish(cent);
+  __syncthreads();
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = (int64_t)tile * TT;
     for (int p0 = threadIdx.x; p0 < TT * Kp; p0 += 512) {
@@ -457,7 +484,7 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
 #pragma unroll
         for (int c = 0; c < DN; ++c) gt[h][c] = a.g_tnext[((size_t)ee * DN + c) * n + uu];
         gs[h] = a.g_s[(size_t)ee * n + uu];
-        const float* gp = a.gam_next + (size_t)(a.ei[ee] - a.centre_base) * DIM * n + uu;
+        const float* gp = a.gam_next + (size_t)cent[ok[h] ? r : 0] * DIM * n + uu;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) gam[h][c] = gp[c * n];
       }
@@ -485,12 +512,14 @@ __global__ __launch_bounds__(256) void k_mix_adjoint(TensorArgs a, int lds_ld, i
         }
       }
     }
+    tc.request(a, e0 + (int64_t)gridDim.x * TT, E);
     __syncthreads();
     if (BF3 || a.channel_mix)   // the BF16 x 3 form is only launched with mixing on
       mix_tile<LMAX, DW, TT, HOLD>(S, lds_ld, mb, (const float*)a.mixB, a.mix_stride, n, Kp, a.mix_scale,
                                    a.g_tout, e0, E);
     else copy_tile<DW, TT>(S, lds_ld, n, a.g_tout, e0, E);
-    __syncthreads();
+    tc.publish(cent);   // every read of this tile's centres was before the barrier
+    __syncthreads();    // S and cent are rewritten by the next tile
   }
 }
 
