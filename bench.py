@@ -309,12 +309,13 @@ def tensor_bytes_per_unit(mc):
             "tp_env_adjoint_final": 4 * w * n + env}
 
 
-def tensor_symbols(mc):
+def tensor_symbols(mc, bf3=True):
     """Kernel symbols (as rocprofv3 prints them) behind each timed tensor-track
     launch kind of one step: the layers' patterns TpPattern<l_max, input kind,
     output kind> (1 natural parity, 2 both parities, 0 the final scalar), the
-    lane groups of the adjoint kernels (64 / n channels) and, for the first
-    layer's adjoint, the rank-1 form of its input."""
+    lane groups of the adjoint kernels (64 / n channels), for the first
+    layer's adjoint the rank-1 form of its input, and for the tile kernels
+    whether the mixing runs as BF16 x 3 (`bf3`, the BF16-mixed modes)."""
     nl, lm, G = mc.n_layers, mc.l_max, 64 // mc.n_tensor
     kin = [1 if (L == 0 or L == nl - 1) else 2 for L in range(nl)]
     kout = [0 if L == nl - 1 else (2 if nl >= 3 and L < nl - 2 else 1) for L in range(nl)]
@@ -326,8 +327,9 @@ def tensor_symbols(mc):
     out = {"tp_env_adjoint_final": [f"k_tp_adjoint_gamma<{pat(nl - 1)}, {G}, {a0(nl - 1)}>",
                                     f"k_tp_adjoint_edges<{pat(nl - 1)}, {G}, {keep(nl - 1)}>"]}
     if nl > 1:
-        out["tp_mix"] = [f"k_tp_mix<{pat(L)}, 16>" for L in range(nl - 1)]
-        out["mix_adjoint"] = [f"k_mix_adjoint<{pat(L + 1)}, 16>" for L in range(nl - 1)]
+        b = "true" if bf3 else "false"
+        out["tp_mix"] = [f"k_tp_mix<{pat(L)}, 16, {b}>" for L in range(nl - 1)]
+        out["mix_adjoint"] = [f"k_mix_adjoint<{pat(L + 1)}, 16, {b}>" for L in range(nl - 1)]
         out["tp_env_adjoint"] = [s for L in range(nl - 1)
                                  for s in (f"k_tp_adjoint_gamma<{pat(L)}, {G}, {a0(L)}>",
                                            f"k_tp_adjoint_edges<{pat(L)}, {G}, {keep(L)}>")]
