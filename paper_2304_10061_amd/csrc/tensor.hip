@@ -676,8 +676,10 @@ __global__ __launch_bounds__(256) void k_tp_adjoint_edges(TensorArgs a) {
   constexpr int LMAX = Pat::Lmax, DIM = Pat::DIM;
   constexpr int GYW = gy_width(LMAX);
   constexpr int n = kWave / G;
-  // edges per lane group whose loads are issued together
-  constexpr int KB = DIM > 9 ? 2 : 4;
+  // edges per lane group whose loads are issued together (two when the
+  // earlier dE/dY rows come along: four then costs more occupancy than the
+  // extra loads in flight return)
+  constexpr int KB = (DIM > 9 || KEEP) ? 2 : 4;
   const int lane = lane_id();
   const int u = lane & (n - 1), g = lane / n;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
